@@ -1,0 +1,348 @@
+"""Pins of the CPU oracle against quantities fixed independently of its code:
+brute-force transforms, closed-form propagation, Fourier coefficients of the
+susceptibility exponential, invariants (flux, mirror symmetry, linearity),
+textbook dynamical theory (Darwin curve) and the scheme's convergence order.
+
+A plausible slip anywhere in the oracle (a dropped term, a wrong sign, a
+swapped band or envelope, a transposed coupling) fails at least one test."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from closed_forms import (dft_brute, gaussian_beam_2d, darwin_reflectivity,
+                          fourier_coefficients)
+
+LAM = 1.24e-10
+TH = math.pi / 4
+CHI0 = complex(-1.5e-5, 1e-8)
+CHIH = complex(3.8e-6, 0.9e-8)
+VACUUM = dict(x_front=1.0, thickness=1.0)        # slab far outside the window
+FILLED = dict(x_front=-1.0, thickness=math.inf)  # every sample inside
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def rand_field(rng, *shape):
+    return rng.normal(size=shape) + 1j * rng.normal(size=shape)
+
+
+def grid(Nx, dx):
+    return (np.arange(Nx) - Nx // 2) * dx
+
+
+# --- Fourier step (Eq. fov4): sign and normalisation -------------------------
+
+@pytest.mark.parametrize("N", [8, 16, 64])
+def test_vacuum_step_is_brute_force_dft_round_trip(N):
+    rng = np.random.default_rng(N)
+    p = O.Problem(N, 0.5e-6, 0.5e-6, 1, CHI0, CHIH, CHIH, TH, LAM, [3e-6], **VACUUM)
+    a0, b0 = rand_field(rng, 1, N), rand_field(rng, 1, N)
+    a, b = O.march(p, a0, Eh_in=b0)
+    for band, x0, x1 in ((+1, a0, a), (-1, b0, b)):
+        P = O.propagator(p, 3e-6, band)
+        X = dft_brute(x0[0]) * P
+        back = np.conj(dft_brute(np.conj(X))) / N     # inverse DFT, 1/N
+        assert rel(x1[0], back) < 1e-13
+
+
+def test_vacuum_is_unitary_parseval():
+    rng = np.random.default_rng(1)
+    p = O.Problem(256, 0.5e-6, 0.5e-6, 25, CHI0, CHIH, CHIH, TH, LAM, [0.0, 2e-6],
+                  **VACUUM)
+    a0, b0 = rand_field(rng, 2, 256), rand_field(rng, 2, 256)
+    a, b = O.march(p, a0, Eh_in=b0)
+    assert abs(np.sum(abs(a) ** 2) / np.sum(abs(a0) ** 2) - 1) < 1e-13
+    assert abs(np.sum(abs(b) ** 2) / np.sum(abs(b0) ** 2) - 1) < 1e-13
+    # Parseval for the transform used inside the step
+    X = np.fft.fft(a0[0])
+    assert abs(np.sum(abs(X) ** 2) / (256 * np.sum(abs(a0[0]) ** 2)) - 1) < 1e-13
+
+
+# --- Free propagation (Eq. fov4, band-shifted p+-): analytic Gaussian beam ---
+
+@pytest.mark.parametrize("band", [+1, -1])
+def test_free_space_gaussian_walkoff(band):
+    Nx, dx, dz, Nz = 1024, 0.5e-6, 0.5e-6, 200
+    x = grid(Nx, dx)
+    x0, w0 = -60e-6 * band, 20e-6
+    psi0 = np.exp(-((x - x0) / w0) ** 2)[None, :]
+    p = O.Problem(Nx, dx, dz, Nz, CHI0, CHIH, CHIH, TH, LAM, [0.0], **VACUUM)
+    if band > 0:
+        out, other = O.march(p, psi0)
+    else:
+        other, out = O.march(p, np.zeros_like(psi0), Eh_in=psi0)
+    k = 2 * math.pi / LAM
+    exact = gaussian_beam_2d(x, Nz * dz, x0, w0, k, TH, band)
+    assert rel(out[0], exact) < 1e-8
+    assert np.max(abs(other)) == 0.0
+    # the carrier +h/2 band walks towards +x (into the slab), -h/2 towards -x
+    cen = np.sum(x * abs(out[0]) ** 2) / np.sum(abs(out[0]) ** 2)
+    assert abs(cen - (x0 + band * Nz * dz)) < 1e-9
+
+
+def test_free_space_gaussian_diffraction():
+    """A 1.5 um waist spreads measurably: pins the K^2/(2 k cos^3) term."""
+    Nx, dx, dz, Nz = 2048, 0.125e-6, 0.5e-6, 300
+    x = grid(Nx, dx)
+    x0, w0 = -75e-6, 1.5e-6
+    psi0 = np.exp(-((x - x0) / w0) ** 2)[None, :]
+    p = O.Problem(Nx, dx, dz, Nz, CHI0, CHIH, CHIH, TH, LAM, [0.0], **VACUUM)
+    out, _ = O.march(p, psi0)
+    k = 2 * math.pi / LAM
+    exact = gaussian_beam_2d(x, Nz * dz, x0, w0, k, TH, +1)
+    no_diffr = (np.exp(1j * k * math.cos(TH) * Nz * dz)
+                * np.exp(-((x - x0 - Nz * dz) / w0) ** 2))
+    assert rel(out[0], exact) < 2e-6
+    assert rel(out[0], no_diffr) > 1e-3      # the diffraction term matters here
+
+
+# --- Coupling constants (Eqs. fov9, fov11, fov12 + Zassenhaus factor) -------
+
+@pytest.mark.parametrize("chih,chihbar,delta,frac", [
+    (CHIH, CHIH, 0.0, 1.0),
+    (complex(3.8e-6, 0.9e-8), complex(2.9e-6, -0.4e-8), 4e-6, 1.0),
+    (complex(1.1e-5, 2e-7), complex(0.7e-5, 1e-7), -7e-6, 0.5),
+])
+def test_coupling_constants_are_fourier_coefficients(chih, chihbar, delta, frac):
+    p = O.Problem(64, 0.5e-6, 0.5e-6, 1, CHI0, chih, chihbar, TH, LAM, [delta],
+                  zassenhaus=False)
+    k = 2 * math.pi / LAM * (1 + delta)
+    h = 2 * (2 * math.pi / LAM) * math.sin(TH)
+    c = math.sqrt(1 - (h / (2 * k)) ** 2)
+    dZ = frac * k * p.dz
+
+    def f(t):  # exp(i dZ (chi0 + chih e^{it} + chihbar e^{-it}) / (2 cos alpha))
+        return np.exp(1j * dZ * (CHI0 + chih * np.exp(1j * t)
+                                 + chihbar * np.exp(-1j * t)) / (2 * c))
+
+    cn = fourier_coefficients(f)
+    d0, dp1, dm1 = O.coupling_constants(p, delta, frac)
+    assert abs(d0 - cn[0]) < 1e-14
+    assert abs(dp1 - cn[+1]) < 1e-14     # multiplies psi~_- in the psi~_+ update
+    assert abs(dm1 - cn[-1]) < 1e-14
+    pz = O.Problem(64, 0.5e-6, 0.5e-6, 1, CHI0, chih, chihbar, TH, LAM, [delta])
+    d0z, dp1z, dm1z = O.coupling_constants(pz, delta, frac)
+    q = dZ ** 2 * chih * chihbar / c ** 2      # D2 dz^2/2 = q/8
+    assert abs(d0z - cn[0] * np.exp(q / 8)) < 1e-14
+    assert dp1z == dp1 and dm1z == dm1
+
+
+def test_zassenhaus_restores_cos_half_w():
+    """With real chih = chihbar and chi0 = 0 the exact two-beam factor has
+    diagonal cos(w/2); J0(w) misses it at O(w^2), J0(w) e^{w^2/8} at O(w^4)."""
+    errs_z, errs_n = [], []
+    for dz in (1e-6, 0.5e-6, 0.25e-6):
+        for zas, errs in ((True, errs_z), (False, errs_n)):
+            p = O.Problem(64, 0.5e-6, dz, 1, 0.0, 3.8e-6, 3.8e-6, TH, LAM, [0.0],
+                          zassenhaus=zas)
+            k = 2 * math.pi / LAM
+            w = k * dz * 3.8e-6 / math.cos(TH)
+            d0, dp1, _ = O.coupling_constants(p, 0.0)
+            errs.append(abs(d0 - math.cos(w / 2)))
+            assert abs(dp1 - 1j * math.sin(w / 2)) < w ** 3 / 20
+    assert 12 < errs_z[0] / errs_z[1] < 20 and 12 < errs_z[1] / errs_z[2] < 20
+    assert 3.5 < errs_n[0] / errs_n[1] < 4.5
+    assert errs_z[0] < errs_n[0] / 50
+
+
+# --- Coupled step structure (Eq. fov10) -------------------------------------
+
+def test_uniform_crystal_matches_per_mode_matrix_power():
+    """Inside an unbounded undeformed crystal the step is diagonal in K:
+    [a^, b^] -> C diag(P+, P-) [a^, b^], C = [[d0, d+1], [d-1, d0]]."""
+    rng = np.random.default_rng(5)
+    Nx, Nz = 64, 37
+    chihbar = complex(2.1e-6, -0.3e-8)
+    deltas = [0.0, 3e-6]
+    p = O.Problem(Nx, 0.5e-6, 0.5e-6, Nz, CHI0, CHIH, chihbar, TH, LAM, deltas,
+                  **FILLED)
+    a0, b0 = rand_field(rng, 2, Nx), rand_field(rng, 2, Nx)
+    a, b = O.march(p, a0, Eh_in=b0)
+    for w, d in enumerate(deltas):
+        Pp, Pm = O.propagator(p, d, +1), O.propagator(p, d, -1)
+        d0, dp1, dm1 = O.coupling_constants(p, d)
+        C = np.array([[d0, dp1], [dm1, d0]])
+        A0, B0 = np.fft.fft(a0[w]), np.fft.fft(b0[w])
+        A, B = np.empty_like(A0), np.empty_like(B0)
+        for m in range(Nx):
+            M = np.linalg.matrix_power(C @ np.diag([Pp[m], Pm[m]]), Nz)
+            A[m], B[m] = M @ np.array([A0[m], B0[m]])
+        assert rel(a[w], np.fft.ifft(A)) < 1e-12
+        assert rel(b[w], np.fft.ifft(B)) < 1e-12
+
+
+@pytest.mark.parametrize("m", [3, -2])
+def test_uniform_strain_couples_shifted_modes(m):
+    """u = g x with h g L = 2 pi m: exp(+ihu) moves psi~_- by +m bins into
+    psi~_+ (the printed sign of Eq. Authier), exp(-ihu) the reverse."""
+    rng = np.random.default_rng(7)
+    Nx, dx, Nz = 64, 0.5e-6, 23
+    p = O.Problem(Nx, dx, 0.5e-6, Nz, CHI0, CHIH, CHIH, TH, LAM, [0.0], **FILLED)
+    h = 2 * (2 * math.pi / LAM) * math.sin(TH)
+    g = 2 * math.pi * m / (h * Nx * dx)
+    u = np.broadcast_to(g * grid(Nx, dx), (Nz, Nx))
+    a0, b0 = rand_field(rng, 1, Nx), rand_field(rng, 1, Nx)
+    a, b = O.march(p, a0, u, Eh_in=b0)
+    Pp, Pm = O.propagator(p, 0.0, +1), O.propagator(p, 0.0, -1)
+    d0, dp1, dm1 = O.coupling_constants(p, 0.0)
+    s = np.exp(-1j * math.pi * m)   # x origin at j = Nx/2
+    A0, B0 = np.fft.fft(a0[0]), np.fft.fft(b0[0])
+    A, B = np.empty_like(A0), np.empty_like(B0)
+    for k in range(Nx):
+        kb = (k - m) % Nx
+        step = np.array([[d0 * Pp[k], dp1 * s * Pm[kb]],
+                         [dm1 * np.conj(s) * Pp[k], d0 * Pm[kb]]])
+        A[k], B[kb] = np.linalg.matrix_power(step, Nz) @ np.array([A0[k], B0[kb]])
+    assert rel(a[0], np.fft.ifft(A)) < 1e-11
+    assert rel(b[0], np.fft.ifft(B)) < 1e-11
+
+
+def test_chi0_only_gives_refraction_phase_and_absorption():
+    rng = np.random.default_rng(9)
+    Nx, Nz, dz = 128, 41, 0.5e-6
+    p = O.Problem(Nx, 0.5e-6, dz, Nz, CHI0, 0.0, 0.0, TH, LAM, [1e-6], **FILLED)
+    pv = O.Problem(Nx, 0.5e-6, dz, Nz, CHI0, 0.0, 0.0, TH, LAM, [1e-6], **VACUUM)
+    a0 = rand_field(rng, 1, Nx)
+    a, b = O.march(p, a0)
+    av, _ = O.march(pv, a0)
+    k = 2 * math.pi / LAM * (1 + 1e-6)
+    c = math.sqrt(1 - (2 * math.pi / LAM * math.sin(TH) / k) ** 2)
+    g0N = np.exp(1j * Nz * k * dz * CHI0 / (2 * c))
+    assert rel(a, g0N * av) < 1e-12
+    assert np.max(abs(b)) == 0.0
+    ratio = np.sum(abs(a) ** 2) / np.sum(abs(av) ** 2)
+    assert abs(ratio / math.exp(-Nz * k * dz * CHI0.imag / c) - 1) < 1e-12
+
+
+def test_flux_balance_per_step_real_susceptibility():
+    """Real chi, chih = chihbar: the 2x2 coupling M satisfies M^H M = g I with
+    g = J0(w)^2 e^{w^2/4} + J1(w)^2 = 1 - w^4/16 + O(w^6); vacuum steps are
+    unitary.  So each step removes exactly (1 - g) of the in-slab flux."""
+    from scipy.special import jv
+    rng = np.random.default_rng(11)
+    Nx, dx, dz = 256, 0.5e-6, 0.5e-6
+    kw = dict(x_front=0.25 * dx, thickness=70 * dx)
+    p = O.Problem(Nx, dx, dz, 1, -1.5e-5, 3.8e-6, 3.8e-6, TH, LAM, [0.0], **kw)
+    pv = O.Problem(Nx, dx, dz, 1, -1.5e-5, 3.8e-6, 3.8e-6, TH, LAM, [0.0], **VACUUM)
+    a0, b0 = rand_field(rng, 1, Nx), rand_field(rng, 1, Nx)
+    ap, bp = O.march(pv, a0, Eh_in=b0)
+    a, b = O.march(p, a0, Eh_in=b0)
+    k = 2 * math.pi / LAM
+    w = k * dz * 3.8e-6 / math.cos(TH)
+    g = jv(0, w) ** 2 * math.exp(w * w / 4) + jv(1, w) ** 2
+    assert abs((1 - g) / (w ** 4 / 16) - 1) < 0.01
+    inside = O.crystal_mask(p)
+    assert inside.sum() == 70
+    before = np.sum(abs(ap) ** 2 + abs(bp) ** 2)
+    lost = (1 - g) * np.sum((abs(ap) ** 2 + abs(bp) ** 2)[:, inside])
+    after = np.sum(abs(a) ** 2 + abs(b) ** 2)
+    assert abs(after - (before - lost)) < 1e-12 * before
+
+
+def test_mirror_symmetry():
+    """x -> -x with psi~_+ <-> psi~_-, chih <-> chihbar, u(x) -> -u(-x) and the
+    slab mirrored maps solutions to solutions.  Exact on a grid with odd Nx,
+    whose wavenumbers are symmetric (an even grid's Nyquist bin maps to
+    itself); there x_j -> -x_j is plain reversal of the samples."""
+    rng = np.random.default_rng(13)
+    Nx, dx, Nz = 127, 0.5e-6, 30
+    chihbar = complex(2.5e-6, 0.4e-8)
+    xf, T = 0.25 * dx, 60.5 * dx
+    u = rng.normal(0, 2e-11, size=(Nz, Nx))
+    p = O.Problem(Nx, dx, 0.5e-6, Nz, CHI0, CHIH, chihbar, TH, LAM, [2e-6],
+                  x_front=xf, thickness=T)
+    pm = O.Problem(Nx, dx, 0.5e-6, Nz, CHI0, chihbar, CHIH, TH, LAM, [2e-6],
+                   x_front=-xf - T, thickness=T)
+    M = lambda f: f[..., ::-1]
+    assert np.allclose(M(grid(Nx, dx)), -grid(Nx, dx), atol=0, rtol=0)
+    assert np.array_equal(M(O.crystal_mask(p)), O.crystal_mask(pm))
+    a0, b0 = rand_field(rng, 1, Nx), rand_field(rng, 1, Nx)
+    a, b = O.march(p, a0, u, Eh_in=b0)
+    am, bm = O.march(pm, M(b0), -M(u), Eh_in=M(a0))
+    assert rel(am, M(b)) < 1e-12
+    assert rel(bm, M(a)) < 1e-12
+
+
+def test_slices_are_independent_and_linear():
+    rng = np.random.default_rng(17)
+    Nx, Nz = 128, 20
+    deltas = [-3e-6, 0.0, 5e-6]
+    u = rng.normal(0, 1e-11, size=(Nz, Nx))
+    p = O.Problem(Nx, 0.5e-6, 0.5e-6, Nz, CHI0, CHIH, CHIH, TH, LAM, deltas)
+    E1, E2 = rand_field(rng, 3, Nx), rand_field(rng, 3, Nx)
+    a, b = O.march(p, E1, u)
+    for w, d in enumerate(deltas):
+        p1 = O.Problem(Nx, 0.5e-6, 0.5e-6, Nz, CHI0, CHIH, CHIH, TH, LAM, [d])
+        a1, b1 = O.march(p1, E1[w:w + 1], u)
+        assert rel(a1[0], a[w]) < 1e-15 and rel(b1[0], b[w]) < 1e-15
+    al, bl = O.march(p, 2.0 * E1 - 0.5j * E2, u)
+    a2, b2 = O.march(p, E2, u)
+    assert rel(al, 2.0 * a - 0.5j * a2) < 1e-13
+    assert rel(bl, 2.0 * b - 0.5j * b2) < 1e-13
+
+
+# --- Physics of the whole step: textbook Darwin curve ----------------------
+
+def test_darwin_curve_thick_crystal():
+    """Wide beam (W0 = 100 um >> extinction length, divergence << Darwin
+    width) on a thick slab: reflected energy in vacuum matches two-beam
+    dynamical theory, including the refraction shift of the plateau centre
+    by -Re(chi0)/sin(2 theta_B)."""
+    Nx, dx, dz, Z, W0, x0 = 2048, 1e-6, 0.5e-6, 600e-6, 100e-6, -300e-6
+    wd = 2 * abs(CHIH) / math.sin(2 * TH)
+    cen = -CHI0.real / math.sin(2 * TH)
+    rel_pos = np.array([-2.0, -1.25, -0.3, 0.0, 0.3, 1.25, 2.0])
+    dth = cen + wd * rel_pos
+    k0 = 2 * math.pi / LAM
+    h = 2 * k0 * math.sin(TH)
+    x = grid(Nx, dx)
+    E0 = np.stack([np.exp(-((x - x0) / W0) ** 2)
+                   * np.exp(1j * (k0 * math.sin(TH + d) - h / 2) * x) for d in dth])
+    p = O.Problem(Nx, dx, dz, int(round(Z / dz)), CHI0, CHIH, CHIH, TH, LAM,
+                  np.zeros(len(dth)))
+    a, b = O.march(p, E0)
+    R = np.sum(abs(b[:, x < 0]) ** 2, axis=1) / np.sum(abs(E0) ** 2, axis=1)
+    Rth = darwin_reflectivity(dth, CHI0, CHIH, CHIH, TH)
+    assert np.all(abs(R - Rth) < 0.01), (R, Rth)
+    assert R[3] > 0.98 and R[0] < 0.03 and R[-1] < 0.03
+
+
+# --- Scheme order (Eq. split-op) ---------------------------------------------
+
+def _conv_errors(order, zassenhaus, factors=(1, 2, 4)):
+    Nx, dx, Z = 512, 0.5e-6, 60e-6
+    x = grid(Nx, dx)
+    k0 = 2 * math.pi / LAM
+    h = 2 * k0 * math.sin(TH)
+    E0 = (np.exp(-((x + 30e-6) / 15e-6) ** 2)
+          * np.exp(1j * (k0 * math.sin(TH + 1.5e-5) - h / 2) * x))[None, :]
+
+    def run(dz):
+        p = O.Problem(Nx, dx, dz, int(round(Z / dz)), CHI0, CHIH, CHIH, TH, LAM,
+                      [0.0], zassenhaus=zassenhaus, split_order=order)
+        return np.concatenate(O.march(p, E0), axis=1)
+
+    ref = run(0.5e-6 / 32)
+    return [rel(run(0.5e-6 / f), ref) for f in factors]
+
+
+@pytest.mark.parametrize("order,zas,lo,hi", [
+    (1, True, 0.9, 1.25),
+    (2, True, 1.8, 2.2),
+    (2, False, 0.9, 1.25),   # without the Zassenhaus factor the B step is O(dz^2)-wrong
+])
+def test_convergence_order(order, zas, lo, hi):
+    e = _conv_errors(order, zas)
+    for i in range(len(e) - 1):
+        assert lo < math.log2(e[i] / e[i + 1]) < hi, e
+
+
+def test_split_coefficients_consistent():
+    for order in (1, 2, 4):
+        A, B = O.split_coefficients(order)
+        assert abs(sum(A) - 1) < 1e-15 and abs(sum(B) - 1) < 1e-15

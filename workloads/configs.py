@@ -1,0 +1,309 @@
+"""Seeded synthetic workloads for the FFT BPM z-march.
+
+Every workload is a symmetric-Bragg slab problem in the (x, z) plane of the
+paper's Section 2.1: x transverse (the reciprocal vector h is along x), z the
+marching axis, crystal occupying x_front <= x < x_front + thickness.
+
+A workload holds
+  * the plan parameters (Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lambda,
+    Nomega), the relative frequency offset delta_w of each slice, the slab;
+  * E0_in[w, j]: the transmitted-beam envelope at z = 0, i.e. the incident
+    field with the carrier exp(i h x / 2) removed (envelope definition,
+    Eq. fov7), sampled at x_j = (j - Nx/2) dx;
+  * u[n, j]: the displacement along h (metres) used by z-step n, or None.
+
+The incident beam is the Gaussian of Section 3.1 (rocking-curve example) with
+the source at its waist (z_x = 0, so the prefactor is 1).  A pulse is the
+Gaussian of Eq. tdp transformed to frequency: one slice per frequency offset,
+amplitude exp(-(omega_0 delta)^2 sigma_t^2 / 2) times a seeded random spectral
+phase.  Displacements are the constant strain gradient of Section 3.2
+(u = x^2 / (2R), i.e. B = 1/(2R)) and a Gaussian thermal bump standing in for
+the finite-element field of Section 3.4, plus seeded white-noise strain.
+
+Nothing here propagates a field: these are inputs only.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+
+# Shared defaults: 1.24 Angstrom, 45 degree symmetric Bragg, synthetic
+# susceptibilities (real parts of x-ray susceptibilities are negative; the
+# small positive imaginary parts give absorption with exp(+i k z) propagation).
+LAMBDA = 1.24e-10
+THETA_B = math.pi / 4
+CHI0 = complex(-1.5e-5, 1e-8)
+CHIH = complex(3.8e-6, 0.9e-8)
+DX = 0.5e-6
+DZ = 0.5e-6
+W0 = 50e-6
+X0 = -100e-6
+
+
+@dataclass
+class Workload:
+    name: str
+    Nx: int
+    dx: float
+    dz: float
+    Nz: int
+    chi0: complex
+    chih: complex
+    chihbar: complex
+    theta_B: float
+    lam: float
+    Nomega: int
+    delta: np.ndarray                 # (Nomega,) relative frequency offsets
+    E0_in: np.ndarray                 # (Nomega, Nx) complex128
+    u: Optional[np.ndarray] = None    # (Nz, Nx) float64 or None
+    x_front: float = 0.0
+    thickness: float = math.inf
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def cell_updates(self) -> int:
+        return self.Nx * self.Nz * self.Nomega
+
+    def plan_args(self) -> dict:
+        return dict(Nx=self.Nx, dx=self.dx, dz=self.dz, Nz=self.Nz,
+                    chi0=self.chi0, chih=self.chih, chihbar=self.chihbar,
+                    theta_B=self.theta_B, lam=self.lam, Nomega=self.Nomega)
+
+    def subset(self, slices) -> "Workload":
+        """Same problem restricted to the listed frequency slices."""
+        idx = np.asarray(slices, dtype=np.int64)
+        return Workload(self.name + f"[{len(idx)} slices]", self.Nx, self.dx,
+                        self.dz, self.Nz, self.chi0, self.chih, self.chihbar,
+                        self.theta_B, self.lam, len(idx), self.delta[idx].copy(),
+                        self.E0_in[idx].copy(), self.u, self.x_front,
+                        self.thickness, dict(self.meta))
+
+
+def x_grid(Nx: int, dx: float) -> np.ndarray:
+    """Sample positions x_j = (j - Nx/2) dx."""
+    return (np.arange(Nx, dtype=np.float64) - Nx // 2) * dx
+
+
+def darwin_relative_width(chih: complex, chihbar: complex, theta_B: float) -> float:
+    """Full Darwin width of a symmetric Bragg reflection in relative photon
+    energy, |sqrt(chih chihbar)| / sin^2(theta_B) (textbook dynamical theory)."""
+    return abs(np.sqrt(complex(chih) * complex(chihbar))) / math.sin(theta_B) ** 2
+
+
+def detuning_grid(Nomega: int, eps_D: float, span_widths: float = 10.0) -> np.ndarray:
+    """Nomega cell-centred relative frequency offsets spanning
+    +-span_widths/2 Darwin widths; a single slice sits at zero offset."""
+    if Nomega == 1:
+        return np.zeros(1)
+    j = np.arange(Nomega, dtype=np.float64)
+    return eps_D * (-span_widths / 2 + span_widths * (j + 0.5) / Nomega)
+
+
+def incident_envelope(Nx, dx, lam, theta_B, delta, theta_i, amp,
+                      x0=X0, w0=W0) -> np.ndarray:
+    """Gaussian beam exp(-(x-x0)^2/W0^2) travelling at glancing angle theta_i,
+    one row per frequency slice (wavenumber k0 (1 + delta_w)), with the
+    carrier exp(i h x / 2), h = 2 k0 sin(theta_B), removed."""
+    x = x_grid(Nx, dx)
+    k0 = 2.0 * math.pi / lam
+    h = 2.0 * k0 * math.sin(theta_B)
+    g = np.exp(-((x - x0) / w0) ** 2)
+    out = np.empty((len(delta), Nx), dtype=np.complex128)
+    for w, d in enumerate(delta):
+        tilt = k0 * (1.0 + d) * math.sin(theta_i) - 0.5 * h
+        out[w] = amp[w] * g * np.exp(1j * tilt * x)
+    return out
+
+
+def pulse_amplitudes(delta, lam, sigma_t, rng, phase_amp=0.1) -> np.ndarray:
+    """Spectral amplitudes of a Gaussian pulse of rms duration sigma_t with a
+    seeded random spectral phase of amplitude phase_amp (radians)."""
+    omega0 = 2.0 * math.pi * C_LIGHT / lam
+    mag = np.exp(-0.5 * (omega0 * np.asarray(delta) * sigma_t) ** 2)
+    ph = phase_amp * rng.uniform(-1.0, 1.0, size=len(delta))
+    return mag * np.exp(1j * ph)
+
+
+def bent_displacement(Nx, dx, Nz, R, x_front=0.0) -> np.ndarray:
+    """Constant strain gradient u = (x - x_front)^2 / (2R), the same in every
+    z row (Section 3.2 with B = 1/(2R))."""
+    xs = x_grid(Nx, dx) - x_front
+    row = xs * xs / (2.0 * R)
+    return np.broadcast_to(row, (Nz, Nx)).copy()
+
+
+def bump_factors(Nx, dx, Nz, dz, amp, sigma, x_front=0.0):
+    """Separable Gaussian bump amp*exp(-(x^2 + (z - zc)^2)/(2 sigma^2)) with
+    zc at mid-depth: returns (gz, gx) with bump[n, j] = (amp * gz[n]) * gx[j]."""
+    xs = x_grid(Nx, dx) - x_front
+    z = np.arange(Nz, dtype=np.float64) * dz
+    zc = Nz * dz / 2.0
+    gx = np.exp(-xs * xs / (2.0 * sigma * sigma))
+    gz = np.exp(-(z - zc) ** 2 / (2.0 * sigma * sigma))
+    return gz, gx
+
+
+def _common(name, Nx, Nz, Nomega, delta, E0, u, **meta) -> Workload:
+    return Workload(name, Nx, DX, DZ, Nz, CHI0, CHIH, CHIH, THETA_B, LAMBDA,
+                    Nomega, np.asarray(delta, dtype=np.float64), E0, u,
+                    0.0, math.inf, dict(meta))
+
+
+def small(Nx=256, Nz=40, Nomega=3, seed=0, deformed=True, dx=DX, dz=DZ,
+          x_front=0.0, thickness=math.inf, x0=None, w0=None) -> Workload:
+    """Small seeded problem for parity tests: a pulse of Nomega slices on a
+    bent crystal with a thermal bump and noise strain, sized so that the
+    oracle runs in well under a second."""
+    rng = np.random.default_rng(seed)
+    eps = darwin_relative_width(CHIH, CHIH, THETA_B)
+    delta = detuning_grid(Nomega, eps)
+    amp = pulse_amplitudes(delta, LAMBDA, 10e-15, rng)
+    L = Nx * dx
+    x0 = -0.2 * L if x0 is None else x0
+    w0 = 0.08 * L if w0 is None else w0
+    E0 = incident_envelope(Nx, dx, LAMBDA, THETA_B, delta, THETA_B, amp, x0, w0)
+    u = None
+    if deformed:
+        u = bent_displacement(Nx, dx, Nz, rng.uniform(1.0, 100.0), x_front)
+        gz, gx = bump_factors(Nx, dx, Nz, dz, rng.uniform(0.2e-10, 1e-10),
+                              0.2 * L, x_front)
+        u += (1e-10 * gz)[:, None] * gx[None, :]
+        strain = rng.normal(0.0, 1e-7, size=(Nz, Nx))
+        cs = np.cumsum(strain, axis=1)
+        j0 = int(np.searchsorted(x_grid(Nx, dx), x_front))
+        u += dx * (cs - cs[:, min(j0, Nx - 1)][:, None])
+    return Workload(f"small-{Nx}x{Nz}x{Nomega}-s{seed}", Nx, dx, dz, Nz, CHI0,
+                    CHIH, CHIH, THETA_B, LAMBDA, Nomega, delta, E0, u,
+                    x_front, thickness, {"seed": seed})
+
+
+def c1_perfect_crystal() -> Workload:
+    """Monochromatic perfect crystal, 1024 x 2000 steps, one slice, incidence
+    at the refraction-shifted Darwin centre, no deformation."""
+    Nx, Nz = 1024, 2000
+    theta_i = THETA_B + 1.5e-5
+    delta = np.zeros(1)
+    E0 = incident_envelope(Nx, DX, LAMBDA, THETA_B, delta, theta_i, np.ones(1))
+    return _common("perfect-crystal-1024x2000x1", Nx, Nz, 1, delta, E0, None,
+                   theta_i=theta_i)
+
+
+def c2_bent_crystal(seed: int = 2) -> Workload:
+    """Bent crystal (R = 10 m), 2048 x 4000 steps, 256 slices of a 10 fs pulse
+    spanning +-5 Darwin widths with a random spectral phase of 0.1 rad."""
+    Nx, Nz, Nw = 2048, 4000, 256
+    rng = np.random.default_rng(seed)
+    eps = darwin_relative_width(CHIH, CHIH, THETA_B)
+    delta = detuning_grid(Nw, eps)
+    amp = pulse_amplitudes(delta, LAMBDA, 10e-15, rng)
+    E0 = incident_envelope(Nx, DX, LAMBDA, THETA_B, delta, THETA_B, amp)
+    u = bent_displacement(Nx, DX, Nz, 10.0)
+    return _common("bent-crystal-2048x4000x256", Nx, Nz, Nw, delta, E0, u,
+                   R=10.0, sigma_t=10e-15, seed=seed)
+
+
+def c3_thermal_bump(seed: int = 3, Nomega: int = 1024) -> Workload:
+    """Thermal bump (1e-10 m, sigma 100 um) plus white-noise strain of rms
+    1e-7, 4096 x 8192 steps, 1024 pulse slices."""
+    Nx, Nz = 4096, 8192
+    rng = np.random.default_rng(seed)
+    eps = darwin_relative_width(CHIH, CHIH, THETA_B)
+    delta = detuning_grid(Nomega, eps)
+    amp = pulse_amplitudes(delta, LAMBDA, 10e-15, rng)
+    E0 = incident_envelope(Nx, DX, LAMBDA, THETA_B, delta, THETA_B, amp)
+    gz, gx = bump_factors(Nx, DX, Nz, DZ, 1e-10, 100e-6)
+    u = (1e-10 * gz)[:, None] * gx[None, :]
+    strain = rng.normal(0.0, 1e-7, size=(Nz, Nx))
+    cs = np.cumsum(strain, axis=1)
+    j0 = Nx // 2
+    u += DX * (cs - cs[:, j0][:, None])
+    return _common("thermal-bump-4096x8192x1024", Nx, Nz, Nomega, delta, E0, u,
+                   sigma_t=10e-15, seed=seed)
+
+
+C4_NX = (256, 512, 1024, 2048, 4096)
+C4_NOMEGA = (1, 16, 64, 256)
+
+
+def c4_problem_specs(n: int = 512, seed: int = 4) -> list:
+    """Sizes and parameters of the uneven batch: Nx in {256..4096}, Nz uniform
+    in [500, 8000], Nomega in {1, 16, 64, 256}, bend radius R in [1, 100] m,
+    bump amplitude in [0, 1e-10] m; one sub-seed per problem."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(n):
+        specs.append(dict(
+            index=i,
+            Nx=int(rng.choice(C4_NX)),
+            Nz=int(rng.integers(500, 8001)),
+            Nomega=int(rng.choice(C4_NOMEGA)),
+            R=float(rng.uniform(1.0, 100.0)),
+            bump=float(rng.uniform(0.0, 1e-10)),
+            seed=int(rng.integers(0, 2**31 - 1)),
+        ))
+    return specs
+
+
+def c4_problem(spec: dict, with_u: bool = True) -> Workload:
+    """Materialise one batch problem: pulse as in the bent-crystal workload,
+    u = x^2/(2R) + separable Gaussian bump (sigma 100 um).  The displacement
+    is also returned in separable form in meta['u_factors'] = (row, gz, gx,
+    amp) with u[n, j] = row[j] + (amp * gz[n]) * gx[j]."""
+    Nx, Nz, Nw = spec["Nx"], spec["Nz"], spec["Nomega"]
+    rng = np.random.default_rng(spec["seed"])
+    eps = darwin_relative_width(CHIH, CHIH, THETA_B)
+    delta = detuning_grid(Nw, eps)
+    amp = pulse_amplitudes(delta, LAMBDA, 10e-15, rng)
+    E0 = incident_envelope(Nx, DX, LAMBDA, THETA_B, delta, THETA_B, amp)
+    xs = x_grid(Nx, DX)
+    row = xs * xs / (2.0 * spec["R"])
+    gz, gx = bump_factors(Nx, DX, Nz, DZ, spec["bump"], 100e-6)
+    u = None
+    if with_u:
+        u = row[None, :] + (spec["bump"] * gz)[:, None] * gx[None, :]
+    w = _common(f"batch-{spec['index']}-{Nx}x{Nz}x{Nw}", Nx, Nz, Nw, delta, E0,
+                u, **spec)
+    w.meta["u_factors"] = (row, gz, gx, spec["bump"])
+    return w
+
+
+def c5_request_trace(rate: float = 200.0, duration: float = 60.0, seed: int = 5):
+    """Poisson arrival trace: list of (arrival_time_s, spec, precision) with
+    sizes drawn as in the uneven batch and precision 'fp64' or 'fp32' with
+    probability 1/2 each."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    i = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        spec = dict(
+            index=i,
+            Nx=int(rng.choice(C4_NX)),
+            Nz=int(rng.integers(500, 8001)),
+            Nomega=int(rng.choice(C4_NOMEGA)),
+            R=float(rng.uniform(1.0, 100.0)),
+            bump=float(rng.uniform(0.0, 1e-10)),
+            seed=int(rng.integers(0, 2**31 - 1)),
+        )
+        prec = "fp64" if rng.uniform() < 0.5 else "fp32"
+        out.append((t, spec, prec))
+        i += 1
+    return out
+
+
+def by_name(name: str) -> Workload:
+    table = {
+        "perfect-crystal-1024x2000x1": c1_perfect_crystal,
+        "bent-crystal-2048x4000x256": c2_bent_crystal,
+        "thermal-bump-4096x8192x1024": c3_thermal_bump,
+    }
+    return table[name]()
