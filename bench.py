@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the FFT beam-propagation z-march on one MI355X.
+
+Workload: the time-dependent bent crystal -- Nx = 2048 transverse points,
+Nz = 4000 steps of 0.5 um, Nomega = 256 frequency slices of a 10 fs pulse,
+u = x^2 / (2R), R = 10 m (seeded synthetic inputs, workloads.c2_bent_crystal).
+One benchmark step is one pass of the whole hot path: the deformation
+pre-pass (exp(i h u) table) plus the march of all slices, inputs resident in
+HBM.  Metric: cell-updates/s = Nx * Nz * Nomega / step time.
+
+Prints one JSON line.  The oracle (CPU, FP64 numpy) is timed on a bounded
+sample of slices on the host's cores as a reported baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("cell-updates/s (Nx·Nz·Nω) fp32 vs fp64 at relL2≤1e-5; "
+          "p50/p99 request latency")
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X vector peaks (published)
+HBM_PEAK_GBS = 8000.0
+
+
+def flops_per_cell_update(Nx: int) -> float:
+    """Algorithmic flops of one (x, z-step, slice) update: four complex FFTs
+    (two envelopes, forward and inverse) at 5 N log2 N each, two complex
+    propagator multiplies (6 each) and the deformed coupling (six complex
+    multiplies and two complex adds)."""
+    return 4 * 5 * math.log2(Nx) + 2 * 6 + (6 * 6 + 2 * 2)
+
+
+def lds_bytes_per_cell_update(Nx: int, storage_bytes: int, passes: int) -> float:
+    """LDS traffic of the kernel design: every exchange between Stockham
+    passes writes and reads each complex sample once, for two envelopes and
+    two transform directions."""
+    return 2 * 2 * (passes - 1) * 2 * 2 * storage_bytes
+
+
+PASSES = {256: 4, 512: 3, 1024: 4, 2048: 4, 4096: 4}
+
+
+def _cpu_worker(args):
+    slices, seed, barrier_t0 = args
+    import numpy as np
+    import oracle as O
+    import workloads as W
+    w = W.c2_bent_crystal(seed=seed).subset(slices)
+    p = O.Problem.from_workload(w)
+    while time.time() < barrier_t0:   # common start after every worker's setup
+        time.sleep(0.001)
+    t0 = time.time()
+    O.march(p, w.E0_in, w.u)
+    t1 = time.time()
+    return w.cell_updates, t0, t1
+
+
+def cpu_baseline(slices_per_core: int = 12, cores: int | None = None) -> dict:
+    """Time the oracle, unmodified, on the host: `cores` processes, each
+    marching `slices_per_core` slices of the workload through all Nz steps
+    with one FFT thread."""
+    import multiprocessing as mp
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    ncpu = os.cpu_count() or 1
+    cores = min(cores or ncpu, 16, ncpu)
+    start = time.time() + 15.0 + 0.5 * cores   # leaves time for input setup
+    jobs = [(list(range(c * slices_per_core, (c + 1) * slices_per_core)), 2, start)
+            for c in range(cores)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_cpu_worker, jobs)
+    cells = sum(r[0] for r in res)
+    wall = max(r[2] for r in res) - min(r[1] for r in res)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": cells / wall, "unit": "cell-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{cores} processes x {slices_per_core} slices x 4000 steps "
+                      f"x 2048 points of the bent-crystal workload "
+                      f"({cells:.3e} cell-updates, {wall:.1f} s wall, {model})"}
+
+
+def run_variant(w, prec, steps, warmup, E0_np, u_t):
+    import numpy as np
+    import torch
+    from paper_2201_08500_amd import Plan
+    plan = Plan.from_workload(w, precision=prec)
+    E0 = torch.from_numpy(E0_np).to(plan.field_dtype).cuda()
+    a = torch.empty_like(E0)
+    b = torch.empty_like(E0)
+    ws = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        plan.deformation_table(u_t, ws, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.march(E0, ws, a, b, stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    march_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    deform_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    out = (a.cpu().numpy().astype(np.complex128), b.cpu().numpy().astype(np.complex128))
+    return dict(total_s=t1 - t0, march_ms=float(np.mean(march_ms)),
+                deform_ms=float(np.mean(deform_ms)), out=out)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--headline", default="fp32s",
+                    choices=["fp32s", "fp32", "fp64"])
+    ap.add_argument("--variants", default="fp32s,fp32,fp64")
+    ap.add_argument("--oracle-slices", default="120,128,136",
+                    help="slices recomputed by the oracle for the error report")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slices-per-core", type=int, default=12)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the "
+              "march shards over frequency slices with no exchange, so N GPUs "
+              "would each run this same single-GPU launch on Nomega/N slices.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from workloads.metrics import report
+
+    torch.cuda.set_device(0)
+    w = W.c2_bent_crystal()
+    u_t = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
+    cells = w.cell_updates
+    variants = [v for v in args.variants.split(",") if v]
+    if args.headline not in variants:
+        variants.insert(0, args.headline)
+
+    results = {}
+    for prec in variants:
+        print(f"[bench] {prec}: warmup {args.warmup}, timing {args.steps} steps",
+              file=sys.stderr, flush=True)
+        results[prec] = run_variant(w, prec, args.steps, args.warmup, w.E0_in, u_t)
+
+    # precision report: every variant against the FP64 GPU run (all slices)
+    # and against the oracle on a few slices
+    sl = [int(s) for s in args.oracle_slices.split(",") if s]
+    import oracle as O
+    ws = w.subset(sl)
+    ref = O.march(O.Problem.from_workload(ws), ws.E0_in, ws.u)
+    ref32 = None
+    prec_report = {}
+    for prec, r in results.items():
+        a, b = r["out"]
+        entry = {}
+        if prec == "fp64":
+            entry["vs_oracle"] = report(a[sl], b[sl], *ref)
+        else:
+            if ref32 is None:
+                E32 = ws.E0_in.astype(np.complex64).astype(np.complex128)
+                ref32 = O.march(O.Problem.from_workload(ws), E32, ws.u)
+            entry["vs_oracle"] = report(a[sl], b[sl], *ref32)
+            if "fp64" in results:
+                entry["vs_fp64_gpu_all_slices"] = report(a, b, *results["fp64"]["out"])
+        march_s = r["march_ms"] / 1e3
+        entry.update(cell_updates_per_s=cells * args.steps / r["total_s"],
+                     march_ms=r["march_ms"], deform_ms=r["deform_ms"],
+                     march_cell_updates_per_s=cells / march_s)
+        prec_report[prec] = entry
+
+    head = results[args.headline]
+    dtype = {"fp32s": "f64", "fp32": "f32", "fp64": "f64"}[args.headline]
+    storage = 8 if args.headline in ("fp32s", "fp32") else 16
+    F = flops_per_cell_update(w.Nx)
+    achieved = F * cells / (head["march_ms"] / 1e3) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    lds_b = lds_bytes_per_cell_update(w.Nx, storage // 2, PASSES[w.Nx])
+    line = {
+        "metric": METRIC,
+        "value": cells * args.steps / head["total_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["total_s"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "Nx": w.Nx, "Nz": w.Nz,
+                   "Nomega": w.Nomega, "precision": args.headline,
+                   "storage": "complex64" if storage == 8 else "complex128"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "march", "flops_per_cell_update": F,
+                     "march_ms": head["march_ms"],
+                     "lds_bytes_per_cell_update": lds_b,
+                     "lds_TBps": lds_b * cells / (head["march_ms"] / 1e3) / 1e12},
+        "precision_variants": prec_report,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle on host cores)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_slices_per_core)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

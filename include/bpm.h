@@ -1,0 +1,137 @@
+/*
+ * bpm.h -- C ABI of the MI355X (gfx950) FFT beam-propagation z-march.
+ *
+ * The library advances the two slowly varying envelopes of a two-beam Bragg
+ * problem -- psi~_+ (transmitted band, carrier +h/2) and psi~_- (reflected
+ * band, carrier -h/2), Eq. fov7 -- through Nz split steps of length dz,
+ * independently for each of Nomega frequency slices of a pulse (Eq. tdp).
+ * One step (Eq. fov10 with the Zassenhaus-like factor of Section 2.1) is
+ *
+ *   a_p = F^-1[ P+(K) F[a] ],  b_p = F^-1[ P-(K) F[b] ],
+ *       P+-(K) = exp(i dz sqrt(k^2 - (K +- h/2)^2))          (Eq. fov4)
+ *   inside the crystal (Pi = 1):
+ *   a' = d0 a_p + d+1 exp(+i h u) b_p,  b' = d0 b_p + d-1 exp(-i h u) a_p
+ *   outside (Pi = 0): a' = a_p, b' = b_p,
+ *
+ * with d0, d+-1 the n = 0, +-1 Jacobi-Anger coefficients of the
+ * susceptibility exponential (Eqs. fov9, fov11, fov12, generalised to
+ * chih != chihbar; d0 times exp(q/8), q = (k dz)^2 chih chihbar / cos^2 alpha)
+ * and u the displacement along h (Eq. Authier, printed sign).
+ *
+ * Units: SI (metres, radians).  Sample j of a field sits at
+ * x_j = (j - Nx/2) dx; row n of u is used by step n (z_n = n dz).
+ * k0 = 2 pi / lambda, h = 2 k0 sin(theta_B), k = k0 (1 + delta_w) for slice w,
+ * cos(alpha) = sqrt(1 - (h / 2k)^2).
+ *
+ * Memory: every field pointer is DEVICE memory, row-major [Nomega][Nx],
+ * interleaved complex (re, im): complex128 for BPM_PREC_FP64, complex64 for
+ * BPM_PREC_FP32 and BPM_PREC_FP32S.  u_field is device float64 [Nz][Nx].
+ * The caller owns all field buffers; the plan owns only its constants.
+ *
+ * Errors: functions return BPM_OK (0) or a negative code and never abort;
+ * bpm_last_error() gives a message for the calling thread.  Calls are
+ * asynchronous on the given stream (a hipStream_t passed as void*, NULL for
+ * the default stream) and never synchronise; buffers must stay alive until
+ * the stream has completed the work.
+ */
+#ifndef BPM_H
+#define BPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } bpm_complex;
+typedef struct bpm_plan bpm_plan;
+
+enum {
+  BPM_OK = 0,
+  BPM_EINVAL = -1,        /* invalid argument or plan state */
+  BPM_ENOMEM = -2,        /* device allocation failed */
+  BPM_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+  BPM_EUNSUPPORTED = -4   /* valid but not implemented (size, option) */
+};
+
+enum {
+  BPM_PREC_FP64 = 0,      /* complex128 fields, FP64 arithmetic throughout */
+  BPM_PREC_FP32 = 1,      /* complex64 fields, FP32 FFT butterflies; FP64
+                             phases (propagator and deformation reduced mod
+                             2 pi in FP64) and FP64 pointwise multiplies */
+  BPM_PREC_FP32S = 2      /* complex64 fields and on-chip storage, FP64
+                             butterflies and pointwise arithmetic */
+};
+
+/* Create a plan for Nomega slices of an Nx-point window (Section 2.1 problem
+ * statement: grid dx, step dz, Nz steps, susceptibilities chi0, chih,
+ * chihbar, Bragg angle theta_B in radians, wavelength lambda in metres).
+ * Nx must be a power of two in [256, 4096]; Nz, Nomega >= 1; dx, dz,
+ * lambda > 0; 0 < theta_B < pi/2.  Defaults: precision FP64, crystal slab
+ * x >= 0 (x_front = 0, infinite thickness), first-order splitting with the
+ * Zassenhaus factor, detuning grid of Nomega cell-centred offsets spanning
+ * +-5 Darwin widths |sqrt(chih chihbar)| / sin^2(theta_B) (zero for a
+ * single slice).  Returns NULL on invalid input (see bpm_last_error). */
+bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
+                          bpm_complex chi0, bpm_complex chih,
+                          bpm_complex chihbar, double theta_B, double lambda,
+                          int Nomega);
+
+/* Setters: allowed until the plan's first propagate, BPM_EINVAL after. */
+int bpm_plan_set_precision(bpm_plan* plan, int precision);
+/* Crystal mask Pi_j = [x_front <= x_j < x_front + thickness]; thickness may
+ * be +inf.  (Symmetric Bragg slab, Section 2.1.) */
+int bpm_plan_set_crystal(bpm_plan* plan, double x_front, double thickness);
+/* Relative frequency offsets delta_w of the Nomega slices (host array,
+ * copied). */
+int bpm_plan_set_detuning(bpm_plan* plan, const double* delta);
+/* split_order: 1 (Eq. fov4), 2 or 4 (Eq. split-op); zassenhaus: 0 or 1. */
+int bpm_plan_set_options(bpm_plan* plan, int split_order, int zassenhaus);
+
+/* Host-only diagnostic: the FP64 constants of slice w for B sub-step 0,
+ * out[0..7] = k, cos(alpha), d0.re, d0.im, d+1.re, d+1.im, d-1.re, d-1.im
+ * (Section 2.1: cos(alpha) = sqrt(1 - (h/2k)^2), Eqs. fov11, fov12 and the
+ * Zassenhaus factor).  Touches no device. */
+int bpm_plan_get_constants(const bpm_plan* plan, int w, double* out);
+
+/* Bytes of device workspace a deformed propagate needs (the per-cell
+ * deformation-phase table exp(i h u), shared by all slices). */
+size_t bpm_workspace_bytes(const bpm_plan* plan);
+
+/* Run the march for all slices.  E0_in: psi~_+ at z = 0 (psi~_- starts at
+ * zero).  u_field may be NULL (undeformed crystal).  E0_out, Eh_out receive
+ * psi~_+ and psi~_- after Nz steps; they must not alias E0_in.  The
+ * workspace is allocated stream-ordered and released on the stream. */
+int bpm_propagate(const bpm_plan* plan, const void* E0_in,
+                  const double* u_field, void* E0_out, void* Eh_out,
+                  void* stream);
+
+/* As bpm_propagate, with a caller-owned workspace of at least
+ * bpm_workspace_bytes(plan) bytes (ignored when u_field is NULL). */
+int bpm_propagate_ws(const bpm_plan* plan, const void* E0_in,
+                     const double* u_field, void* E0_out, void* Eh_out,
+                     void* workspace, void* stream);
+
+/* The two halves of bpm_propagate_ws, for callers that time or schedule
+ * them separately.
+ * bpm_deformation_table: fill the workspace with exp(i h u) for every cell
+ * (Eq. Authier; h u reduced modulo 2 pi in FP64 before an FP32 sincos for
+ * the FP32 precisions, FP64 sincos for BPM_PREC_FP64).
+ * bpm_march: the Nz-step march of all slices reading that table (or none
+ * when table is NULL, i.e. u = 0). */
+int bpm_deformation_table(const bpm_plan* plan, const double* u_field,
+                          void* workspace, void* stream);
+int bpm_march(const bpm_plan* plan, const void* E0_in, const void* table,
+              void* E0_out, void* Eh_out, void* stream);
+
+void bpm_plan_destroy(bpm_plan* plan);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* bpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPM_H */

@@ -1,0 +1,233 @@
+"""ctypes binding of libbpm.so (include/bpm.h): argument marshalling only.
+
+Every step of the march runs in the library's gfx950 kernels; PyTorch only
+provides device memory and streams.  If the library is not built the import
+fails loudly -- there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbpm.so")
+
+BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_EUNSUPPORTED = 0, -1, -2, -3, -4
+PRECISION = {"fp64": 0, "fp32": 1, "fp32s": 2}
+_CODES = {BPM_EINVAL: "EINVAL", BPM_ENOMEM: "ENOMEM", BPM_EHIP: "EHIP",
+          BPM_EUNSUPPORTED: "EUNSUPPORTED"}
+
+
+class BpmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bpm error {_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class bpm_complex(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+# (name, restype, argtypes) of every exported function
+_SIGNATURES = [
+    ("bpm_plan_create", ctypes.c_void_p,
+     [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+      bpm_complex, bpm_complex, bpm_complex, ctypes.c_double, ctypes.c_double,
+      ctypes.c_int]),
+    ("bpm_plan_set_precision", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("bpm_plan_set_crystal", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]),
+    ("bpm_plan_set_detuning", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    ("bpm_plan_set_options", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    ("bpm_plan_get_constants", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    ("bpm_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p]),
+    ("bpm_propagate", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_void_p, ctypes.c_void_p]),
+    ("bpm_propagate_ws", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("bpm_deformation_table", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("bpm_march", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_void_p, ctypes.c_void_p]),
+    ("bpm_plan_destroy", None, [ctypes.c_void_p]),
+    ("bpm_last_error", ctypes.c_char_p, []),
+]
+
+
+def lib():
+    """The loaded library (raises if libbpm.so has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(
+                    f"{LIB_PATH} is missing: build it with "
+                    "paper_2201_08500_amd.build.build() (no fallback path exists)")
+            handle = ctypes.CDLL(LIB_PATH)
+            for name, res, args in _SIGNATURES:
+                fn = getattr(handle, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = handle
+    return _lib
+
+
+def last_error() -> str:
+    return lib().bpm_last_error().decode()
+
+
+def _check(rc):
+    if rc != BPM_OK:
+        raise BpmError(rc, last_error())
+
+
+def _cx(z) -> bpm_complex:
+    z = complex(z)
+    return bpm_complex(z.real, z.imag)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Owns a bpm_plan (see include/bpm.h for the meaning of every argument)."""
+
+    def __init__(self, Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam,
+                 Nomega, precision="fp64", x_front=None, thickness=None,
+                 delta=None, split_order=1, zassenhaus=True):
+        L = lib()
+        self._h = None
+        h = L.bpm_plan_create(int(Nx), float(dx), float(dz), int(Nz),
+                              _cx(chi0), _cx(chih), _cx(chihbar),
+                              float(theta_B), float(lam), int(Nomega))
+        if not h:
+            raise BpmError(BPM_EINVAL, last_error())
+        self._h = ctypes.c_void_p(h)
+        self.Nx, self.Nz, self.Nomega = int(Nx), int(Nz), int(Nomega)
+        self.precision = precision
+        _check(L.bpm_plan_set_precision(self._h, PRECISION[precision]))
+        if x_front is not None or thickness is not None:
+            _check(L.bpm_plan_set_crystal(
+                self._h, float(0.0 if x_front is None else x_front),
+                float(math.inf if thickness is None else thickness)))
+        if delta is not None:
+            arr = (ctypes.c_double * self.Nomega)(*[float(d) for d in delta])
+            _check(L.bpm_plan_set_detuning(self._h, arr))
+        if split_order != 1 or not zassenhaus:
+            _check(L.bpm_plan_set_options(self._h, int(split_order),
+                                          int(bool(zassenhaus))))
+
+    @classmethod
+    def from_workload(cls, w, precision="fp64", **kw):
+        return cls(w.Nx, w.dx, w.dz, w.Nz, w.chi0, w.chih, w.chihbar,
+                   w.theta_B, w.lam, w.Nomega, precision=precision,
+                   x_front=w.x_front, thickness=w.thickness, delta=w.delta, **kw)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def field_dtype(self):
+        import torch
+        return torch.complex128 if self.precision == "fp64" else torch.complex64
+
+    def constants(self, w: int):
+        out = (ctypes.c_double * 8)()
+        _check(lib().bpm_plan_get_constants(self._h, int(w), out))
+        return list(out)
+
+    def workspace_bytes(self) -> int:
+        return int(lib().bpm_workspace_bytes(self._h))
+
+    def _check_field(self, t, name):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()
+                and t.dtype == self.field_dtype
+                and tuple(t.shape) == (self.Nomega, self.Nx)):
+            raise ValueError(f"{name} must be a contiguous CUDA {self.field_dtype} "
+                             f"tensor of shape ({self.Nomega}, {self.Nx})")
+
+    def propagate(self, E0_in, u=None, E0_out=None, Eh_out=None,
+                  workspace=None, stream=None):
+        """bpm_propagate (or bpm_propagate_ws when a workspace is given);
+        returns (E0_out, Eh_out).  Asynchronous on the stream."""
+        import torch
+        self._check_field(E0_in, "E0_in")
+        if u is not None:
+            if not (u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
+                    and tuple(u.shape) == (self.Nz, self.Nx)):
+                raise ValueError(f"u must be a contiguous CUDA float64 tensor "
+                                 f"of shape ({self.Nz}, {self.Nx})")
+        if E0_out is None:
+            E0_out = torch.empty_like(E0_in)
+        if Eh_out is None:
+            Eh_out = torch.empty_like(E0_in)
+        self._check_field(E0_out, "E0_out")
+        self._check_field(Eh_out, "Eh_out")
+        s = _stream_handle(stream)
+        if workspace is None:
+            rc = lib().bpm_propagate(self._h, _ptr(E0_in), _ptr(u), _ptr(E0_out),
+                                     _ptr(Eh_out), s)
+        else:
+            if workspace.numel() * workspace.element_size() < self.workspace_bytes():
+                raise ValueError("workspace too small")
+            rc = lib().bpm_propagate_ws(self._h, _ptr(E0_in), _ptr(u),
+                                        _ptr(E0_out), _ptr(Eh_out),
+                                        _ptr(workspace), s)
+        _check(rc)
+        return E0_out, Eh_out
+
+    def deformation_table(self, u, workspace, stream=None):
+        """bpm_deformation_table: exp(i h u) for every cell into workspace."""
+        import torch
+        if not (u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
+                and tuple(u.shape) == (self.Nz, self.Nx)):
+            raise ValueError("u must be a contiguous CUDA float64 (Nz, Nx) tensor")
+        if workspace.numel() * workspace.element_size() < self.workspace_bytes():
+            raise ValueError("workspace too small")
+        _check(lib().bpm_deformation_table(self._h, _ptr(u), _ptr(workspace),
+                                           _stream_handle(stream)))
+        return workspace
+
+    def march(self, E0_in, table, E0_out, Eh_out, stream=None):
+        """bpm_march: the Nz-step march reading a deformation table (or None)."""
+        self._check_field(E0_in, "E0_in")
+        self._check_field(E0_out, "E0_out")
+        self._check_field(Eh_out, "Eh_out")
+        _check(lib().bpm_march(self._h, _ptr(E0_in), _ptr(table), _ptr(E0_out),
+                               _ptr(Eh_out), _stream_handle(stream)))
+        return E0_out, Eh_out
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.bpm_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,363 @@
+// Host side of the C ABI: argument validation, FP64 plan constants, device
+// constant upload and the propagate entry points.
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <string>
+
+#include "bpm_internal.h"
+
+using cplx = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(BPM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// J0(sqrt q) and 2 J1(sqrt q)/sqrt q as power series in q:
+//   S0 = sum_m (-q/4)^m / (m!)^2,  S1 = sum_m (-q/4)^m / (m! (m+1)!).
+// Both are entire and even in sqrt(q), so no branch of sqrt(q) is needed
+// (Jacobi-Anger coefficients of Eqs. fov11, fov12 with chih != chihbar).
+void bessel_series(cplx q, cplx& S0, cplx& S1) {
+  const cplx x = -q / 4.0;
+  cplx t0 = 1.0, t1 = 1.0;
+  S0 = t0;
+  S1 = t1;
+  for (int m = 1; m < 300; ++m) {
+    t0 *= x / double(m) / double(m);
+    t1 *= x / double(m) / double(m + 1);
+    S0 += t0;
+    S1 += t1;
+    if (std::abs(t0) <= 1e-18 * std::abs(S0) &&
+        std::abs(t1) <= 1e-18 * std::abs(S1))
+      break;
+  }
+}
+
+// Sub-step fractions of Eq. split-op.
+void split_fractions(int order, int& n, double a[4], double b[4]) {
+  if (order == 2) {
+    n = 2;
+    a[0] = 0.0; a[1] = 1.0;
+    b[0] = 0.5; b[1] = 0.5;
+  } else if (order == 4) {
+    const double t = 1.0 / (2.0 - std::cbrt(2.0));
+    n = 4;
+    a[0] = 0.0; a[1] = t; a[2] = 1.0 - 2.0 * t; a[3] = t;
+    b[0] = t / 2; b[1] = (1 - t) / 2; b[2] = (1 - t) / 2; b[3] = t / 2;
+  } else {
+    n = 1;
+    a[0] = 1.0;
+    b[0] = 1.0;
+  }
+}
+
+// Per-slice constants: k, and for each B sub-step of length frac*dz the
+// coupling d0 = S0 exp(q/8) g0 (Zassenhaus factor D2 dZ^2/2 = q/8),
+// d+-1 = i (dZ chi_{h,hbar} / 2c) S1 g0, g0 = exp(i dZ chi0 / 2c),
+// q = dZ^2 chih chihbar / c^2, dZ = frac k dz, c = sqrt(1 - (h/2k)^2).
+int compute_slice_constants(bpm_plan* p) {
+  int nsub;
+  double a[4], b[4];
+  split_fractions(p->split_order, nsub, a, b);
+  p->sc.assign(p->Nomega, bpm::SliceConst{});
+  for (int w = 0; w < p->Nomega; ++w) {
+    bpm::SliceConst& s = p->sc[w];
+    const double k = p->k0 * (1.0 + p->delta[w]);
+    const double sh = 0.5 * p->h / k;
+    if (!(k > 0.0) || !(sh < 1.0))
+      return fail(BPM_EINVAL, "slice " + std::to_string(w) +
+                                  ": h/2 >= k (no propagating Bragg pair)");
+    const double c = std::sqrt(1.0 - sh * sh);
+    s.k = k;
+    for (int i = 0; i < nsub; ++i) {
+      const double dZ = b[i] * k * p->dz;
+      const cplx q = dZ * dZ * p->chih * p->chihbar / (c * c);
+      if (std::abs(q) > 16.0)
+        return fail(BPM_EINVAL,
+                    "step too long for the two-beam expansion: |q| = " +
+                        std::to_string(std::abs(q)) + " > 16");
+      cplx S0, S1;
+      bessel_series(q, S0, S1);
+      const cplx I(0.0, 1.0);
+      const cplx g0 = std::exp(I * dZ * p->chi0 / (2.0 * c));
+      cplx d0 = S0 * g0;
+      if (p->zassenhaus) d0 *= std::exp(q / 8.0);
+      const cplx dp1 = I * (dZ * p->chih / (2.0 * c)) * S1 * g0;
+      const cplx dm1 = I * (dZ * p->chihbar / (2.0 * c)) * S1 * g0;
+      s.d[i][0] = d0.real(); s.d[i][1] = d0.imag();
+      s.d[i][2] = dp1.real(); s.d[i][3] = dp1.imag();
+      s.d[i][4] = dm1.real(); s.d[i][5] = dm1.imag();
+    }
+  }
+  return BPM_OK;
+}
+
+// Freeze the plan on first use: constants computed and uploaded once.
+int freeze(bpm_plan* p) {
+  std::lock_guard<std::mutex> lock(p->mu);
+  if (p->frozen) return BPM_OK;
+  int rc = compute_slice_constants(p);
+  if (rc != BPM_OK) return rc;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipMalloc(&p->dev_sc, sizeof(bpm::SliceConst) * p->Nomega);
+  if (e != hipSuccess) {
+    p->dev_sc = nullptr;
+    return fail(BPM_ENOMEM, std::string("hipMalloc(plan constants): ") +
+                                hipGetErrorString(e));
+  }
+  e = hipMemcpy(p->dev_sc, p->sc.data(), sizeof(bpm::SliceConst) * p->Nomega,
+                hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan constants)");
+  p->frozen = true;
+  return BPM_OK;
+}
+
+int check_mutable(bpm_plan* p) {
+  if (!p) return fail(BPM_EINVAL, "plan is NULL");
+  if (p->frozen) return fail(BPM_EINVAL, "plan is frozen after its first propagate");
+  return BPM_OK;
+}
+
+void default_detuning(bpm_plan* p) {
+  p->delta.assign(p->Nomega, 0.0);
+  if (p->Nomega == 1) return;
+  const double eps = std::abs(std::sqrt(p->chih * p->chihbar)) /
+                     (std::sin(p->theta_B) * std::sin(p->theta_B));
+  for (int j = 0; j < p->Nomega; ++j)
+    p->delta[j] = eps * (-5.0 + 10.0 * (j + 0.5) / p->Nomega);
+}
+
+bpm::MarchParams march_params(const bpm_plan* p, const void* E0_in,
+                              const void* table, void* E0_out, void* Eh_out) {
+  bpm::MarchParams m{};
+  m.E0_in = E0_in;
+  m.E0_out = E0_out;
+  m.Eh_out = Eh_out;
+  m.table = table;
+  m.sc = p->dev_sc;
+  m.Nz = p->Nz;
+  int nsub;
+  double b[4];
+  split_fractions(p->split_order, nsub, m.a_frac, b);
+  m.nsub = nsub;
+  m.dx = p->dx;
+  m.dz = p->dz;
+  m.h_half = 0.5 * p->h;
+  m.x_front = p->x_front;
+  m.x_end = p->x_front + p->thickness;
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
+                          bpm_complex chi0, bpm_complex chih,
+                          bpm_complex chihbar, double theta_B, double lambda,
+                          int Nomega) {
+  g_error.clear();
+  if (!is_pow2(Nx) || Nx < 256 || Nx > 4096) {
+    fail(BPM_EINVAL, "Nx must be a power of two in [256, 4096]");
+    return nullptr;
+  }
+  if (Nz < 1 || Nomega < 1) {
+    fail(BPM_EINVAL, "Nz and Nomega must be >= 1");
+    return nullptr;
+  }
+  if (!(dx > 0) || !(dz > 0) || !(lambda > 0) || !std::isfinite(dx) ||
+      !std::isfinite(dz) || !std::isfinite(lambda)) {
+    fail(BPM_EINVAL, "dx, dz and lambda must be finite and > 0");
+    return nullptr;
+  }
+  if (!(theta_B > 0) || !(theta_B < M_PI / 2)) {
+    fail(BPM_EINVAL, "theta_B must lie in (0, pi/2)");
+    return nullptr;
+  }
+  bpm_plan* p = new bpm_plan();
+  p->Nx = Nx;
+  p->Nz = Nz;
+  p->Nomega = Nomega;
+  p->dx = dx;
+  p->dz = dz;
+  p->chi0 = cplx(chi0.re, chi0.im);
+  p->chih = cplx(chih.re, chih.im);
+  p->chihbar = cplx(chihbar.re, chihbar.im);
+  p->theta_B = theta_B;
+  p->lambda = lambda;
+  p->k0 = 2.0 * M_PI / lambda;
+  p->h = 2.0 * p->k0 * std::sin(theta_B);
+  default_detuning(p);
+  return p;
+}
+
+int bpm_plan_set_precision(bpm_plan* p, int precision) {
+  int rc = check_mutable(p);
+  if (rc) return rc;
+  if (precision != BPM_PREC_FP64 && precision != BPM_PREC_FP32 &&
+      precision != BPM_PREC_FP32S)
+    return fail(BPM_EINVAL, "unknown precision");
+  p->precision = precision;
+  return BPM_OK;
+}
+
+int bpm_plan_set_crystal(bpm_plan* p, double x_front, double thickness) {
+  int rc = check_mutable(p);
+  if (rc) return rc;
+  if (!std::isfinite(x_front) || !(thickness >= 0))
+    return fail(BPM_EINVAL, "x_front must be finite and thickness >= 0");
+  p->x_front = x_front;
+  p->thickness = thickness;
+  return BPM_OK;
+}
+
+int bpm_plan_set_detuning(bpm_plan* p, const double* delta) {
+  int rc = check_mutable(p);
+  if (rc) return rc;
+  if (!delta) return fail(BPM_EINVAL, "delta is NULL");
+  for (int j = 0; j < p->Nomega; ++j)
+    if (!std::isfinite(delta[j]) || !(delta[j] > -1.0))
+      return fail(BPM_EINVAL, "delta must be finite and > -1");
+  p->delta.assign(delta, delta + p->Nomega);
+  return BPM_OK;
+}
+
+int bpm_plan_set_options(bpm_plan* p, int split_order, int zassenhaus) {
+  int rc = check_mutable(p);
+  if (rc) return rc;
+  if (split_order != 1 && split_order != 2 && split_order != 4)
+    return fail(BPM_EINVAL, "split_order must be 1, 2 or 4");
+  if (zassenhaus != 0 && zassenhaus != 1)
+    return fail(BPM_EINVAL, "zassenhaus must be 0 or 1");
+  if (split_order != 1)
+    return fail(BPM_EUNSUPPORTED, "only first-order splitting is implemented on the GPU");
+  p->split_order = split_order;
+  p->zassenhaus = zassenhaus;
+  return BPM_OK;
+}
+
+int bpm_plan_get_constants(const bpm_plan* cp, int w, double* out) {
+  g_error.clear();
+  if (!cp || !out) return fail(BPM_EINVAL, "plan and out must be non-NULL");
+  if (w < 0 || w >= cp->Nomega) return fail(BPM_EINVAL, "slice index out of range");
+  bpm_plan tmp;
+  tmp.Nx = cp->Nx; tmp.Nz = cp->Nz; tmp.Nomega = cp->Nomega;
+  tmp.dx = cp->dx; tmp.dz = cp->dz;
+  tmp.chi0 = cp->chi0; tmp.chih = cp->chih; tmp.chihbar = cp->chihbar;
+  tmp.theta_B = cp->theta_B; tmp.lambda = cp->lambda;
+  tmp.split_order = cp->split_order; tmp.zassenhaus = cp->zassenhaus;
+  tmp.delta = cp->delta; tmp.k0 = cp->k0; tmp.h = cp->h;
+  int rc = compute_slice_constants(&tmp);
+  if (rc) return rc;
+  const bpm::SliceConst& s = tmp.sc[w];
+  const double sh = 0.5 * tmp.h / s.k;
+  out[0] = s.k;
+  out[1] = std::sqrt(1.0 - sh * sh);
+  for (int i = 0; i < 6; ++i) out[2 + i] = s.d[0][i];
+  return BPM_OK;
+}
+
+size_t bpm_workspace_bytes(const bpm_plan* p) {
+  if (!p) return 0;
+  const size_t cell = p->precision == BPM_PREC_FP64 ? 16 : 8;
+  return size_t(p->Nx) * size_t(p->Nz) * cell;
+}
+
+int bpm_deformation_table(const bpm_plan* cp, const double* u_field,
+                          void* workspace, void* stream) {
+  g_error.clear();
+  if (!cp) return fail(BPM_EINVAL, "plan is NULL");
+  if (!u_field || !workspace)
+    return fail(BPM_EINVAL, "u_field and workspace must be non-NULL");
+  bpm_plan* p = const_cast<bpm_plan*>(cp);
+  int rc = freeze(p);
+  if (rc) return rc;
+  rc = bpm::launch_deform(p->precision, p->Nx, p->Nz, p->h, u_field, workspace,
+                          static_cast<hipStream_t>(stream));
+  if (rc) return fail(rc, "deformation pre-pass launch failed");
+  return BPM_OK;
+}
+
+int bpm_march(const bpm_plan* cp, const void* E0_in, const void* table,
+              void* E0_out, void* Eh_out, void* stream) {
+  g_error.clear();
+  if (!cp) return fail(BPM_EINVAL, "plan is NULL");
+  if (!E0_in || !E0_out || !Eh_out)
+    return fail(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
+  if (E0_in == E0_out || E0_in == Eh_out || E0_out == Eh_out)
+    return fail(BPM_EINVAL, "output buffers must not alias each other or E0_in");
+  bpm_plan* p = const_cast<bpm_plan*>(cp);
+  int rc = freeze(p);
+  if (rc) return rc;
+  const bpm::MarchParams m = march_params(p, E0_in, table, E0_out, Eh_out);
+  rc = bpm::launch_march(p->precision, p->Nx, p->Nomega, m,
+                         static_cast<hipStream_t>(stream));
+  if (rc == BPM_EUNSUPPORTED) return fail(rc, "unsupported size/precision");
+  if (rc) return fail(rc, "march kernel launch failed");
+  return BPM_OK;
+}
+
+int bpm_propagate_ws(const bpm_plan* cp, const void* E0_in,
+                     const double* u_field, void* E0_out, void* Eh_out,
+                     void* workspace, void* stream) {
+  g_error.clear();
+  if (!cp) return fail(BPM_EINVAL, "plan is NULL");
+  if (!E0_in || !E0_out || !Eh_out)
+    return fail(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
+  if (E0_in == E0_out || E0_in == Eh_out || E0_out == Eh_out)
+    return fail(BPM_EINVAL, "output buffers must not alias each other or E0_in");
+  if (u_field && !workspace)
+    return fail(BPM_EINVAL, "a deformed propagate needs a workspace");
+  if (u_field) {
+    int rc = bpm_deformation_table(cp, u_field, workspace, stream);
+    if (rc) return rc;
+  }
+  return bpm_march(cp, E0_in, u_field ? workspace : nullptr, E0_out, Eh_out,
+                   stream);
+}
+
+int bpm_propagate(const bpm_plan* p, const void* E0_in, const double* u_field,
+                  void* E0_out, void* Eh_out, void* stream) {
+  g_error.clear();
+  if (!p) return fail(BPM_EINVAL, "plan is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  if (u_field) {
+    hipError_t e = hipMallocAsync(&ws, bpm_workspace_bytes(p), s);
+    if (e != hipSuccess)
+      return fail(BPM_ENOMEM, std::string("hipMallocAsync(workspace): ") +
+                                  hipGetErrorString(e));
+  }
+  int rc = bpm_propagate_ws(p, E0_in, u_field, E0_out, Eh_out, ws, stream);
+  if (ws) {
+    hipError_t e = hipFreeAsync(ws, s);
+    if (rc == BPM_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+  }
+  return rc;
+}
+
+void bpm_plan_destroy(bpm_plan* p) {
+  if (!p) return;
+  if (p->dev_sc) (void)hipFree(p->dev_sc);
+  delete p;
+}
+
+const char* bpm_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

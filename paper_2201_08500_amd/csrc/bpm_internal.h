@@ -1,0 +1,72 @@
+// Internal declarations shared by the host plan (bpm_host.cpp) and the
+// gfx950 kernels (bpm_march.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bpm.h"
+
+namespace bpm {
+
+// Per-slice constants, computed on the host in FP64 and read by the march
+// kernel.  k: wavenumber of the slice; d0, dp1, dm1: coupling constants of
+// one B sub-step (Eq. fov10 with the Zassenhaus factor); up to 4 sub-steps.
+struct SliceConst {
+  double k;
+  double pad;
+  double d[4][6];   // per sub-step: d0.re, d0.im, dp1.re, dp1.im, dm1.re, dm1.im
+};
+
+// Scalars of one launch of the march over a contiguous range of slices.
+struct MarchParams {
+  const void* E0_in;        // [Nomega][Nx] complex (ST precision)
+  void* E0_out;
+  void* Eh_out;
+  const void* table;        // [Nz][Nx] exp(i h u), or nullptr (u == 0)
+  const SliceConst* sc;     // [Nomega]
+  int Nz;
+  int nsub;                 // B sub-steps per step (1, 2 or 4)
+  double dx, dz;
+  double h_half;            // h / 2
+  double x_front, x_end;    // slab [x_front, x_end)
+  double a_frac[4];         // A sub-step fractions (0 = skip)
+};
+
+// One unit of batched work: a contiguous range of slices of one problem.
+struct WorkItem {
+  MarchParams p;
+  int slice0;               // first slice of this item
+  int nslices;              // slices in this item
+  int Nx;                   // selects the kernel body
+  int pad;
+};
+
+int launch_deform(int prec, int Nx, int Nz, double h, const double* u,
+                  void* table, hipStream_t stream);
+int launch_march(int prec, int Nx, int Nomega, const MarchParams& p,
+                 hipStream_t stream);
+
+}  // namespace bpm
+
+struct bpm_plan {
+  int Nx = 0, Nz = 0, Nomega = 0;
+  double dx = 0, dz = 0;
+  std::complex<double> chi0, chih, chihbar;
+  double theta_B = 0, lambda = 0;
+  int precision = BPM_PREC_FP64;
+  double x_front = 0.0, thickness = HUGE_VAL;
+  int split_order = 1, zassenhaus = 1;
+  std::vector<double> delta;
+  // derived (FP64)
+  double k0 = 0, h = 0;
+  std::vector<bpm::SliceConst> sc;
+  bpm::SliceConst* dev_sc = nullptr;
+  int device = -1;
+  bool frozen = false;
+  std::mutex mu;
+};

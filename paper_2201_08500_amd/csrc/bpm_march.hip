@@ -1,0 +1,651 @@
+// gfx950 kernels of the FFT beam-propagation z-march.
+//
+// One workgroup advances one frequency slice through all Nz split steps
+// (Eq. fov10, first-order splitting of Eq. fov4).  Both envelopes stay
+// on-chip for the whole march: thread t of T = Nx/R threads keeps the R
+// samples t + T*i (i = 0..R-1) of psi~_+ and of psi~_- in registers.  Each
+// FFT along x is a Stockham autosort transform: radix-Rp butterflies in
+// registers, one LDS exchange between passes (both envelopes exchanged under
+// a single barrier), natural-order output landing back in the same register
+// slots, so the propagator (a function of the bin K) and the coupling (a
+// function of x) are register-local and need no extra exchange.  HBM traffic
+// per slice-step is one row of the deformation table exp(i h u).
+//
+// There is no matrix-core work here: the step is FFT plus pointwise complex
+// arithmetic, bound by VALU and LDS throughput.
+
+#include <utility>
+
+#include "bpm_internal.h"
+
+namespace bpm {
+namespace {
+
+// ---------------------------------------------------------------- complex --
+
+template <class T>
+struct cx {
+  T x, y;
+};
+
+template <class T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <class T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+template <class T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <class T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// multiply by -i (forward transform) or +i (inverse transform)
+template <bool INV, class T>
+__device__ __forceinline__ cx<T> rot(cx<T> a) {
+  if constexpr (INV)
+    return {-a.y, a.x};
+  else
+    return {a.y, -a.x};
+}
+
+template <class D, class S>
+__device__ __forceinline__ cx<D> conv(cx<S> a) {
+  return {static_cast<D>(a.x), static_cast<D>(a.y)};
+}
+
+// ------------------------------------------------------- small DFT kernels --
+// Forward kernel exp(-2 pi i n k / R), inverse exp(+2 pi i n k / R); no
+// scaling.  Outputs are in natural order.
+
+constexpr double kCos16[16] = {
+    1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+    -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977,
+    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674};
+
+// a * W16^J with W16 = exp(-+2 pi i / 16)
+template <int J, bool INV, class T>
+__device__ __forceinline__ cx<T> tw16(cx<T> a) {
+  constexpr int j = J & 15;
+  if constexpr (j == 0) {
+    return a;
+  } else if constexpr (j == 4) {
+    return rot<INV>(a);
+  } else if constexpr (j == 8) {
+    return {-a.x, -a.y};
+  } else if constexpr (j == 12) {
+    return rot<!INV>(a);
+  } else {
+    constexpr double c = kCos16[j];
+    constexpr double s = kCos16[(j + 12) & 15];  // sin(2 pi j / 16)
+    const T wr = static_cast<T>(c);
+    const T wi = static_cast<T>(INV ? s : -s);
+    return {a.x * wr - a.y * wi, a.x * wi + a.y * wr};
+  }
+}
+
+template <bool INV, class T>
+__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  const cx<T> t = a;
+  a = t + b;
+  b = t - b;
+}
+
+template <bool INV, class T>
+__device__ __forceinline__ void dft4(cx<T>& x0, cx<T>& x1, cx<T>& x2,
+                                     cx<T>& x3) {
+  const cx<T> t0 = x0 + x2, t1 = x0 - x2, t2 = x1 + x3;
+  const cx<T> t3 = rot<INV>(x1 - x3);
+  x0 = t0 + t2;
+  x2 = t0 - t2;
+  x1 = t1 + t3;
+  x3 = t1 - t3;
+}
+
+template <int R, bool INV, class T>
+__device__ __forceinline__ void dft(cx<T> (&v)[R]) {
+  if constexpr (R == 2) {
+    dft2<INV>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    // even/odd split: X_k = E_k + W8^k O_k, X_{k+4} = E_k - W8^k O_k
+    dft4<INV>(v[0], v[2], v[4], v[6]);
+    dft4<INV>(v[1], v[3], v[5], v[7]);
+    const cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    const cx<T> o0 = v[1];
+    const cx<T> o1 = tw16<2, INV>(v[3]);
+    const cx<T> o2 = tw16<4, INV>(v[5]);
+    const cx<T> o3 = tw16<6, INV>(v[7]);
+    v[0] = e0 + o0;
+    v[4] = e0 - o0;
+    v[1] = e1 + o1;
+    v[5] = e1 - o1;
+    v[2] = e2 + o2;
+    v[6] = e2 - o2;
+    v[3] = e3 + o3;
+    v[7] = e3 - o3;
+  } else if constexpr (R == 16) {
+    // 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+    v[5] = tw16<1, INV>(v[5]);
+    v[6] = tw16<2, INV>(v[6]);
+    v[7] = tw16<3, INV>(v[7]);
+    v[9] = tw16<2, INV>(v[9]);
+    v[10] = tw16<4, INV>(v[10]);
+    v[11] = tw16<6, INV>(v[11]);
+    v[13] = tw16<3, INV>(v[13]);
+    v[14] = tw16<6, INV>(v[14]);
+    v[15] = tw16<9, INV>(v[15]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    cx<T> o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = o[i];
+  } else {
+    static_assert(R == 2, "unsupported radix");
+  }
+}
+
+// ------------------------------------------------------ double-double math --
+// Used once per slice and bin to form the propagator phase dz*kz, which is
+// ~2.5e4 rad at typical sizes: a plain FP64 evaluation would carry ~1e-12 rad
+// of error that every one of the Nz steps repeats.  Evaluated to ~1e-30
+// relative and reduced modulo 2 pi before the final FP64 rounding.
+
+struct dd {
+  double hi, lo;
+};
+
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ dd quick_two_sum(double a, double b) {
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  const double p = a * b;
+  return {p, __fma_rn(a, b, -p)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  const dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = quick_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return quick_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double b) {
+  dd p = two_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return quick_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ dd dd_div_d(dd a, double b) {
+  const double q1 = a.hi / b;
+  const dd p = two_prod(q1, b);
+  const double r = ((a.hi - p.hi) - p.lo) + a.lo;
+  return quick_two_sum(q1, r / b);
+}
+__device__ __forceinline__ dd dd_sqrt(dd a) {
+  const double s = sqrt(a.hi);
+  const dd s2 = two_prod(s, s);
+  const double r = (((a.hi - s2.hi) - s2.lo) + a.lo) / (2.0 * s);
+  return quick_two_sum(s, r);
+}
+
+#pragma clang fp contract(fast)
+
+// 2 pi as a double-double
+constexpr double kTwoPiHi = 6.283185307179586232;
+constexpr double kTwoPiLo = 2.4492935982947064e-16;
+
+// exp(i frac dz sqrt(k^2 - (K_m + band h/2)^2)) / Nx for signed bin m,
+// K_m = 2 pi m / (Nx dx); principal root (decay) for evanescent waves.
+__device__ cx<double> propagator(int m, int Nx, double dx, double k,
+                                 double h_half, double band, double len) {
+  const dd two_pi = {kTwoPiHi, kTwoPiLo};
+  const dd K = dd_div_d(dd_mul_d(two_pi, static_cast<double>(m)),
+                        static_cast<double>(Nx) * dx);
+  const dd kp = dd_add(K, dd{band * h_half, 0.0});
+  const dd kz2 = dd_add(two_prod(k, k), dd_neg(dd_mul(kp, kp)));
+  const double inv_n = 1.0 / static_cast<double>(Nx);
+  if (kz2.hi < 0.0) {
+    const double decay = len * sqrt(-kz2.hi);
+    return {exp(-decay) * inv_n, 0.0};
+  }
+  dd phi = dd_mul_d(dd_sqrt(kz2), len);
+  const double n = floor(phi.hi / kTwoPiHi);
+  phi = dd_add(phi, dd_neg(dd_mul_d(two_pi, n)));
+  if (phi.hi < 0.0) phi = dd_add(phi, two_pi);
+  if (phi.hi >= kTwoPiHi) phi = dd_add(phi, dd_neg(two_pi));
+  const double r = phi.hi + phi.lo;
+  double s, c;
+  sincos(r, &s, &c);
+  return {c * inv_n, s * inv_n};
+}
+
+// ---------------------------------------------------------------- barrier --
+// Workgroup barrier ordering LDS traffic only: global loads in flight (the
+// prefetched deformation row) are not drained by it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// -------------------------------------------------------------- precision --
+
+template <int PREC>
+struct Prec;
+template <>
+struct Prec<BPM_PREC_FP64> {
+  using CT = double;  // butterfly arithmetic
+  using ST = double;  // LDS, fields and deformation table
+};
+template <>
+struct Prec<BPM_PREC_FP32> {
+  using CT = float;
+  using ST = float;
+};
+template <>
+struct Prec<BPM_PREC_FP32S> {
+  using CT = double;
+  using ST = float;
+};
+
+template <class T>
+struct vec2;
+template <>
+struct vec2<float> {
+  using type = float2;
+};
+template <>
+struct vec2<double> {
+  using type = double2;
+};
+
+// ------------------------------------------------------------- the march --
+
+template <int PREC, int N, int R, int... RADS>
+struct March {
+  using CT = typename Prec<PREC>::CT;
+  using ST = typename Prec<PREC>::ST;
+  using SV = typename vec2<ST>::type;
+  static constexpr int T = N / R;             // threads per slice
+  static constexpr int NP = sizeof...(RADS);  // Stockham passes per FFT
+  static constexpr int rad[NP] = {RADS...};
+  static constexpr int prod_rad() {
+    int p = 1;
+    for (int i = 0; i < NP; ++i) p *= rad[i];
+    return p;
+  }
+  static_assert(prod_rad() == N, "radices must multiply to N");
+  static constexpr int ns(int p) {  // sub-transform length before pass p
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= rad[i];
+    return s;
+  }
+  static constexpr int tw_off(int p) {  // first twiddle of pass p
+    int o = 0;
+    for (int i = 1; i < p; ++i) o += (R / rad[i]) * (rad[i] - 1);
+    return o;
+  }
+  static constexpr int NTW = tw_off(NP) > 0 ? tw_off(NP) : 1;
+  // Two LDS buffers (one barrier per exchange) when they fit in 160 KiB.
+  static constexpr size_t kEnvBytes = size_t(N) * sizeof(SV);
+  static constexpr int NBUF = (4 * kEnvBytes <= 160 * 1024) ? 2 : 1;
+  static constexpr size_t kLdsBytes = NBUF * 2 * kEnvBytes;
+
+  using Reg = cx<CT>[R];
+
+  __device__ static void store(SV* lds, int idx, cx<CT> v) {
+    SV s;
+    s.x = static_cast<ST>(v.x);
+    s.y = static_cast<ST>(v.y);
+    lds[idx] = s;
+  }
+  __device__ static cx<CT> load(const SV* lds, int idx) {
+    const SV s = lds[idx];
+    return {static_cast<CT>(s.x), static_cast<CT>(s.y)};
+  }
+
+  // Stockham pass P (radix rad[P], sub-length Ns): butterfly jb reads
+  // x[jb + r N/Rp], applies twiddles W_{Ns Rp}^{r (jb mod Ns)}, transforms,
+  // and writes x[(jb/Ns) Ns Rp + jb mod Ns + r Ns].  Thread t owns
+  // butterflies jb = t + s T and, on input, register slot s + r (R/Rp).
+  template <int P, bool INV>
+  __device__ static void pass(Reg& a, Reg& b, const cx<CT> (&tw)[NTW],
+                              SV* lds, int t, int& xbuf) {
+    constexpr int Rp = rad[P];
+    constexpr int Ns = ns(P);
+    constexpr int G = R / Rp;
+    constexpr bool last = (P == NP - 1);
+    SV* la = lds + xbuf * 2 * N;
+    SV* lb = la + N;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      cx<CT> va[Rp], vb[Rp];
+#pragma unroll
+      for (int r = 0; r < Rp; ++r) {
+        va[r] = a[s + r * G];
+        vb[r] = b[s + r * G];
+      }
+      if constexpr (P > 0) {
+#pragma unroll
+        for (int r = 1; r < Rp; ++r) {
+          const cx<CT> w = tw[tw_off(P) + s * (Rp - 1) + (r - 1)];
+          if constexpr (INV) {
+            va[r] = cmulc(va[r], w);
+            vb[r] = cmulc(vb[r], w);
+          } else {
+            va[r] = cmul(va[r], w);
+            vb[r] = cmul(vb[r], w);
+          }
+        }
+      }
+      dft<Rp, INV>(va);
+      dft<Rp, INV>(vb);
+      if constexpr (last) {
+#pragma unroll
+        for (int r = 0; r < Rp; ++r) {
+          a[s + r * G] = va[r];
+          b[s + r * G] = vb[r];
+        }
+      } else {
+        const int jb = t + s * T;
+        const int base = (jb / Ns) * Ns * Rp + (jb % Ns);
+#pragma unroll
+        for (int r = 0; r < Rp; ++r) {
+          store(la, base + r * Ns, va[r]);
+          store(lb, base + r * Ns, vb[r]);
+        }
+      }
+    }
+    if constexpr (!last) {
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        a[i] = load(la, t + T * i);
+        b[i] = load(lb, t + T * i);
+      }
+      if constexpr (NBUF == 1) {
+        lds_barrier();
+      } else {
+        xbuf ^= 1;
+      }
+    }
+  }
+
+  template <bool INV, int... P>
+  __device__ static void fft_impl(Reg& a, Reg& b, const cx<CT> (&tw)[NTW],
+                                  SV* lds, int t, int& xbuf,
+                                  std::integer_sequence<int, P...>) {
+    (pass<P, INV>(a, b, tw, lds, t, xbuf), ...);
+  }
+  template <bool INV>
+  __device__ static void fft(Reg& a, Reg& b, const cx<CT> (&tw)[NTW], SV* lds,
+                             int t, int& xbuf) {
+    fft_impl<INV>(a, b, tw, lds, t, xbuf, std::make_integer_sequence<int, NP>{});
+  }
+
+  // Twiddles W_{Ns Rp}^{r (jb mod Ns)} of every pass after the first.
+  template <int P>
+  __device__ static void twiddles_pass(cx<CT> (&tw)[NTW], int t) {
+    if constexpr (P > 0) {
+      constexpr int Rp = rad[P];
+      constexpr int Ns = ns(P);
+      constexpr int G = R / Rp;
+#pragma unroll
+      for (int s = 0; s < G; ++s) {
+        const int jb = t + s * T;
+        const int j = jb % Ns;
+#pragma unroll
+        for (int r = 1; r < Rp; ++r) {
+          // exp(-2 pi i r j / (Ns Rp)); sincospi keeps the argument exact
+          double sn, cs;
+          sincospi(-2.0 * double(r * j) / double(Ns * Rp), &sn, &cs);
+          tw[tw_off(P) + s * (Rp - 1) + (r - 1)] = {static_cast<CT>(cs),
+                                                    static_cast<CT>(sn)};
+        }
+      }
+    }
+  }
+  template <int... P>
+  __device__ static void twiddles_impl(cx<CT> (&tw)[NTW], int t,
+                                       std::integer_sequence<int, P...>) {
+    (twiddles_pass<P>(tw, t), ...);
+  }
+
+  // Whole march of one slice by threads t = 0..T-1 of the calling group.
+  template <bool DEFORMED>
+  __device__ static void run(const MarchParams& p, int slice, int t, SV* lds) {
+    const SliceConst& sc = p.sc[slice];
+    const SV* in = static_cast<const SV*>(p.E0_in) + size_t(slice) * N;
+    SV* out_a = static_cast<SV*>(p.E0_out) + size_t(slice) * N;
+    SV* out_b = static_cast<SV*>(p.Eh_out) + size_t(slice) * N;
+    const SV* table = static_cast<const SV*>(p.table);
+
+    cx<CT> tw[NTW];
+    twiddles_impl(tw, t, std::make_integer_sequence<int, NP>{});
+
+    // Propagators of the bins this thread owns after a forward transform
+    // (bin t + T i, signed), 1/Nx of the inverse transform folded in.
+    cx<double> Pp[R], Pm[R];
+    bool inside[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int m = t + T * i;
+      const int ms = m < N / 2 ? m : m - N;
+      Pp[i] = propagator(ms, N, p.dx, sc.k, p.h_half, +1.0, p.dz);
+      Pm[i] = propagator(ms, N, p.dx, sc.k, p.h_half, -1.0, p.dz);
+      const double x = static_cast<double>(m - N / 2) * p.dx;
+      inside[i] = (x >= p.x_front) && (x < p.x_end);
+    }
+    const cx<double> d0 = {sc.d[0][0], sc.d[0][1]};
+    const cx<double> dp1 = {sc.d[0][2], sc.d[0][3]};
+    const cx<double> dm1 = {sc.d[0][4], sc.d[0][5]};
+
+    Reg a, b;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const SV v = in[t + T * i];
+      a[i] = {static_cast<CT>(v.x), static_cast<CT>(v.y)};
+      b[i] = {CT(0), CT(0)};
+    }
+
+    int xbuf = 0;
+    SV e[R];
+    if constexpr (DEFORMED) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) e[i] = table[t + T * i];
+    }
+    for (int n = 0; n < p.Nz; ++n) {
+      // Row n of exp(i h u) is in e[]; fetch row n+1 while this step runs.
+      SV e_next[R];
+      if constexpr (DEFORMED) {
+        const int nn = (n + 1 < p.Nz) ? n + 1 : n;
+        const SV* row = table + size_t(nn) * N;
+#pragma unroll
+        for (int i = 0; i < R; ++i) e_next[i] = row[t + T * i];
+      }
+
+      fft<false>(a, b, tw, lds, t, xbuf);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        a[i] = conv<CT>(cmul(conv<double>(a[i]), Pp[i]));
+        b[i] = conv<CT>(cmul(conv<double>(b[i]), Pm[i]));
+      }
+      fft<true>(a, b, tw, lds, t, xbuf);
+
+      // Coupling (Eq. fov10) in FP64 inside the slab.
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const cx<double> A = conv<double>(a[i]);
+        const cx<double> B = conv<double>(b[i]);
+        cx<double> na, nb;
+        if constexpr (DEFORMED) {
+          const cx<double> ee = {static_cast<double>(e[i].x),
+                                 static_cast<double>(e[i].y)};
+          na = cmul(d0, A) + cmul(dp1, cmul(ee, B));
+          nb = cmul(d0, B) + cmul(dm1, cmulc(A, ee));
+        } else {
+          na = cmul(d0, A) + cmul(dp1, B);
+          nb = cmul(d0, B) + cmul(dm1, A);
+        }
+        if (inside[i]) {
+          a[i] = conv<CT>(na);
+          b[i] = conv<CT>(nb);
+        }
+      }
+      if constexpr (DEFORMED) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) e[i] = e_next[i];
+      }
+    }
+
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      SV va, vb;
+      va.x = static_cast<ST>(a[i].x);
+      va.y = static_cast<ST>(a[i].y);
+      vb.x = static_cast<ST>(b[i].x);
+      vb.y = static_cast<ST>(b[i].y);
+      out_a[t + T * i] = va;
+      out_b[t + T * i] = vb;
+    }
+  }
+};
+
+template <class M, bool DEFORMED>
+__global__ void __launch_bounds__(M::T) march_kernel(MarchParams p) {
+  __shared__ typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
+  M::template run<DEFORMED>(p, blockIdx.x, threadIdx.x, lds);
+}
+
+// exp(i h u): FP64 sincos for FP64 tables; for FP32 tables h*u is reduced
+// modulo 2 pi in FP64 first, then rounded to FP32 for the sincos.  One
+// thread per cell, grid-stride.
+template <class ST>
+__global__ void deform_kernel(const double* __restrict__ u, size_t n, double h,
+                              typename vec2<ST>::type* __restrict__ out) {
+  const double two_pi = kTwoPiHi;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    typename vec2<ST>::type v;
+    if constexpr (sizeof(ST) == 4) {
+      double r = fmod(h * u[i], two_pi);
+      if (r < 0.0) r += two_pi;
+      float s, c;
+      sincosf(static_cast<float>(r), &s, &c);
+      v.x = c;
+      v.y = s;
+    } else {
+      double s, c;
+      sincos(h * u[i], &s, &c);
+      v.x = c;
+      v.y = s;
+    }
+    out[i] = v;
+  }
+}
+
+// ------------------------------------------------------------ dispatching --
+
+template <int PREC, int N>
+struct Choice;
+// Radix schedules: R samples per thread per envelope; passes multiply to N.
+template <int PREC>
+struct Choice<PREC, 256> {
+  using type = March<PREC, 256, 4, 4, 4, 4, 4>;
+};
+template <int PREC>
+struct Choice<PREC, 512> {
+  using type = March<PREC, 512, 8, 8, 8, 8>;
+};
+template <int PREC>
+struct Choice<PREC, 1024> {
+  using type = March<PREC, 1024, 8, 8, 8, 4, 4>;
+};
+template <int PREC>
+struct Choice<PREC, 2048> {
+  using type = March<PREC, 2048, 8, 8, 8, 8, 4>;
+};
+template <int PREC>
+struct Choice<PREC, 4096> {
+  using type = March<PREC, 4096, 8, 8, 8, 8, 8>;
+};
+
+template <int PREC, int N>
+int launch_n(int Nomega, const MarchParams& p, hipStream_t stream) {
+  using M = typename Choice<PREC, N>::type;
+  if (p.table)
+    hipLaunchKernelGGL((march_kernel<M, true>), dim3(Nomega), dim3(M::T), 0,
+                       stream, p);
+  else
+    hipLaunchKernelGGL((march_kernel<M, false>), dim3(Nomega), dim3(M::T), 0,
+                       stream, p);
+  return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
+}
+
+template <int PREC>
+int launch_prec(int Nx, int Nomega, const MarchParams& p, hipStream_t s) {
+  switch (Nx) {
+    case 256: return launch_n<PREC, 256>(Nomega, p, s);
+    case 512: return launch_n<PREC, 512>(Nomega, p, s);
+    case 1024: return launch_n<PREC, 1024>(Nomega, p, s);
+    case 2048: return launch_n<PREC, 2048>(Nomega, p, s);
+    case 4096: return launch_n<PREC, 4096>(Nomega, p, s);
+    default: return BPM_EUNSUPPORTED;
+  }
+}
+
+}  // namespace
+
+int launch_march(int prec, int Nx, int Nomega, const MarchParams& p,
+                 hipStream_t stream) {
+  switch (prec) {
+    case BPM_PREC_FP64: return launch_prec<BPM_PREC_FP64>(Nx, Nomega, p, stream);
+    case BPM_PREC_FP32: return launch_prec<BPM_PREC_FP32>(Nx, Nomega, p, stream);
+    case BPM_PREC_FP32S: return launch_prec<BPM_PREC_FP32S>(Nx, Nomega, p, stream);
+    default: return BPM_EUNSUPPORTED;
+  }
+}
+
+int launch_deform(int prec, int Nx, int Nz, double h, const double* u,
+                  void* table, hipStream_t stream) {
+  const size_t n = size_t(Nx) * size_t(Nz);
+  const int block = 256;
+  const size_t want = (n + block - 1) / block;
+  const int grid = static_cast<int>(want < 8192 ? want : 8192);
+  if (prec == BPM_PREC_FP64)
+    hipLaunchKernelGGL(deform_kernel<double>, dim3(grid), dim3(block), 0,
+                       stream, u, n, h, static_cast<double2*>(table));
+  else
+    hipLaunchKernelGGL(deform_kernel<float>, dim3(grid), dim3(block), 0,
+                       stream, u, n, h, static_cast<float2*>(table));
+  return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
+}
+
+}  // namespace bpm

@@ -138,9 +138,10 @@ def bent_displacement(Nx, dx, Nz, R, x_front=0.0) -> np.ndarray:
     return np.broadcast_to(row, (Nz, Nx)).copy()
 
 
-def bump_factors(Nx, dx, Nz, dz, amp, sigma, x_front=0.0):
-    """Separable Gaussian bump amp*exp(-(x^2 + (z - zc)^2)/(2 sigma^2)) with
-    zc at mid-depth: returns (gz, gx) with bump[n, j] = (amp * gz[n]) * gx[j]."""
+def bump_factors(Nx, dx, Nz, dz, sigma, x_front=0.0):
+    """Separable Gaussian bump exp(-(x^2 + (z - zc)^2)/(2 sigma^2)) with zc at
+    mid-depth: returns (gz, gx); a bump of amplitude A is
+    bump[n, j] = (A * gz[n]) * gx[j]."""
     xs = x_grid(Nx, dx) - x_front
     z = np.arange(Nz, dtype=np.float64) * dz
     zc = Nz * dz / 2.0
@@ -170,13 +171,15 @@ def small(Nx=256, Nz=40, Nomega=3, seed=0, deformed=True, dx=DX, dz=DZ,
     E0 = incident_envelope(Nx, dx, LAMBDA, THETA_B, delta, THETA_B, amp, x0, w0)
     u = None
     if deformed:
-        u = bent_displacement(Nx, dx, Nz, rng.uniform(1.0, 100.0), x_front)
-        gz, gx = bump_factors(Nx, dx, Nz, dz, rng.uniform(0.2e-10, 1e-10),
-                              0.2 * L, x_front)
-        u += (1e-10 * gz)[:, None] * gx[None, :]
+        xg = x_grid(Nx, dx)
+        x_ref = min(max(x_front, xg[0]), xg[-1])   # bend measured from the slab face
+        u = bent_displacement(Nx, dx, Nz, rng.uniform(1.0, 100.0), x_ref)
+        amp = rng.uniform(0.2e-10, 1e-10)
+        gz, gx = bump_factors(Nx, dx, Nz, dz, 0.2 * L, x_ref)
+        u += (amp * gz)[:, None] * gx[None, :]
         strain = rng.normal(0.0, 1e-7, size=(Nz, Nx))
         cs = np.cumsum(strain, axis=1)
-        j0 = int(np.searchsorted(x_grid(Nx, dx), x_front))
+        j0 = int(np.searchsorted(xg, x_ref))
         u += dx * (cs - cs[:, min(j0, Nx - 1)][:, None])
     return Workload(f"small-{Nx}x{Nz}x{Nomega}-s{seed}", Nx, dx, dz, Nz, CHI0,
                     CHIH, CHIH, THETA_B, LAMBDA, Nomega, delta, E0, u,
@@ -217,7 +220,7 @@ def c3_thermal_bump(seed: int = 3, Nomega: int = 1024) -> Workload:
     delta = detuning_grid(Nomega, eps)
     amp = pulse_amplitudes(delta, LAMBDA, 10e-15, rng)
     E0 = incident_envelope(Nx, DX, LAMBDA, THETA_B, delta, THETA_B, amp)
-    gz, gx = bump_factors(Nx, DX, Nz, DZ, 1e-10, 100e-6)
+    gz, gx = bump_factors(Nx, DX, Nz, DZ, 100e-6)
     u = (1e-10 * gz)[:, None] * gx[None, :]
     strain = rng.normal(0.0, 1e-7, size=(Nz, Nx))
     cs = np.cumsum(strain, axis=1)
@@ -263,7 +266,7 @@ def c4_problem(spec: dict, with_u: bool = True) -> Workload:
     E0 = incident_envelope(Nx, DX, LAMBDA, THETA_B, delta, THETA_B, amp)
     xs = x_grid(Nx, DX)
     row = xs * xs / (2.0 * spec["R"])
-    gz, gx = bump_factors(Nx, DX, Nz, DZ, spec["bump"], 100e-6)
+    gz, gx = bump_factors(Nx, DX, Nz, DZ, 100e-6)
     u = None
     if with_u:
         u = row[None, :] + (spec["bump"] * gz)[:, None] * gx[None, :]
