@@ -73,8 +73,8 @@ def cpu_baseline(slices_per_core: int = 12, cores: int | None = None) -> dict:
     ncpu = os.cpu_count() or 1
     cores = min(cores or ncpu, 16, ncpu)
     start = time.time() + 15.0 + 0.5 * cores   # leaves time for input setup
-    jobs = [(list(range(c * slices_per_core, (c + 1) * slices_per_core)), 2, start)
-            for c in range(cores)]
+    jobs = [([(c * slices_per_core + i) % 256 for i in range(slices_per_core)], 2,
+             start) for c in range(cores)]
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
         res = pool.map(_cpu_worker, jobs)
@@ -135,6 +135,100 @@ def run_variant(w, prec, steps, warmup, E0_np, u_t):
                 deform_ms=float(np.mean(deform_ms)), out=out)
 
 
+def bench_batch(args):
+    """Uneven batch: 512 problems (seeded sizes: Nx 256..4096, Nz 500..8000,
+    Nomega 1..256), one prepared batch captured in a hipGraph and replayed.
+    Reports cell-updates/s of the replay and of running the same jobs one
+    after another on the stream."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2201_08500_amd import Batch, Job, Plan
+    from workloads.metrics import report
+
+    torch.cuda.set_device(0)
+    specs = W.c4_problem_specs(args.batch_problems, seed=4)
+    jobs, works = [], []
+    cells = 0
+    for s in specs:
+        w = W.c4_problem(s, with_u=False)
+        row, gz, gx, amp = w.meta["u_factors"]
+        p = Plan.from_workload(w, precision=args.headline)
+        E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
+        row_t, gz_t, gx_t = (torch.from_numpy(v).cuda() for v in (row, gz, gx))
+        # same operation order as the numpy generator: row + (amp gz) gx
+        u = (row_t[None, :] + (amp * gz_t)[:, None] * gx_t[None, :]).contiguous()
+        jobs.append(Job(p, E0, u))
+        works.append(w)
+        cells += w.cell_updates
+    print(f"[bench] batch: {len(jobs)} problems, {cells:.3e} cell-updates",
+          file=sys.stderr, flush=True)
+    t_prep = time.perf_counter()
+    batch = Batch(jobs)
+    t_prep = time.perf_counter() - t_prep
+    batch.launch()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            batch.launch()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    seq = None
+    if args.batch_compare:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        outs = [(torch.empty_like(j.E0_out), torch.empty_like(j.Eh_out)) for j in jobs]
+        e0.record()
+        for j, (oa, ob) in zip(jobs, outs):
+            j.plan.propagate(j.E0_in, j.u, oa, ob, workspace=j.workspace)
+        e1.record()
+        torch.cuda.synchronize()
+        seq = e0.elapsed_time(e1) / 1e3
+        same = all(torch.equal(oa, j.E0_out) and torch.equal(ob, j.Eh_out)
+                   for j, (oa, ob) in zip(jobs, outs))
+        del outs
+    # oracle spot check: two slices of the smallest problem
+    import oracle as O
+    i = min(range(len(works)), key=lambda k: works[k].Nx * works[k].Nz)
+    wsub = W.c4_problem(specs[i]).subset(sorted({0, works[i].Nomega // 2}))
+    sl = sorted({0, works[i].Nomega // 2})
+    E32 = wsub.E0_in.astype(np.complex64).astype(np.complex128)
+    ao, bo = O.march(O.Problem.from_workload(wsub), E32, wsub.u)
+    rep = report(jobs[i].E0_out.cpu().numpy()[sl].astype(np.complex128),
+                 jobs[i].Eh_out.cpu().numpy()[sl].astype(np.complex128), ao, bo)
+    t = float(np.median(times))
+    line = {
+        "metric": METRIC, "value": cells / t, "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32s": "f64", "fp32": "f32", "fp64": "f64"}[args.headline],
+        "data": "synthetic",
+        "config": {"workload": f"uneven-batch-{len(jobs)}-problems",
+                   "precision": args.headline, "cell_updates": cells,
+                   "graph": "one hipGraph replay per step"},
+        "batch": dict(batch.info(), prepare_s=t_prep,
+                      replay_s=[float(x) for x in times],
+                      sequential_s=seq,
+                      sequential_cell_updates_per_s=(cells / seq) if seq else None,
+                      sequential_bitwise_equal=(same if seq else None),
+                      oracle_spot_check=dict(problem=works[i].name, slices=sl, **rep)),
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,7 +240,15 @@ def main():
     ap.add_argument("--oracle-slices", default="120,128,136",
                     help="slices recomputed by the oracle for the error report")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slices-per-core", type=int, default=12)
+    ap.add_argument("--cpu-slices-per-core", type=int, default=96)
+    ap.add_argument("--workload", default="bent-crystal",
+                    choices=["bent-crystal", "batch"])
+    ap.add_argument("--batch-problems", type=int, default=512)
+    ap.add_argument("--batch-compare", action="store_true",
+                    help="also time the same jobs run one after another")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this size, the "
+                         "reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -155,6 +257,9 @@ def main():
               "would each run this same single-GPU launch on Nomega/N slices.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     import numpy as np
     import torch
@@ -169,6 +274,13 @@ def main():
     if args.headline not in variants:
         variants.insert(0, args.headline)
 
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     results = {}
     for prec in variants:
         print(f"[bench] {prec}: warmup {args.warmup}, timing {args.steps} steps",
@@ -178,21 +290,24 @@ def main():
     # precision report: every variant against the FP64 GPU run (all slices)
     # and against the oracle on a few slices
     sl = [int(s) for s in args.oracle_slices.split(",") if s]
-    import oracle as O
-    ws = w.subset(sl)
-    ref = O.march(O.Problem.from_workload(ws), ws.E0_in, ws.u)
-    ref32 = None
+    ref = ref32 = None
+    if sl:
+        import oracle as O
+        ws = w.subset(sl)
+        ref = O.march(O.Problem.from_workload(ws), ws.E0_in, ws.u)
     prec_report = {}
     for prec, r in results.items():
         a, b = r["out"]
         entry = {}
         if prec == "fp64":
-            entry["vs_oracle"] = report(a[sl], b[sl], *ref)
+            if sl:
+                entry["vs_oracle"] = report(a[sl], b[sl], *ref)
         else:
-            if ref32 is None:
+            if sl and ref32 is None:
                 E32 = ws.E0_in.astype(np.complex64).astype(np.complex128)
                 ref32 = O.march(O.Problem.from_workload(ws), E32, ws.u)
-            entry["vs_oracle"] = report(a[sl], b[sl], *ref32)
+            if sl:
+                entry["vs_oracle"] = report(a[sl], b[sl], *ref32)
             if "fp64" in results:
                 entry["vs_fp64_gpu_all_slices"] = report(a, b, *results["fp64"]["out"])
         march_s = r["march_ms"] / 1e3

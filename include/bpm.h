@@ -125,6 +125,46 @@ int bpm_deformation_table(const bpm_plan* plan, const double* u_field,
 int bpm_march(const bpm_plan* plan, const void* E0_in, const void* table,
               void* E0_out, void* Eh_out, void* stream);
 
+/* One entry of a batch: a plan and its buffers (workspace as in
+ * bpm_propagate_ws, required when u_field is not NULL).  Jobs must not share
+ * output buffers or workspaces. */
+typedef struct {
+  const bpm_plan* plan;
+  const void* E0_in;
+  const double* u_field;
+  void* E0_out;
+  void* Eh_out;
+  void* workspace;
+} bpm_job;
+
+typedef struct bpm_batch bpm_batch;
+
+/* Prepare many independent problems (any mix of sizes and precisions, the
+ * data-parallel axis of Eq. tdp extended across problems): freezes the
+ * plans, splits every job into its frequency slices, groups the slices by
+ * (precision, Nx) and assigns each group's slices, longest march first, to
+ * the work groups that are resident at once on the device.  Allocates the
+ * device work lists (synchronous).  NULL on error. */
+bpm_batch* bpm_batch_create(const bpm_job* jobs, int njobs);
+
+/* Enqueue a prepared batch on the stream: one deformation pre-pass per
+ * deformed job, then one persistent launch per (precision, Nx) group.
+ * Kernel launches only -- no allocation, memset or synchronisation -- so
+ * the call may be captured in a hipGraph and replayed.  Every slice runs the
+ * same code as bpm_propagate_ws, so results are bitwise identical to running
+ * each job alone. */
+int bpm_batch_launch(const bpm_batch* batch, void* stream);
+
+/* Diagnostics: persistent launches, slices and work groups of a batch. */
+int bpm_batch_info(const bpm_batch* batch, int* n_launches, int* n_slices,
+                   int* n_workgroups);
+
+void bpm_batch_destroy(bpm_batch* batch);
+
+/* One-shot batch: create (work lists allocated stream-ordered), launch and
+ * release the work lists on the stream. */
+int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream);
+
 void bpm_plan_destroy(bpm_plan* plan);
 
 /* Message for the last error on the calling thread ("" if none). */

@@ -6,8 +6,11 @@ include/bpm.h); this package is its thin Python binding.
 """
 
 from ._native import (  # noqa: F401
+    Batch,
     BpmError,
+    Job,
     Plan,
+    propagate_batch,
     PRECISION,
     LIB_PATH,
     lib,

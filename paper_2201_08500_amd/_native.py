@@ -31,6 +31,12 @@ class bpm_complex(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
 
 
+class bpm_job(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("E0_in", ctypes.c_void_p),
+                ("u_field", ctypes.c_void_p), ("E0_out", ctypes.c_void_p),
+                ("Eh_out", ctypes.c_void_p), ("workspace", ctypes.c_void_p)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -61,6 +67,14 @@ _SIGNATURES = [
     ("bpm_march", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_void_p, ctypes.c_void_p]),
+    ("bpm_batch_create", ctypes.c_void_p, [ctypes.POINTER(bpm_job), ctypes.c_int]),
+    ("bpm_batch_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("bpm_batch_info", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+      ctypes.POINTER(ctypes.c_int)]),
+    ("bpm_batch_destroy", None, [ctypes.c_void_p]),
+    ("bpm_propagate_batch", ctypes.c_int,
+     [ctypes.POINTER(bpm_job), ctypes.c_int, ctypes.c_void_p]),
     ("bpm_plan_destroy", None, [ctypes.c_void_p]),
     ("bpm_last_error", ctypes.c_char_p, []),
 ]
@@ -231,3 +245,76 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Job:
+    """One batch entry: a Plan and its device buffers (outputs allocated if
+    not given; a workspace is allocated for a deformed job if not given)."""
+
+    def __init__(self, plan, E0_in, u=None, E0_out=None, Eh_out=None,
+                 workspace=None):
+        import torch
+        plan._check_field(E0_in, "E0_in")
+        self.plan, self.E0_in, self.u = plan, E0_in, u
+        self.E0_out = torch.empty_like(E0_in) if E0_out is None else E0_out
+        self.Eh_out = torch.empty_like(E0_in) if Eh_out is None else Eh_out
+        plan._check_field(self.E0_out, "E0_out")
+        plan._check_field(self.Eh_out, "Eh_out")
+        if u is not None:
+            if not (u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
+                    and tuple(u.shape) == (plan.Nz, plan.Nx)):
+                raise ValueError("u must be a contiguous CUDA float64 (Nz, Nx) tensor")
+            if workspace is None:
+                workspace = torch.empty(plan.workspace_bytes(), dtype=torch.uint8,
+                                        device=E0_in.device)
+        self.workspace = workspace
+
+    def as_struct(self) -> bpm_job:
+        return bpm_job(self.plan.handle, self.E0_in.data_ptr(),
+                       None if self.u is None else self.u.data_ptr(),
+                       self.E0_out.data_ptr(), self.Eh_out.data_ptr(),
+                       None if self.workspace is None else self.workspace.data_ptr())
+
+
+def _job_array(jobs):
+    arr = (bpm_job * len(jobs))(*[j.as_struct() for j in jobs])
+    return arr
+
+
+class Batch:
+    """bpm_batch: prepared once, launched (or graph-captured) many times."""
+
+    def __init__(self, jobs):
+        self.jobs = list(jobs)           # keeps plans and buffers alive
+        h = lib().bpm_batch_create(_job_array(self.jobs), len(self.jobs))
+        if not h:
+            raise BpmError(BPM_EINVAL, last_error())
+        self._h = ctypes.c_void_p(h)
+
+    def launch(self, stream=None):
+        _check(lib().bpm_batch_launch(self._h, _stream_handle(stream)))
+
+    def info(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().bpm_batch_info(self._h, ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)))
+        return dict(launches=a.value, slices=b.value, workgroups=c.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.bpm_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def propagate_batch(jobs, stream=None):
+    """bpm_propagate_batch over Job objects (asynchronous on the stream)."""
+    jobs = list(jobs)
+    _check(lib().bpm_propagate_batch(_job_array(jobs), len(jobs),
+                                     _stream_handle(stream)))
+    return jobs

@@ -6,8 +6,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <limits>
+#include <map>
+#include <queue>
 #include <string>
+#include <utility>
 
 #include "bpm_internal.h"
 
@@ -162,6 +166,191 @@ bpm::MarchParams march_params(const bpm_plan* p, const void* E0_in,
   m.x_front = p->x_front;
   m.x_end = p->x_front + p->thickness;
   return m;
+}
+
+struct DeformJob {
+  int prec, Nx, Nz;
+  double h;
+  const double* u;
+  void* table;
+};
+
+struct BatchGroup {
+  int prec, Nx;
+  int n_groups;
+  int n_items;
+  bpm::BatchItem* d_items;
+  int* d_offsets;
+};
+
+}  // namespace
+
+struct bpm_batch {
+  std::vector<DeformJob> deforms;
+  std::vector<BatchGroup> groups;
+  void* d_mem = nullptr;        // one device allocation for all work lists
+  bool stream_ordered = false;  // allocated with hipMallocAsync
+};
+
+namespace {
+
+int validate_job(const bpm_job& j, int idx) {
+  const std::string at = "job " + std::to_string(idx) + ": ";
+  if (!j.plan) return fail(BPM_EINVAL, at + "plan is NULL");
+  if (!j.E0_in || !j.E0_out || !j.Eh_out)
+    return fail(BPM_EINVAL, at + "E0_in, E0_out and Eh_out must be non-NULL");
+  if (j.E0_in == j.E0_out || j.E0_in == j.Eh_out || j.E0_out == j.Eh_out)
+    return fail(BPM_EINVAL, at + "output buffers must not alias each other or E0_in");
+  if (j.u_field && !j.workspace)
+    return fail(BPM_EINVAL, at + "a deformed job needs a workspace");
+  return BPM_OK;
+}
+
+// Build a batch; with a non-null stream the device work lists are
+// allocated stream-ordered on it.
+int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
+                bool stream_ordered, bpm_batch** out) {
+  *out = nullptr;
+  if (!jobs || njobs < 1) return fail(BPM_EINVAL, "jobs must be a non-empty array");
+  for (int i = 0; i < njobs; ++i) {
+    int rc = validate_job(jobs[i], i);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < njobs; ++i) {
+    int rc = freeze(const_cast<bpm_plan*>(jobs[i].plan));
+    if (rc) return fail(rc, "job " + std::to_string(i) + ": " + g_error);
+  }
+  int dev = 0, n_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+
+  auto* b = new bpm_batch();
+  std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> by_variant;
+  for (int i = 0; i < njobs; ++i) {
+    const bpm_plan* p = jobs[i].plan;
+    if (jobs[i].u_field)
+      b->deforms.push_back({p->precision, p->Nx, p->Nz, p->h, jobs[i].u_field,
+                            jobs[i].workspace});
+    for (int w = 0; w < p->Nomega; ++w)
+      by_variant[{p->precision, p->Nx}].push_back({i, w});
+  }
+  // Host work lists: per variant, items ordered by group, longest first.
+  struct HostGroup {
+    int prec, Nx, n_groups;
+    std::vector<bpm::BatchItem> items;
+    std::vector<int> offsets;
+  };
+  std::vector<HostGroup> host;
+  for (auto& kv : by_variant) {
+    const int prec = kv.first.first, Nx = kv.first.second;
+    auto& slices = kv.second;
+    int per_cu = 0, threads = 0;
+    int rc = bpm::march_occupancy(prec, Nx, &per_cu, &threads);
+    if (rc) {
+      delete b;
+      return fail(rc, "occupancy query failed for Nx " + std::to_string(Nx));
+    }
+    const int resident = std::max(1, per_cu) * std::max(1, n_cu);
+    const int G = std::min<int>(resident, static_cast<int>(slices.size()));
+    // longest march first, then LPT: each slice to the least-loaded group
+    std::stable_sort(slices.begin(), slices.end(), [&](auto& x, auto& y) {
+      return jobs[x.first].plan->Nz > jobs[y.first].plan->Nz;
+    });
+    using Load = std::pair<long long, int>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int g = 0; g < G; ++g) heap.push({0, g});
+    std::vector<std::vector<std::pair<int, int>>> per_group(G);
+    for (auto& s : slices) {
+      Load l = heap.top();
+      heap.pop();
+      per_group[l.second].push_back(s);
+      l.first += jobs[s.first].plan->Nz;
+      heap.push(l);
+    }
+    HostGroup hg{prec, Nx, G, {}, {0}};
+    for (int g = 0; g < G; ++g) {
+      for (auto& s : per_group[g]) {
+        const bpm_job& j = jobs[s.first];
+        bpm::BatchItem it{};
+        it.p = march_params(j.plan, j.E0_in, j.u_field ? j.workspace : nullptr,
+                            j.E0_out, j.Eh_out);
+        it.slice = s.second;
+        hg.items.push_back(it);
+      }
+      hg.offsets.push_back(static_cast<int>(hg.items.size()));
+    }
+    host.push_back(std::move(hg));
+  }
+  // One device allocation: [items of every group][offsets of every group].
+  size_t bytes = 0;
+  std::vector<size_t> item_off, offs_off;
+  for (auto& hg : host) {
+    item_off.push_back(bytes);
+    bytes += hg.items.size() * sizeof(bpm::BatchItem);
+  }
+  for (auto& hg : host) {
+    bytes = (bytes + 255) & ~size_t(255);
+    offs_off.push_back(bytes);
+    bytes += hg.offsets.size() * sizeof(int);
+  }
+  e = stream_ordered ? hipMallocAsync(&b->d_mem, bytes, alloc_stream)
+                     : hipMalloc(&b->d_mem, bytes);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(BPM_ENOMEM, std::string("batch work lists: ") + hipGetErrorString(e));
+  }
+  b->stream_ordered = stream_ordered;
+  auto* staging = new std::vector<char>(bytes);
+  for (size_t g = 0; g < host.size(); ++g) {
+    std::memcpy(staging->data() + item_off[g], host[g].items.data(),
+                host[g].items.size() * sizeof(bpm::BatchItem));
+    std::memcpy(staging->data() + offs_off[g], host[g].offsets.data(),
+                host[g].offsets.size() * sizeof(int));
+    char* base = static_cast<char*>(b->d_mem);
+    b->groups.push_back({host[g].prec, host[g].Nx, host[g].n_groups,
+                         static_cast<int>(host[g].items.size()),
+                         reinterpret_cast<bpm::BatchItem*>(base + item_off[g]),
+                         reinterpret_cast<int*>(base + offs_off[g])});
+  }
+  if (stream_ordered) {
+    // The host staging buffer is released by the stream once the copy ran.
+    e = hipMemcpyAsync(b->d_mem, staging->data(), bytes, hipMemcpyHostToDevice,
+                       alloc_stream);
+    if (e == hipSuccess)
+      e = hipLaunchHostFunc(
+          alloc_stream,
+          [](void* v) { delete static_cast<std::vector<char>*>(v); }, staging);
+    else
+      delete staging;
+  } else {
+    e = hipMemcpy(b->d_mem, staging->data(), bytes, hipMemcpyHostToDevice);
+    delete staging;
+  }
+  if (e != hipSuccess) {
+    if (stream_ordered)
+      (void)hipFreeAsync(b->d_mem, alloc_stream);
+    else
+      (void)hipFree(b->d_mem);
+    delete b;
+    return hip_fail(e, "batch work-list upload");
+  }
+  *out = b;
+  return BPM_OK;
+}
+
+int batch_launch(const bpm_batch* b, hipStream_t s) {
+  for (const auto& d : b->deforms) {
+    int rc = bpm::launch_deform(d.prec, d.Nx, d.Nz, d.h, d.u, d.table, s);
+    if (rc) return fail(rc, "deformation pre-pass launch failed");
+  }
+  for (const auto& g : b->groups) {
+    int rc = bpm::launch_march_batch(g.prec, g.Nx, g.d_items, g.d_offsets,
+                                     g.n_groups, s);
+    if (rc) return fail(rc, "persistent march launch failed");
+  }
+  return BPM_OK;
 }
 
 }  // namespace
@@ -349,6 +538,54 @@ int bpm_propagate(const bpm_plan* p, const void* E0_in, const double* u_field,
     hipError_t e = hipFreeAsync(ws, s);
     if (rc == BPM_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
   }
+  return rc;
+}
+
+bpm_batch* bpm_batch_create(const bpm_job* jobs, int njobs) {
+  g_error.clear();
+  bpm_batch* b = nullptr;
+  batch_build(jobs, njobs, nullptr, false, &b);
+  return b;
+}
+
+int bpm_batch_launch(const bpm_batch* b, void* stream) {
+  g_error.clear();
+  if (!b) return fail(BPM_EINVAL, "batch is NULL");
+  return batch_launch(b, static_cast<hipStream_t>(stream));
+}
+
+int bpm_batch_info(const bpm_batch* b, int* n_launches, int* n_slices,
+                   int* n_workgroups) {
+  g_error.clear();
+  if (!b) return fail(BPM_EINVAL, "batch is NULL");
+  int items = 0, wgs = 0;
+  for (const auto& g : b->groups) {
+    items += g.n_items;
+    wgs += g.n_groups;
+  }
+  if (n_launches) *n_launches = static_cast<int>(b->groups.size());
+  if (n_slices) *n_slices = items;
+  if (n_workgroups) *n_workgroups = wgs;
+  return BPM_OK;
+}
+
+void bpm_batch_destroy(bpm_batch* b) {
+  if (!b) return;
+  if (b->d_mem) (void)hipFree(b->d_mem);
+  delete b;
+}
+
+int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream) {
+  g_error.clear();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bpm_batch* b = nullptr;
+  int rc = batch_build(jobs, njobs, s, true, &b);
+  if (rc) return rc;
+  rc = batch_launch(b, s);
+  hipError_t e = hipFreeAsync(b->d_mem, s);
+  b->d_mem = nullptr;
+  delete b;
+  if (rc == BPM_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync(batch)");
   return rc;
 }
 

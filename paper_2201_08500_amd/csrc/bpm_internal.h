@@ -37,19 +37,23 @@ struct MarchParams {
   double a_frac[4];         // A sub-step fractions (0 = skip)
 };
 
-// One unit of batched work: a contiguous range of slices of one problem.
-struct WorkItem {
+// One unit of batched work: one slice of one problem.
+struct BatchItem {
   MarchParams p;
-  int slice0;               // first slice of this item
-  int nslices;              // slices in this item
-  int Nx;                   // selects the kernel body
-  int pad;
+  int slice;
+  int pad[3];
 };
 
 int launch_deform(int prec, int Nx, int Nz, double h, const double* u,
                   void* table, hipStream_t stream);
 int launch_march(int prec, int Nx, int Nomega, const MarchParams& p,
                  hipStream_t stream);
+// Persistent launch: n_groups work groups, group g runs
+// items[offsets[g] .. offsets[g+1]) (device arrays).
+int launch_march_batch(int prec, int Nx, const BatchItem* items,
+                       const int* offsets, int n_groups, hipStream_t stream);
+// Resident work groups per CU and threads per group of a march variant.
+int march_occupancy(int prec, int Nx, int* wg_per_cu, int* threads);
 
 }  // namespace bpm
 

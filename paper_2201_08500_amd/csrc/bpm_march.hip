@@ -45,6 +45,12 @@ template <class T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
+// p*x + q*y with the real parts and imaginary parts each one FMA chain
+template <class T>
+__device__ __forceinline__ cx<T> cmuladd(cx<T> p, cx<T> x, cx<T> q, cx<T> y) {
+  return {p.x * x.x - p.y * x.y + q.x * y.x - q.y * y.y,
+          p.x * x.y + p.y * x.x + q.x * y.y + q.y * y.x};
+}
 // multiply by -i (forward transform) or +i (inverse transform)
 template <bool INV, class T>
 __device__ __forceinline__ cx<T> rot(cx<T> a) {
@@ -499,24 +505,22 @@ struct March {
       }
       fft<true>(a, b, tw, lds, t, xbuf);
 
-      // Coupling (Eq. fov10) in FP64 inside the slab.
+      // Coupling (Eq. fov10) in FP64 where the slab is; samples outside
+      // keep the propagated field (whole-wave vacuum groups branch past).
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        const cx<double> A = conv<double>(a[i]);
-        const cx<double> B = conv<double>(b[i]);
-        cx<double> na, nb;
-        if constexpr (DEFORMED) {
-          const cx<double> ee = {static_cast<double>(e[i].x),
-                                 static_cast<double>(e[i].y)};
-          na = cmul(d0, A) + cmul(dp1, cmul(ee, B));
-          nb = cmul(d0, B) + cmul(dm1, cmulc(A, ee));
-        } else {
-          na = cmul(d0, A) + cmul(dp1, B);
-          nb = cmul(d0, B) + cmul(dm1, A);
-        }
         if (inside[i]) {
-          a[i] = conv<CT>(na);
-          b[i] = conv<CT>(nb);
+          const cx<double> A = conv<double>(a[i]);
+          const cx<double> B = conv<double>(b[i]);
+          cx<double> cp = dp1, cm = dm1;
+          if constexpr (DEFORMED) {
+            const cx<double> ee = {static_cast<double>(e[i].x),
+                                   static_cast<double>(e[i].y)};
+            cp = cmul(dp1, ee);    // d+1 exp(+i h u)
+            cm = cmulc(dm1, ee);   // d-1 exp(-i h u)
+          }
+          a[i] = conv<CT>(cmuladd(d0, A, cp, B));
+          b[i] = conv<CT>(cmuladd(d0, B, cm, A));
         }
       }
       if constexpr (DEFORMED) {
@@ -542,6 +546,28 @@ template <class M, bool DEFORMED>
 __global__ void __launch_bounds__(M::T) march_kernel(MarchParams p) {
   __shared__ typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
   M::template run<DEFORMED>(p, blockIdx.x, threadIdx.x, lds);
+}
+
+// Persistent march over a precomputed list of (problem, slice) items: work
+// group g runs items offsets[g] .. offsets[g+1]-1 one after another.  Each
+// item runs exactly the per-slice code of march_kernel, so results do not
+// depend on how items are packed.
+template <class M>
+__global__ void __launch_bounds__(M::T)
+    march_batch_kernel(const BatchItem* __restrict__ items,
+                       const int* __restrict__ offsets) {
+  __shared__ typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
+  const int k0 = offsets[blockIdx.x];
+  const int k1 = offsets[blockIdx.x + 1];
+  for (int k = k0; k < k1; ++k) {
+    const MarchParams p = items[k].p;
+    const int slice = items[k].slice;
+    if (p.table)
+      M::template run<true>(p, slice, threadIdx.x, lds);
+    else
+      M::template run<false>(p, slice, threadIdx.x, lds);
+    lds_barrier();   // LDS of this item fully consumed before the next one
+  }
 }
 
 // exp(i h u): FP64 sincos for FP64 tables; for FP32 tables h*u is reduced
@@ -597,26 +623,24 @@ struct Choice<PREC, 4096> {
   using type = March<PREC, 4096, 8, 8, 8, 8, 8>;
 };
 
-template <int PREC, int N>
-int launch_n(int Nomega, const MarchParams& p, hipStream_t stream) {
-  using M = typename Choice<PREC, N>::type;
-  if (p.table)
-    hipLaunchKernelGGL((march_kernel<M, true>), dim3(Nomega), dim3(M::T), 0,
-                       stream, p);
-  else
-    hipLaunchKernelGGL((march_kernel<M, false>), dim3(Nomega), dim3(M::T), 0,
-                       stream, p);
-  return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
-}
-
-template <int PREC>
-int launch_prec(int Nx, int Nomega, const MarchParams& p, hipStream_t s) {
+// Calls f(M{}) with the March variant of (precision, Nx).
+template <int PREC, class F>
+int with_n(int Nx, F&& f) {
   switch (Nx) {
-    case 256: return launch_n<PREC, 256>(Nomega, p, s);
-    case 512: return launch_n<PREC, 512>(Nomega, p, s);
-    case 1024: return launch_n<PREC, 1024>(Nomega, p, s);
-    case 2048: return launch_n<PREC, 2048>(Nomega, p, s);
-    case 4096: return launch_n<PREC, 4096>(Nomega, p, s);
+    case 256: return f(typename Choice<PREC, 256>::type{});
+    case 512: return f(typename Choice<PREC, 512>::type{});
+    case 1024: return f(typename Choice<PREC, 1024>::type{});
+    case 2048: return f(typename Choice<PREC, 2048>::type{});
+    case 4096: return f(typename Choice<PREC, 4096>::type{});
+    default: return BPM_EUNSUPPORTED;
+  }
+}
+template <class F>
+int with_variant(int prec, int Nx, F&& f) {
+  switch (prec) {
+    case BPM_PREC_FP64: return with_n<BPM_PREC_FP64>(Nx, f);
+    case BPM_PREC_FP32: return with_n<BPM_PREC_FP32>(Nx, f);
+    case BPM_PREC_FP32S: return with_n<BPM_PREC_FP32S>(Nx, f);
     default: return BPM_EUNSUPPORTED;
   }
 }
@@ -625,12 +649,40 @@ int launch_prec(int Nx, int Nomega, const MarchParams& p, hipStream_t s) {
 
 int launch_march(int prec, int Nx, int Nomega, const MarchParams& p,
                  hipStream_t stream) {
-  switch (prec) {
-    case BPM_PREC_FP64: return launch_prec<BPM_PREC_FP64>(Nx, Nomega, p, stream);
-    case BPM_PREC_FP32: return launch_prec<BPM_PREC_FP32>(Nx, Nomega, p, stream);
-    case BPM_PREC_FP32S: return launch_prec<BPM_PREC_FP32S>(Nx, Nomega, p, stream);
-    default: return BPM_EUNSUPPORTED;
-  }
+  return with_variant(prec, Nx, [&](auto m) {
+    using M = decltype(m);
+    if (p.table)
+      hipLaunchKernelGGL((march_kernel<M, true>), dim3(Nomega), dim3(M::T), 0,
+                         stream, p);
+    else
+      hipLaunchKernelGGL((march_kernel<M, false>), dim3(Nomega), dim3(M::T), 0,
+                         stream, p);
+    return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
+  });
+}
+
+int launch_march_batch(int prec, int Nx, const BatchItem* items,
+                       const int* offsets, int n_groups, hipStream_t stream) {
+  return with_variant(prec, Nx, [&](auto m) {
+    using M = decltype(m);
+    hipLaunchKernelGGL((march_batch_kernel<M>), dim3(n_groups), dim3(M::T), 0,
+                       stream, items, offsets);
+    return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
+  });
+}
+
+int march_occupancy(int prec, int Nx, int* wg_per_cu, int* threads) {
+  return with_variant(prec, Nx, [&](auto m) {
+    using M = decltype(m);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(&march_batch_kernel<M>), M::T,
+            0) != hipSuccess)
+      return BPM_EHIP;
+    *wg_per_cu = n;
+    *threads = M::T;
+    return BPM_OK;
+  });
 }
 
 int launch_deform(int prec, int Nx, int Nz, double h, const double* u,

@@ -1,0 +1,134 @@
+"""GPU tests of the batched persistent launch (bpm_batch_*): every slice of
+every job equals the same job run alone (bitwise), graph capture and replay
+reproduce the eager result, and sampled slices of problems drawn from the
+uneven-batch workload match the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from workloads.metrics import report
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def make_jobs(specs):
+    from paper_2201_08500_amd import Job, Plan
+    jobs, works = [], []
+    for w, prec in specs:
+        p = Plan.from_workload(w, precision=prec)
+        E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
+        u = None if w.u is None else torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
+        jobs.append(Job(p, E0, u))
+        works.append(w)
+    return jobs, works
+
+
+def alone(job):
+    a, b = job.plan.propagate(job.E0_in, job.u)
+    torch.cuda.synchronize()
+    return a.cpu(), b.cpu()
+
+
+MIX = [
+    (dict(Nx=256, Nz=30, Nomega=7, seed=1), "fp32s"),
+    (dict(Nx=512, Nz=41, Nomega=3, seed=2, deformed=False), "fp64"),
+    (dict(Nx=1024, Nz=17, Nomega=5, seed=3), "fp32"),
+    (dict(Nx=2048, Nz=23, Nomega=2, seed=4), "fp32s"),
+    (dict(Nx=4096, Nz=12, Nomega=3, seed=5), "fp64"),
+    (dict(Nx=256, Nz=55, Nomega=1, seed=6, deformed=False), "fp32s"),
+    (dict(Nx=2048, Nz=9, Nomega=4, seed=7), "fp32s"),
+]
+
+
+def test_batch_equals_each_job_alone_bitwise():
+    from paper_2201_08500_amd import Batch
+    jobs, _ = make_jobs([(W.small(**kw), prec) for kw, prec in MIX])
+    ref = [alone(j) for j in jobs]
+    b = Batch(jobs)
+    info = b.info()
+    assert info["slices"] == sum(kw["Nomega"] for kw, _ in MIX)
+    assert info["launches"] == len({(kw["Nx"], p) for kw, p in MIX})
+    for j in jobs:
+        j.E0_out.zero_()
+        j.Eh_out.zero_()
+    b.launch()
+    torch.cuda.synchronize()
+    for j, (ra, rb) in zip(jobs, ref):
+        assert torch.equal(j.E0_out.cpu(), ra) and torch.equal(j.Eh_out.cpu(), rb)
+
+
+def test_one_shot_batch_equals_prepared_batch():
+    from paper_2201_08500_amd import propagate_batch
+    jobs, _ = make_jobs([(W.small(**kw), prec) for kw, prec in MIX[:4]])
+    ref = [alone(j) for j in jobs]
+    propagate_batch(jobs)
+    torch.cuda.synchronize()
+    for j, (ra, rb) in zip(jobs, ref):
+        assert torch.equal(j.E0_out.cpu(), ra) and torch.equal(j.Eh_out.cpu(), rb)
+
+
+def test_batch_graph_capture_and_replay():
+    """The launch holds kernels only: capture it once, replay three times
+    with eager work and synchronisation in between, compare every replay."""
+    from paper_2201_08500_amd import Batch
+    jobs, _ = make_jobs([(W.small(**kw), prec) for kw, prec in MIX])
+    b = Batch(jobs)
+    b.launch()
+    torch.cuda.synchronize()
+    eager = [(j.E0_out.clone(), j.Eh_out.clone()) for j in jobs]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            b.launch()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for j in jobs:
+            j.E0_out.fill_(rep + 1.0)
+            j.Eh_out.fill_(-rep - 1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for j, (ea, eb) in zip(jobs, eager):
+            assert torch.equal(j.E0_out, ea) and torch.equal(j.Eh_out, eb), rep
+
+
+def test_batch_rejects_bad_jobs():
+    from paper_2201_08500_amd import Batch, BpmError, Job
+    jobs, _ = make_jobs([(W.small(**MIX[0][0]), "fp32s")])
+    j = jobs[0]
+    bad = Job(j.plan, j.E0_in, j.u, E0_out=j.E0_out, Eh_out=j.E0_out)
+    with pytest.raises(BpmError):
+        Batch([bad])
+    with pytest.raises(BpmError):
+        Batch([])
+
+
+def test_uneven_batch_problems_sampled_against_oracle():
+    """Sixteen problems of the uneven-batch workload at their real sizes in
+    one prepared batch (fp32s); two slices of the three smallest problems
+    recomputed by the oracle."""
+    from paper_2201_08500_amd import Batch
+    specs = W.c4_problem_specs()[:16]
+    works = [W.c4_problem(s) for s in specs]
+    jobs, _ = make_jobs([(w, "fp32s") for w in works])
+    b = Batch(jobs)
+    b.launch()
+    torch.cuda.synchronize()
+    order = sorted(range(len(works)), key=lambda i: works[i].Nx * works[i].Nz)
+    for i in order[:3]:
+        w = works[i]
+        sl = sorted({0, w.Nomega // 2})
+        ws = w.subset(sl)
+        E32 = ws.E0_in.astype(np.complex64).astype(np.complex128)
+        ao, bo = O.march(O.Problem.from_workload(ws), E32, ws.u)
+        a = jobs[i].E0_out.cpu().numpy()[sl].astype(np.complex128)
+        bb = jobs[i].Eh_out.cpu().numpy()[sl].astype(np.complex128)
+        r = report(a, bb, ao, bo)
+        print(f"\n{w.name} slices {sl}: {r}", flush=True)
+        assert r["rel_l2"] <= 1e-5 and r["phase_err_rad"] <= 1e-4, r
