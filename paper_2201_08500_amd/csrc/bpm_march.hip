@@ -319,8 +319,26 @@ struct March {
     return o;
   }
   static constexpr int NTW = tw_off(NP) > 0 ? tw_off(NP) : 1;
+  // LDS address of sample idx in the exchange after pass p: one gap of Ns
+  // slots every max(Rp Ns, L) samples, L = samples per 128-byte bank row.
+  // The pass writes x[(Rp a + r) Ns + b] for consecutive butterflies
+  // (b = jb mod Ns, a = jb / Ns) and the next pass reads consecutive samples;
+  // with the gaps both hit distinct banks across each group of L lanes.
+  static constexpr int kL = 128 / int(sizeof(SV));
+  static constexpr int pad_div(int p) {
+    return rad[p] * ns(p) > kL ? rad[p] * ns(p) : kL;
+  }
+  static constexpr int env_slots() {
+    int m = N;
+    for (int p = 0; p + 1 < NP; ++p) {
+      const int e = N + ns(p) * ((N - 1) / pad_div(p)) ;
+      m = e > m ? e : m;
+    }
+    return m;
+  }
+  static constexpr int kEnv = env_slots();
   // Two LDS buffers (one barrier per exchange) when they fit in 160 KiB.
-  static constexpr size_t kEnvBytes = size_t(N) * sizeof(SV);
+  static constexpr size_t kEnvBytes = size_t(kEnv) * sizeof(SV);
   static constexpr int NBUF = (4 * kEnvBytes <= 160 * 1024) ? 2 : 1;
   static constexpr size_t kLdsBytes = NBUF * 2 * kEnvBytes;
 
@@ -348,8 +366,9 @@ struct March {
     constexpr int Ns = ns(P);
     constexpr int G = R / Rp;
     constexpr bool last = (P == NP - 1);
-    SV* la = lds + xbuf * 2 * N;
-    SV* lb = la + N;
+    constexpr int D = pad_div(P);
+    SV* la = lds + xbuf * 2 * kEnv;
+    SV* lb = la + kEnv;
 #pragma unroll
     for (int s = 0; s < G; ++s) {
       cx<CT> va[Rp], vb[Rp];
@@ -384,8 +403,10 @@ struct March {
         const int base = (jb / Ns) * Ns * Rp + (jb % Ns);
 #pragma unroll
         for (int r = 0; r < Rp; ++r) {
-          store(la, base + r * Ns, va[r]);
-          store(lb, base + r * Ns, vb[r]);
+          const int idx = base + r * Ns;
+          const int slot = idx + Ns * (idx / D);
+          store(la, slot, va[r]);
+          store(lb, slot, vb[r]);
         }
       }
     }
@@ -393,8 +414,10 @@ struct March {
       lds_barrier();
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        a[i] = load(la, t + T * i);
-        b[i] = load(lb, t + T * i);
+        const int idx = t + T * i;
+        const int slot = idx + Ns * (idx / D);
+        a[i] = load(la, slot);
+        b[i] = load(lb, slot);
       }
       if constexpr (NBUF == 1) {
         lds_barrier();

@@ -270,8 +270,9 @@ def c4_problem(spec: dict, with_u: bool = True) -> Workload:
     u = None
     if with_u:
         u = row[None, :] + (spec["bump"] * gz)[:, None] * gx[None, :]
+    meta = {k: v for k, v in spec.items() if k not in ("Nx", "Nz", "Nomega")}
     w = _common(f"batch-{spec['index']}-{Nx}x{Nz}x{Nw}", Nx, Nz, Nw, delta, E0,
-                u, **spec)
+                u, **meta)
     w.meta["u_factors"] = (row, gz, gx, spec["bump"])
     return w
 
