@@ -64,6 +64,13 @@ enum {
                              butterflies and pointwise arithmetic */
 };
 
+/* Transform schedules of the march (all give the same result to rounding):
+ * STOCKHAM -- radix-R Stockham passes, one work-group barrier per pass;
+ * FOURSTEP -- radix-W across the W wavefronts of a slice plus a Stockham
+ * transform inside each wavefront, two barriers per z-step;
+ * AUTO -- the library's measured default for (precision, Nx). */
+enum { BPM_SCHED_AUTO = -1, BPM_SCHED_STOCKHAM = 0, BPM_SCHED_FOURSTEP = 1 };
+
 /* Create a plan for Nomega slices of an Nx-point window (Section 2.1 problem
  * statement: grid dx, step dz, Nz steps, susceptibilities chi0, chih,
  * chihbar, Bragg angle theta_B in radians, wavelength lambda in metres).
@@ -88,6 +95,11 @@ int bpm_plan_set_crystal(bpm_plan* plan, double x_front, double thickness);
 int bpm_plan_set_detuning(bpm_plan* plan, const double* delta);
 /* split_order: 1 (Eq. fov4), 2 or 4 (Eq. split-op); zassenhaus: 0 or 1. */
 int bpm_plan_set_options(bpm_plan* plan, int split_order, int zassenhaus);
+
+/* Transform schedule (BPM_SCHED_*); default AUTO.  get returns the
+ * schedule a propagate would use. */
+int bpm_plan_set_schedule(bpm_plan* plan, int schedule);
+int bpm_plan_get_schedule(const bpm_plan* plan);
 
 /* Host-only diagnostic: the FP64 constants of slice w for B sub-step 0,
  * out[0..7] = k, cos(alpha), d0.re, d0.im, d+1.re, d+1.im, d-1.re, d-1.im

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbpm.so")
 
 BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_EUNSUPPORTED = 0, -1, -2, -3, -4
 PRECISION = {"fp64": 0, "fp32": 1, "fp32s": 2}
+SCHEDULE = {"auto": -1, "stockham": 0, "fourstep": 1}
 _CODES = {BPM_EINVAL: "EINVAL", BPM_ENOMEM: "ENOMEM", BPM_EHIP: "EHIP",
           BPM_EUNSUPPORTED: "EUNSUPPORTED"}
 
@@ -53,6 +54,8 @@ _SIGNATURES = [
      [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     ("bpm_plan_set_options", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    ("bpm_plan_set_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("bpm_plan_get_schedule", ctypes.c_int, [ctypes.c_void_p]),
     ("bpm_plan_get_constants", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     ("bpm_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p]),
@@ -130,7 +133,7 @@ class Plan:
 
     def __init__(self, Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam,
                  Nomega, precision="fp64", x_front=None, thickness=None,
-                 delta=None, split_order=1, zassenhaus=True):
+                 delta=None, split_order=1, zassenhaus=True, schedule=None):
         L = lib()
         self._h = None
         h = L.bpm_plan_create(int(Nx), float(dx), float(dz), int(Nz),
@@ -152,6 +155,13 @@ class Plan:
         if split_order != 1 or not zassenhaus:
             _check(L.bpm_plan_set_options(self._h, int(split_order),
                                           int(bool(zassenhaus))))
+        if schedule is not None:
+            _check(L.bpm_plan_set_schedule(self._h, SCHEDULE[schedule]
+                                           if isinstance(schedule, str) else int(schedule)))
+
+    @property
+    def schedule(self) -> int:
+        return int(lib().bpm_plan_get_schedule(self._h))
 
     @classmethod
     def from_workload(cls, w, precision="fp64", **kw):

@@ -10,6 +10,7 @@
 #include <limits>
 #include <map>
 #include <queue>
+#include <tuple>
 #include <string>
 #include <utility>
 
@@ -132,6 +133,11 @@ int freeze(bpm_plan* p) {
   return BPM_OK;
 }
 
+int plan_schedule(const bpm_plan* p) {
+  return p->schedule >= 0 ? p->schedule
+                          : bpm::default_schedule(p->precision, p->Nx);
+}
+
 int check_mutable(bpm_plan* p) {
   if (!p) return fail(BPM_EINVAL, "plan is NULL");
   if (p->frozen) return fail(BPM_EINVAL, "plan is frozen after its first propagate");
@@ -176,7 +182,7 @@ struct DeformJob {
 };
 
 struct BatchGroup {
-  int prec, Nx;
+  int prec, Nx, sched;
   int n_groups;
   int n_items;
   bpm::BatchItem* d_items;
@@ -227,27 +233,28 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
 
   auto* b = new bpm_batch();
-  std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> by_variant;
+  std::map<std::tuple<int, int, int>, std::vector<std::pair<int, int>>> by_variant;
   for (int i = 0; i < njobs; ++i) {
     const bpm_plan* p = jobs[i].plan;
     if (jobs[i].u_field)
       b->deforms.push_back({p->precision, p->Nx, p->Nz, p->h, jobs[i].u_field,
                             jobs[i].workspace});
     for (int w = 0; w < p->Nomega; ++w)
-      by_variant[{p->precision, p->Nx}].push_back({i, w});
+      by_variant[{p->precision, p->Nx, plan_schedule(p)}].push_back({i, w});
   }
   // Host work lists: per variant, items ordered by group, longest first.
   struct HostGroup {
-    int prec, Nx, n_groups;
+    int prec, Nx, sched, n_groups;
     std::vector<bpm::BatchItem> items;
     std::vector<int> offsets;
   };
   std::vector<HostGroup> host;
   for (auto& kv : by_variant) {
-    const int prec = kv.first.first, Nx = kv.first.second;
+    const int prec = std::get<0>(kv.first), Nx = std::get<1>(kv.first);
+    const int sched = std::get<2>(kv.first);
     auto& slices = kv.second;
     int per_cu = 0, threads = 0;
-    int rc = bpm::march_occupancy(prec, Nx, &per_cu, &threads);
+    int rc = bpm::march_occupancy(prec, Nx, sched, &per_cu, &threads);
     if (rc) {
       delete b;
       return fail(rc, "occupancy query failed for Nx " + std::to_string(Nx));
@@ -269,7 +276,7 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
       l.first += jobs[s.first].plan->Nz;
       heap.push(l);
     }
-    HostGroup hg{prec, Nx, G, {}, {0}};
+    HostGroup hg{prec, Nx, sched, G, {}, {0}};
     for (int g = 0; g < G; ++g) {
       for (auto& s : per_group[g]) {
         const bpm_job& j = jobs[s.first];
@@ -309,7 +316,7 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
     std::memcpy(staging->data() + offs_off[g], host[g].offsets.data(),
                 host[g].offsets.size() * sizeof(int));
     char* base = static_cast<char*>(b->d_mem);
-    b->groups.push_back({host[g].prec, host[g].Nx, host[g].n_groups,
+    b->groups.push_back({host[g].prec, host[g].Nx, host[g].sched, host[g].n_groups,
                          static_cast<int>(host[g].items.size()),
                          reinterpret_cast<bpm::BatchItem*>(base + item_off[g]),
                          reinterpret_cast<int*>(base + offs_off[g])});
@@ -346,8 +353,8 @@ int batch_launch(const bpm_batch* b, hipStream_t s) {
     if (rc) return fail(rc, "deformation pre-pass launch failed");
   }
   for (const auto& g : b->groups) {
-    int rc = bpm::launch_march_batch(g.prec, g.Nx, g.d_items, g.d_offsets,
-                                     g.n_groups, s);
+    int rc = bpm::launch_march_batch(g.prec, g.Nx, g.sched, g.d_items,
+                                     g.d_offsets, g.n_groups, s);
     if (rc) return fail(rc, "persistent march launch failed");
   }
   return BPM_OK;
@@ -441,6 +448,21 @@ int bpm_plan_set_options(bpm_plan* p, int split_order, int zassenhaus) {
   return BPM_OK;
 }
 
+int bpm_plan_set_schedule(bpm_plan* p, int schedule) {
+  int rc = check_mutable(p);
+  if (rc) return rc;
+  if (schedule != BPM_SCHED_AUTO && schedule != BPM_SCHED_STOCKHAM &&
+      schedule != BPM_SCHED_FOURSTEP)
+    return fail(BPM_EINVAL, "unknown schedule");
+  p->schedule = schedule;
+  return BPM_OK;
+}
+
+int bpm_plan_get_schedule(const bpm_plan* p) {
+  if (!p) return fail(BPM_EINVAL, "plan is NULL");
+  return plan_schedule(p);
+}
+
 int bpm_plan_get_constants(const bpm_plan* cp, int w, double* out) {
   g_error.clear();
   if (!cp || !out) return fail(BPM_EINVAL, "plan and out must be non-NULL");
@@ -495,7 +517,7 @@ int bpm_march(const bpm_plan* cp, const void* E0_in, const void* table,
   int rc = freeze(p);
   if (rc) return rc;
   const bpm::MarchParams m = march_params(p, E0_in, table, E0_out, Eh_out);
-  rc = bpm::launch_march(p->precision, p->Nx, p->Nomega, m,
+  rc = bpm::launch_march(p->precision, p->Nx, plan_schedule(p), p->Nomega, m,
                          static_cast<hipStream_t>(stream));
   if (rc == BPM_EUNSUPPORTED) return fail(rc, "unsupported size/precision");
   if (rc) return fail(rc, "march kernel launch failed");

@@ -46,14 +46,17 @@ struct BatchItem {
 
 int launch_deform(int prec, int Nx, int Nz, double h, const double* u,
                   void* table, hipStream_t stream);
-int launch_march(int prec, int Nx, int Nomega, const MarchParams& p,
-                 hipStream_t stream);
+// sched: transform schedule (0 Stockham, 1 four-step), see bpm.h.
+int launch_march(int prec, int Nx, int sched, int Nomega,
+                 const MarchParams& p, hipStream_t stream);
 // Persistent launch: n_groups work groups, group g runs
 // items[offsets[g] .. offsets[g+1]) (device arrays).
-int launch_march_batch(int prec, int Nx, const BatchItem* items,
+int launch_march_batch(int prec, int Nx, int sched, const BatchItem* items,
                        const int* offsets, int n_groups, hipStream_t stream);
 // Resident work groups per CU and threads per group of a march variant.
-int march_occupancy(int prec, int Nx, int* wg_per_cu, int* threads);
+int march_occupancy(int prec, int Nx, int sched, int* wg_per_cu, int* threads);
+// Library default schedule of (precision, Nx).
+int default_schedule(int prec, int Nx);
 
 }  // namespace bpm
 
@@ -65,6 +68,7 @@ struct bpm_plan {
   int precision = BPM_PREC_FP64;
   double x_front = 0.0, thickness = HUGE_VAL;
   int split_order = 1, zassenhaus = 1;
+  int schedule = -1;  // BPM_SCHED_AUTO
   std::vector<double> delta;
   // derived (FP64)
   double k0 = 0, h = 0;

@@ -261,6 +261,13 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Orders LDS accesses of one wavefront in the compiler only: the hardware
+// executes a wavefront's LDS instructions in program order.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // -------------------------------------------------------------- precision --
 
 template <int PREC>
@@ -294,8 +301,10 @@ struct vec2<double> {
 
 // ------------------------------------------------------------- the march --
 
-template <int PREC, int N, int R, int... RADS>
+template <int PREC, int N_, int R_, int... RADS>
 struct March {
+  static constexpr int N = N_;  // transform length
+  static constexpr int R = R_;  // samples per thread per envelope
   using CT = typename Prec<PREC>::CT;
   using ST = typename Prec<PREC>::ST;
   using SV = typename vec2<ST>::type;
@@ -359,7 +368,14 @@ struct March {
   // x[jb + r N/Rp], applies twiddles W_{Ns Rp}^{r (jb mod Ns)}, transforms,
   // and writes x[(jb/Ns) Ns Rp + jb mod Ns + r Ns].  Thread t owns
   // butterflies jb = t + s T and, on input, register slot s + r (R/Rp).
-  template <int P, bool INV>
+  // Exchange synchronisation: kDouble / kSingle -- a work-group barrier per
+  // exchange with two / one LDS buffers; kWave -- the T threads are one
+  // wavefront, whose LDS operations execute in program order, so a
+  // compiler-only fence is enough and one buffer is reused.
+  enum { kDouble = 0, kSingle = 1, kWave = 2 };
+  static constexpr int kSync = NBUF == 2 ? kDouble : kSingle;
+
+  template <int P, bool INV, int SYNC = kSync>
   __device__ static void pass(Reg& a, Reg& b, const cx<CT> (&tw)[NTW],
                               SV* lds, int t, int& xbuf) {
     constexpr int Rp = rad[P];
@@ -367,7 +383,7 @@ struct March {
     constexpr int G = R / Rp;
     constexpr bool last = (P == NP - 1);
     constexpr int D = pad_div(P);
-    SV* la = lds + xbuf * 2 * kEnv;
+    SV* la = lds + (SYNC == kDouble ? xbuf * 2 * kEnv : 0);
     SV* lb = la + kEnv;
 #pragma unroll
     for (int s = 0; s < G; ++s) {
@@ -411,7 +427,10 @@ struct March {
       }
     }
     if constexpr (!last) {
-      lds_barrier();
+      if constexpr (SYNC == kWave)
+        wave_sync();
+      else
+        lds_barrier();
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int idx = t + T * i;
@@ -419,24 +438,27 @@ struct March {
         a[i] = load(la, slot);
         b[i] = load(lb, slot);
       }
-      if constexpr (NBUF == 1) {
+      if constexpr (SYNC == kSingle) {
         lds_barrier();
+      } else if constexpr (SYNC == kWave) {
+        wave_sync();
       } else {
         xbuf ^= 1;
       }
     }
   }
 
-  template <bool INV, int... P>
+  template <bool INV, int SYNC, int... P>
   __device__ static void fft_impl(Reg& a, Reg& b, const cx<CT> (&tw)[NTW],
                                   SV* lds, int t, int& xbuf,
                                   std::integer_sequence<int, P...>) {
-    (pass<P, INV>(a, b, tw, lds, t, xbuf), ...);
+    (pass<P, INV, SYNC>(a, b, tw, lds, t, xbuf), ...);
   }
-  template <bool INV>
+  template <bool INV, int SYNC = kSync>
   __device__ static void fft(Reg& a, Reg& b, const cx<CT> (&tw)[NTW], SV* lds,
                              int t, int& xbuf) {
-    fft_impl<INV>(a, b, tw, lds, t, xbuf, std::make_integer_sequence<int, NP>{});
+    fft_impl<INV, SYNC>(a, b, tw, lds, t, xbuf,
+                        std::make_integer_sequence<int, NP>{});
   }
 
   // Twiddles W_{Ns Rp}^{r (jb mod Ns)} of every pass after the first.
@@ -467,108 +489,256 @@ struct March {
     (twiddles_pass<P>(tw, t), ...);
   }
 
-  // Whole march of one slice by threads t = 0..T-1 of the calling group.
-  template <bool DEFORMED>
-  __device__ static void run(const MarchParams& p, int slice, int t, SV* lds) {
-    const SliceConst& sc = p.sc[slice];
-    const SV* in = static_cast<const SV*>(p.E0_in) + size_t(slice) * N;
-    SV* out_a = static_cast<SV*>(p.E0_out) + size_t(slice) * N;
-    SV* out_b = static_cast<SV*>(p.Eh_out) + size_t(slice) * N;
-    const SV* table = static_cast<const SV*>(p.table);
-
+  // Transform interface used by march_slice: per-thread context (twiddles),
+  // the DFT bin held in register slot i after forward(), and in-place
+  // forward / inverse transforms of both envelopes.
+  struct Ctx {
     cx<CT> tw[NTW];
-    twiddles_impl(tw, t, std::make_integer_sequence<int, NP>{});
+    int xbuf;
+  };
+  __device__ static void init(Ctx& c, int t) {
+    twiddles_impl(c.tw, t, std::make_integer_sequence<int, NP>{});
+    c.xbuf = 0;
+  }
+  __device__ static int bin(int t, int i) { return t + T * i; }
+  __device__ static void forward(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
+    fft<false>(a, b, c.tw, lds, t, c.xbuf);
+  }
+  __device__ static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
+    fft<true>(a, b, c.tw, lds, t, c.xbuf);
+  }
+};
 
-    // Propagators of the bins this thread owns after a forward transform
-    // (bin t + T i, signed), 1/Nx of the inverse transform folded in.
-    cx<double> Pp[R], Pm[R];
-    bool inside[R];
+// Four-step transform of N = W M: a radix-W DFT across the W wavefronts of
+// the slice (in registers), one work-group exchange per direction, and an
+// M-point Stockham transform inside each wavefront whose exchanges need no
+// work-group barrier.  Per z-step that is 2 barriers instead of one per
+// Stockham pass, and between them the wavefronts run independently, so one
+// wavefront's LDS traffic overlaps the others' arithmetic.
+//
+// Layouts.  x-space (input and output): thread t keeps x[t + T i], i < R,
+// the same as the Stockham path.  With m_j = t + T j (j < J = R/W) and
+// n = m + M q, slot j + J q holds x[m_j + M q].  Forward: DFT over q, twiddle
+// W_N^{m k1}, exchange so that wavefront k1 holds y[m][k1] for all m (lane l,
+// slot i -> m = l + 64 i), then the M-point transform over m.  Slot i of
+// lane l in wavefront w ends with bin K = w + W (l + 64 i).
+template <int PREC, int W, class In>
+struct FourStep {
+  using CT = typename Prec<PREC>::CT;
+  using ST = typename Prec<PREC>::ST;
+  using SV = typename vec2<ST>::type;
+  static_assert(In::T == 64, "the in-wave transform must use one wavefront");
+  static constexpr int M = In::N;
+  static constexpr int R = In::R;
+  static constexpr int N = W * M;
+  static constexpr int T = 64 * W;
+  static constexpr int J = R / W;
+  static_assert(W == 1 || (R % W == 0 && W <= 8), "unsupported wave count");
+  static constexpr int kRegion = 2 * In::kEnv;  // per wavefront: a then b
+  static constexpr size_t kG = size_t(W) * kRegion;
+  static constexpr size_t kGp = W > 1 ? size_t(W) * 2 * M : 0;
+  // Separate forward and inverse exchange buffers when they fit; otherwise
+  // one buffer and two extra barriers per step.
+  static constexpr bool kAlias = (kG + kGp) * sizeof(SV) > 160 * 1024;
+  static constexpr size_t kLdsBytes = (kAlias ? kG : kG + kGp) * sizeof(SV);
+  static constexpr int NTWX = W > 1 ? J * (W - 1) : 1;
+  using Reg = cx<CT>[R];
+
+  struct Ctx {
+    typename In::Ctx in;
+    cx<CT> twx[NTWX];
+  };
+  __device__ static void init(Ctx& c, int t) {
+    In::init(c.in, t & 63);
+    if constexpr (W > 1) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int m = t + T * i;
-      const int ms = m < N / 2 ? m : m - N;
-      Pp[i] = propagator(ms, N, p.dx, sc.k, p.h_half, +1.0, p.dz);
-      Pm[i] = propagator(ms, N, p.dx, sc.k, p.h_half, -1.0, p.dz);
-      const double x = static_cast<double>(m - N / 2) * p.dx;
-      inside[i] = (x >= p.x_front) && (x < p.x_end);
+      for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int k1 = 1; k1 < W; ++k1) {
+          double sn, cs;
+          sincospi(-2.0 * double((t + T * j) * k1) / double(N), &sn, &cs);
+          c.twx[j * (W - 1) + k1 - 1] = {static_cast<CT>(cs), static_cast<CT>(sn)};
+        }
     }
-    const cx<double> d0 = {sc.d[0][0], sc.d[0][1]};
-    const cx<double> dp1 = {sc.d[0][2], sc.d[0][3]};
-    const cx<double> dm1 = {sc.d[0][4], sc.d[0][5]};
+  }
+  __device__ static int bin(int t, int i) {
+    return (t >> 6) + W * ((t & 63) + 64 * i);
+  }
 
-    Reg a, b;
+  __device__ static void forward(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
+    const int wv = t >> 6, l = t & 63;
+    SV* own = lds + wv * kRegion;
+    if constexpr (W > 1) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const SV v = in[t + T * i];
-      a[i] = {static_cast<CT>(v.x), static_cast<CT>(v.y)};
-      b[i] = {CT(0), CT(0)};
-    }
-
-    int xbuf = 0;
-    SV e[R];
-    if constexpr (DEFORMED) {
+      for (int j = 0; j < J; ++j) {
+        cx<CT> va[W], vb[W];
 #pragma unroll
-      for (int i = 0; i < R; ++i) e[i] = table[t + T * i];
-    }
-    for (int n = 0; n < p.Nz; ++n) {
-      // Row n of exp(i h u) is in e[]; fetch row n+1 while this step runs.
-      SV e_next[R];
-      if constexpr (DEFORMED) {
-        const int nn = (n + 1 < p.Nz) ? n + 1 : n;
-        const SV* row = table + size_t(nn) * N;
+        for (int q = 0; q < W; ++q) {
+          va[q] = a[j + J * q];
+          vb[q] = b[j + J * q];
+        }
+        dft<W, false>(va);
+        dft<W, false>(vb);
 #pragma unroll
-        for (int i = 0; i < R; ++i) e_next[i] = row[t + T * i];
-      }
-
-      fft<false>(a, b, tw, lds, t, xbuf);
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        a[i] = conv<CT>(cmul(conv<double>(a[i]), Pp[i]));
-        b[i] = conv<CT>(cmul(conv<double>(b[i]), Pm[i]));
-      }
-      fft<true>(a, b, tw, lds, t, xbuf);
-
-      // Coupling (Eq. fov10) in FP64 where the slab is; samples outside
-      // keep the propagated field (whole-wave vacuum groups branch past).
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        if (inside[i]) {
-          const cx<double> A = conv<double>(a[i]);
-          const cx<double> B = conv<double>(b[i]);
-          cx<double> cp = dp1, cm = dm1;
-          if constexpr (DEFORMED) {
-            const cx<double> ee = {static_cast<double>(e[i].x),
-                                   static_cast<double>(e[i].y)};
-            cp = cmul(dp1, ee);    // d+1 exp(+i h u)
-            cm = cmulc(dm1, ee);   // d-1 exp(-i h u)
+        for (int k1 = 0; k1 < W; ++k1) {
+          if (k1 > 0) {
+            const cx<CT> w = c.twx[j * (W - 1) + k1 - 1];
+            va[k1] = cmul(va[k1], w);
+            vb[k1] = cmul(vb[k1], w);
           }
-          a[i] = conv<CT>(cmuladd(d0, A, cp, B));
-          b[i] = conv<CT>(cmuladd(d0, B, cm, A));
+          In::store(lds + k1 * kRegion, t + T * j, va[k1]);
+          In::store(lds + k1 * kRegion + In::kEnv, t + T * j, vb[k1]);
         }
       }
-      if constexpr (DEFORMED) {
+      lds_barrier();
 #pragma unroll
-        for (int i = 0; i < R; ++i) e[i] = e_next[i];
+      for (int i = 0; i < R; ++i) {
+        a[i] = In::load(own, l + 64 * i);
+        b[i] = In::load(own + In::kEnv, l + 64 * i);
       }
+      wave_sync();
     }
+    In::template fft<false, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
+  }
 
+  __device__ static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
+    const int wv = t >> 6, l = t & 63;
+    SV* own = lds + wv * kRegion;
+    In::template fft<true, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
+    if constexpr (W > 1) {
+      SV* gp = kAlias ? lds : lds + kG;
+      constexpr int kStride = kAlias ? kRegion : 2 * M;
+      constexpr int kB = kAlias ? In::kEnv : M;
+      if constexpr (kAlias) lds_barrier();  // all wavefronts done with scratch
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      SV va, vb;
-      va.x = static_cast<ST>(a[i].x);
-      va.y = static_cast<ST>(a[i].y);
-      vb.x = static_cast<ST>(b[i].x);
-      vb.y = static_cast<ST>(b[i].y);
-      out_a[t + T * i] = va;
-      out_b[t + T * i] = vb;
+      for (int i = 0; i < R; ++i) {
+        In::store(gp + wv * kStride, l + 64 * i, a[i]);
+        In::store(gp + wv * kStride + kB, l + 64 * i, b[i]);
+      }
+      lds_barrier();
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        cx<CT> va[W], vb[W];
+#pragma unroll
+        for (int k1 = 0; k1 < W; ++k1) {
+          va[k1] = In::load(gp + k1 * kStride, t + T * j);
+          vb[k1] = In::load(gp + k1 * kStride + kB, t + T * j);
+          if (k1 > 0) {
+            const cx<CT> w = c.twx[j * (W - 1) + k1 - 1];
+            va[k1] = cmulc(va[k1], w);
+            vb[k1] = cmulc(vb[k1], w);
+          }
+        }
+        dft<W, true>(va);
+        dft<W, true>(vb);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          a[j + J * q] = va[q];
+          b[j + J * q] = vb[q];
+        }
+      }
+      if constexpr (kAlias) lds_barrier();  // exchange read before reuse
     }
   }
 };
 
+// Whole march of one slice by threads t = 0..T-1 of the calling group, for
+// either transform (Eq. fov10 per step, first-order splitting).
+template <class Tr, bool DEFORMED>
+__device__ void march_slice(const MarchParams& p, int slice, int t,
+                            typename Tr::SV* lds) {
+  using CT = typename Tr::CT;
+  using ST = typename Tr::ST;
+  using SV = typename Tr::SV;
+  constexpr int N = Tr::N, R = Tr::R, T = Tr::T;
+  const SliceConst& sc = p.sc[slice];
+  const SV* in = static_cast<const SV*>(p.E0_in) + size_t(slice) * N;
+  SV* out_a = static_cast<SV*>(p.E0_out) + size_t(slice) * N;
+  SV* out_b = static_cast<SV*>(p.Eh_out) + size_t(slice) * N;
+  const SV* table = static_cast<const SV*>(p.table);
+
+  typename Tr::Ctx ctx;
+  Tr::init(ctx, t);
+
+  // Propagators of the bins this thread holds after a forward transform,
+  // 1/Nx of the inverse transform folded in; slab mask of its x samples.
+  cx<double> Pp[R], Pm[R];
+  bool inside[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int k = Tr::bin(t, i);
+    const int ks = k < N / 2 ? k : k - N;
+    Pp[i] = propagator(ks, N, p.dx, sc.k, p.h_half, +1.0, p.dz);
+    Pm[i] = propagator(ks, N, p.dx, sc.k, p.h_half, -1.0, p.dz);
+    const double x = static_cast<double>(t + T * i - N / 2) * p.dx;
+    inside[i] = (x >= p.x_front) && (x < p.x_end);
+  }
+  const cx<double> d0 = {sc.d[0][0], sc.d[0][1]};
+  const cx<double> dp1 = {sc.d[0][2], sc.d[0][3]};
+  const cx<double> dm1 = {sc.d[0][4], sc.d[0][5]};
+
+  cx<CT> a[R], b[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const SV v = in[t + T * i];
+    a[i] = {static_cast<CT>(v.x), static_cast<CT>(v.y)};
+    b[i] = {CT(0), CT(0)};
+  }
+
+  for (int n = 0; n < p.Nz; ++n) {
+    // Row n of exp(i h u), fetched at the start of the step and used by the
+    // coupling at its end, so its latency hides behind the transforms.
+    SV e[R];
+    if constexpr (DEFORMED) {
+      const SV* row = table + size_t(n) * N;
+#pragma unroll
+      for (int i = 0; i < R; ++i) e[i] = row[t + T * i];
+    }
+
+    Tr::forward(a, b, ctx, lds, t);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      a[i] = conv<CT>(cmul(conv<double>(a[i]), Pp[i]));
+      b[i] = conv<CT>(cmul(conv<double>(b[i]), Pm[i]));
+    }
+    Tr::inverse(a, b, ctx, lds, t);
+
+    // Coupling (Eq. fov10) in FP64 where the slab is; samples outside keep
+    // the propagated field (whole-wave vacuum groups branch past).
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (inside[i]) {
+        const cx<double> A = conv<double>(a[i]);
+        const cx<double> B = conv<double>(b[i]);
+        cx<double> cp = dp1, cm = dm1;
+        if constexpr (DEFORMED) {
+          const cx<double> ee = {static_cast<double>(e[i].x),
+                                 static_cast<double>(e[i].y)};
+          cp = cmul(dp1, ee);    // d+1 exp(+i h u)
+          cm = cmulc(dm1, ee);   // d-1 exp(-i h u)
+        }
+        a[i] = conv<CT>(cmuladd(d0, A, cp, B));
+        b[i] = conv<CT>(cmuladd(d0, B, cm, A));
+      }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    SV va, vb;
+    va.x = static_cast<ST>(a[i].x);
+    va.y = static_cast<ST>(a[i].y);
+    vb.x = static_cast<ST>(b[i].x);
+    vb.y = static_cast<ST>(b[i].y);
+    out_a[t + T * i] = va;
+    out_b[t + T * i] = vb;
+  }
+}
+
 template <class M, bool DEFORMED>
 __global__ void __launch_bounds__(M::T) march_kernel(MarchParams p) {
   __shared__ typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
-  M::template run<DEFORMED>(p, blockIdx.x, threadIdx.x, lds);
+  march_slice<M, DEFORMED>(p, blockIdx.x, threadIdx.x, lds);
 }
 
 // Persistent march over a precomputed list of (problem, slice) items: work
@@ -586,9 +756,9 @@ __global__ void __launch_bounds__(M::T)
     const MarchParams p = items[k].p;
     const int slice = items[k].slice;
     if (p.table)
-      M::template run<true>(p, slice, threadIdx.x, lds);
+      march_slice<M, true>(p, slice, threadIdx.x, lds);
     else
-      M::template run<false>(p, slice, threadIdx.x, lds);
+      march_slice<M, false>(p, slice, threadIdx.x, lds);
     lds_barrier();   // LDS of this item fully consumed before the next one
   }
 }
@@ -622,57 +792,61 @@ __global__ void deform_kernel(const double* __restrict__ u, size_t n, double h,
 
 // ------------------------------------------------------------ dispatching --
 
-template <int PREC, int N>
+// Schedules of the z-march transform for each (precision, Nx):
+//   0 -- Stockham: R samples per thread per envelope, one work-group barrier
+//        per pass (radix lists multiply to N);
+//   1 -- four-step: radix-W across W wavefronts and a 256- or 512-point
+//        Stockham inside each wavefront, two barriers per step.
+template <int PREC, int N, int SCHED>
 struct Choice;
-// Radix schedules: R samples per thread per envelope; passes multiply to N.
-template <int PREC>
-struct Choice<PREC, 256> {
-  using type = March<PREC, 256, 4, 4, 4, 4, 4>;
-};
-template <int PREC>
-struct Choice<PREC, 512> {
-  using type = March<PREC, 512, 8, 8, 8, 8>;
-};
-template <int PREC>
-struct Choice<PREC, 1024> {
-  using type = March<PREC, 1024, 8, 8, 8, 4, 4>;
-};
-template <int PREC>
-struct Choice<PREC, 2048> {
-  using type = March<PREC, 2048, 8, 8, 8, 8, 4>;
-};
-template <int PREC>
-struct Choice<PREC, 4096> {
-  using type = March<PREC, 4096, 8, 8, 8, 8, 8>;
-};
+template <int PREC> struct Choice<PREC, 256, 0> { using type = March<PREC, 256, 4, 4, 4, 4, 4>; };
+template <int PREC> struct Choice<PREC, 512, 0> { using type = March<PREC, 512, 8, 8, 8, 8>; };
+template <int PREC> struct Choice<PREC, 1024, 0> { using type = March<PREC, 1024, 8, 8, 8, 4, 4>; };
+template <int PREC> struct Choice<PREC, 2048, 0> { using type = March<PREC, 2048, 8, 8, 8, 8, 4>; };
+template <int PREC> struct Choice<PREC, 4096, 0> { using type = March<PREC, 4096, 8, 8, 8, 8, 8>; };
+template <int PREC> using InWave512 = March<PREC, 512, 8, 8, 8, 8>;
+template <int PREC> using InWave256 = March<PREC, 256, 4, 4, 4, 4, 4>;
+template <int PREC> struct Choice<PREC, 256, 1> { using type = FourStep<PREC, 1, InWave256<PREC>>; };
+template <int PREC> struct Choice<PREC, 512, 1> { using type = FourStep<PREC, 1, InWave512<PREC>>; };
+template <int PREC> struct Choice<PREC, 1024, 1> { using type = FourStep<PREC, 2, InWave512<PREC>>; };
+template <int PREC> struct Choice<PREC, 2048, 1> { using type = FourStep<PREC, 4, InWave512<PREC>>; };
+template <int PREC> struct Choice<PREC, 4096, 1> { using type = FourStep<PREC, 8, InWave512<PREC>>; };
 
-// Calls f(M{}) with the March variant of (precision, Nx).
+// Calls f(M{}) with the transform of (precision, Nx, schedule).
+template <int PREC, int N, class F>
+int with_sched(int sched, F&& f) {
+  switch (sched) {
+    case 0: return f(typename Choice<PREC, N, 0>::type{});
+    case 1: return f(typename Choice<PREC, N, 1>::type{});
+    default: return BPM_EUNSUPPORTED;
+  }
+}
 template <int PREC, class F>
-int with_n(int Nx, F&& f) {
+int with_n(int Nx, int sched, F&& f) {
   switch (Nx) {
-    case 256: return f(typename Choice<PREC, 256>::type{});
-    case 512: return f(typename Choice<PREC, 512>::type{});
-    case 1024: return f(typename Choice<PREC, 1024>::type{});
-    case 2048: return f(typename Choice<PREC, 2048>::type{});
-    case 4096: return f(typename Choice<PREC, 4096>::type{});
+    case 256: return with_sched<PREC, 256>(sched, f);
+    case 512: return with_sched<PREC, 512>(sched, f);
+    case 1024: return with_sched<PREC, 1024>(sched, f);
+    case 2048: return with_sched<PREC, 2048>(sched, f);
+    case 4096: return with_sched<PREC, 4096>(sched, f);
     default: return BPM_EUNSUPPORTED;
   }
 }
 template <class F>
-int with_variant(int prec, int Nx, F&& f) {
+int with_variant(int prec, int Nx, int sched, F&& f) {
   switch (prec) {
-    case BPM_PREC_FP64: return with_n<BPM_PREC_FP64>(Nx, f);
-    case BPM_PREC_FP32: return with_n<BPM_PREC_FP32>(Nx, f);
-    case BPM_PREC_FP32S: return with_n<BPM_PREC_FP32S>(Nx, f);
+    case BPM_PREC_FP64: return with_n<BPM_PREC_FP64>(Nx, sched, f);
+    case BPM_PREC_FP32: return with_n<BPM_PREC_FP32>(Nx, sched, f);
+    case BPM_PREC_FP32S: return with_n<BPM_PREC_FP32S>(Nx, sched, f);
     default: return BPM_EUNSUPPORTED;
   }
 }
 
 }  // namespace
 
-int launch_march(int prec, int Nx, int Nomega, const MarchParams& p,
-                 hipStream_t stream) {
-  return with_variant(prec, Nx, [&](auto m) {
+int launch_march(int prec, int Nx, int sched, int Nomega,
+                 const MarchParams& p, hipStream_t stream) {
+  return with_variant(prec, Nx, sched, [&](auto m) {
     using M = decltype(m);
     if (p.table)
       hipLaunchKernelGGL((march_kernel<M, true>), dim3(Nomega), dim3(M::T), 0,
@@ -684,9 +858,9 @@ int launch_march(int prec, int Nx, int Nomega, const MarchParams& p,
   });
 }
 
-int launch_march_batch(int prec, int Nx, const BatchItem* items,
+int launch_march_batch(int prec, int Nx, int sched, const BatchItem* items,
                        const int* offsets, int n_groups, hipStream_t stream) {
-  return with_variant(prec, Nx, [&](auto m) {
+  return with_variant(prec, Nx, sched, [&](auto m) {
     using M = decltype(m);
     hipLaunchKernelGGL((march_batch_kernel<M>), dim3(n_groups), dim3(M::T), 0,
                        stream, items, offsets);
@@ -694,8 +868,9 @@ int launch_march_batch(int prec, int Nx, const BatchItem* items,
   });
 }
 
-int march_occupancy(int prec, int Nx, int* wg_per_cu, int* threads) {
-  return with_variant(prec, Nx, [&](auto m) {
+int march_occupancy(int prec, int Nx, int sched, int* wg_per_cu,
+                    int* threads) {
+  return with_variant(prec, Nx, sched, [&](auto m) {
     using M = decltype(m);
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -706,6 +881,12 @@ int march_occupancy(int prec, int Nx, int* wg_per_cu, int* threads) {
     *threads = M::T;
     return BPM_OK;
   });
+}
+
+int default_schedule(int prec, int Nx) {
+  (void)prec;
+  (void)Nx;
+  return 1;
 }
 
 int launch_deform(int prec, int Nx, int Nz, double h, const double* u,

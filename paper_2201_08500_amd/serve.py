@@ -1,0 +1,304 @@
+"""Continuous-batching server for z-march requests.
+
+Requests (one problem each: a plan, its incident field and its displacement)
+arrive at any time.  A scheduler thread admits them, in arrival order, as
+device memory (an HBM footprint budget) and in-flight slots allow:
+- it materialises each admitted request's buffers on the device;
+- it packs everything admitted since the last launch into ONE batched
+  persistent launch (bpm_propagate_batch) on a free stream;
+- it polls completion events, so requests that arrive while others run are
+  launched as soon as memory and a slot free up, and their work overlaps
+  the running work on the device.
+
+Every slice runs the same code alone or in any mix, so a request's result
+does not depend on what it was batched with.  Latency is arrival to outputs
+ready (completion event observed).  Outputs stay device-resident.
+
+The device side is a backend object, so the scheduling logic is testable on
+the CPU with a simulated device (tests/test_serve.py); GpuBackend drives
+libbpm.so.
+"""
+
+from __future__ import annotations
+
+import collections
+import math
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+from typing import Any, Optional
+
+
+@dataclass
+class Request:
+    """One problem.  `spec` is backend-specific (GpuBackend: a Workload-like
+    object with plan parameters, E0_in and a displacement description)."""
+    spec: Any
+    precision: str = "fp32s"
+    arrival: float = 0.0                 # server clock (s); set by submit()
+    rid: int = -1
+    footprint: int = 0                   # device bytes while admitted
+    cell_updates: int = 0
+    future: Future = field(default_factory=Future)
+    state: str = "new"                   # new, queued, running, done, failed, cancelled
+    admitted: float = math.nan
+    launched: float = math.nan
+    finished: float = math.nan
+    device: Any = None                   # backend's per-request device state
+
+
+class Server:
+    """Admission by footprint, continuous batching over in-flight slots."""
+
+    def __init__(self, backend, budget_bytes: float = 200e9,
+                 max_in_flight: int = 4, tick_s: float = 0.0005,
+                 max_batch: int = 512):
+        self.backend = backend
+        self.budget = float(budget_bytes)
+        self.max_in_flight = int(max_in_flight)
+        self.tick = float(tick_s)
+        self.max_batch = int(max_batch)
+        self._lock = threading.Lock()
+        self._incoming = collections.deque()
+        self._pending = collections.deque()
+        self._in_flight = []                 # (handle, [requests])
+        self._used = 0.0
+        self._next_id = 0
+        self._t0 = time.perf_counter()
+        self._stop = threading.Event()
+        self._thread = None
+        self.completed = []
+        self.failed = []
+        self.launches = 0
+        self.peak_used = 0.0
+
+    # ---------------------------------------------------------------- API --
+    def now(self) -> float:
+        return time.perf_counter() - self._t0
+
+    def start(self):
+        self._thread = threading.Thread(target=self._run, name="bpm-serve",
+                                        daemon=True)
+        self._thread.start()
+        return self
+
+    def submit(self, req: Request) -> Future:
+        req.footprint = int(self.backend.footprint(req))
+        req.cell_updates = int(self.backend.cell_updates(req))
+        with self._lock:
+            req.rid = self._next_id
+            self._next_id += 1
+            req.arrival = self.now()
+            req.state = "queued"
+            if req.footprint > self.budget:
+                req.state = "failed"
+                req.future.set_exception(MemoryError(
+                    f"request {req.rid} needs {req.footprint} B, more than the "
+                    f"whole budget {self.budget:.0f} B"))
+                self.failed.append(req)
+            else:
+                self._incoming.append(req)
+        return req.future
+
+    def cancel(self, req: Request) -> bool:
+        """Cancel a request that has not been admitted yet."""
+        with self._lock:
+            for q in (self._incoming, self._pending):
+                if req in q:
+                    q.remove(req)
+                    req.state = "cancelled"
+                    req.future.cancel()
+                    return True
+        return False
+
+    def drain(self, timeout: Optional[float] = None) -> bool:
+        """Wait until every submitted request has finished."""
+        t_end = None if timeout is None else time.perf_counter() + timeout
+        while True:
+            with self._lock:
+                busy = self._incoming or self._pending or self._in_flight
+            if not busy:
+                return True
+            if t_end is not None and time.perf_counter() > t_end:
+                return False
+            time.sleep(self.tick)
+
+    def stop(self):
+        self._stop.set()
+        if self._thread is not None:
+            self._thread.join()
+
+    def stats(self) -> dict:
+        done = [r for r in self.completed if r.state == "done"]
+        lat = sorted(r.finished - r.arrival for r in done)
+
+        def pct(p):
+            if not lat:
+                return math.nan
+            k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
+            return lat[k]
+        span = (max(r.finished for r in done) - min(r.arrival for r in done)) if done else math.nan
+        cells = sum(r.cell_updates for r in done)
+        return dict(completed=len(done), failed=len(self.failed),
+                    launches=self.launches, p50_s=pct(50), p99_s=pct(99),
+                    max_s=lat[-1] if lat else math.nan,
+                    cell_updates=cells, span_s=span,
+                    cell_updates_per_s=(cells / span) if done and span > 0 else math.nan,
+                    peak_budget_used=self.peak_used)
+
+    # ---------------------------------------------------------- scheduler --
+    def _run(self):
+        while not self._stop.is_set():
+            progressed = self._poll() | self._admit_and_launch()
+            if not progressed:
+                time.sleep(self.tick)
+
+    def _poll(self) -> bool:
+        done_any = False
+        still = []
+        for handle, reqs in self._in_flight:
+            status = self.backend.poll(handle)
+            if status is None:
+                still.append((handle, reqs))
+                continue
+            done_any = True
+            t = self.now()
+            for r in reqs:
+                r.finished = t
+                self.backend.release(r)
+                with self._lock:
+                    self._used -= r.footprint
+                if status is True:
+                    r.state = "done"
+                    self.completed.append(r)
+                    r.future.set_result(r)
+                else:
+                    r.state = "failed"
+                    self.failed.append(r)
+                    r.future.set_exception(RuntimeError(str(status)))
+        self._in_flight = still
+        return done_any
+
+    def _admit_and_launch(self) -> bool:
+        with self._lock:
+            while self._incoming:
+                self._pending.append(self._incoming.popleft())
+            if len(self._in_flight) >= self.max_in_flight or not self._pending:
+                return False
+            batch = []
+            while (self._pending and len(batch) < self.max_batch
+                   and self._used + self._pending[0].footprint <= self.budget):
+                r = self._pending.popleft()
+                self._used += r.footprint
+                self.peak_used = max(self.peak_used, self._used)
+                r.admitted = self.now()
+                batch.append(r)
+        if not batch:
+            return False
+        ok = []
+        for r in batch:
+            try:
+                self.backend.materialize(r)
+                ok.append(r)
+            except Exception as e:          # noqa: BLE001 -- reported per request
+                self._fail_now(r, e)
+        if not ok:
+            return True
+        try:
+            handle = self.backend.launch(ok)
+        except Exception as e:              # noqa: BLE001
+            for r in ok:
+                self._fail_now(r, e)
+            return True
+        t = self.now()
+        for r in ok:
+            r.launched = t
+            r.state = "running"
+        self._in_flight.append((handle, ok))
+        self.launches += 1
+        return True
+
+    def _fail_now(self, r, err):
+        r.state = "failed"
+        r.finished = self.now()
+        try:
+            self.backend.release(r)
+        finally:
+            with self._lock:
+                self._used -= r.footprint
+            self.failed.append(r)
+            r.future.set_exception(err if isinstance(err, Exception) else RuntimeError(str(err)))
+
+
+class GpuBackend:
+    """Device side over libbpm.so: buffers from torch, one bpm_propagate_batch
+    per launch on a pool of streams, completion by events.
+
+    A request's spec is a Workload-like object (plan parameters, E0_in on the
+    host, `meta['u_factors'] = (row, gz, gx, amp)` describing
+    u[n, j] = row[j] + (amp gz[n]) gx[j], or `u` as an array, or no u)."""
+
+    def __init__(self, streams: int = 4, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self._k = 0
+
+    @staticmethod
+    def _cell(prec):
+        return 16 if prec == "fp64" else 8
+
+    def footprint(self, req) -> int:
+        w = req.spec
+        c = self._cell(req.precision)
+        has_u = w.u is not None or "u_factors" in w.meta
+        per_u = (8 + c) * w.Nz * w.Nx if has_u else 0
+        return per_u + 3 * c * w.Nomega * w.Nx
+
+    def cell_updates(self, req) -> int:
+        w = req.spec
+        return w.Nx * w.Nz * w.Nomega
+
+    def materialize(self, req):
+        from . import Job, Plan
+        torch = self.torch
+        w = req.spec
+        s = self.streams[self._k % len(self.streams)]
+        with torch.cuda.stream(s):
+            plan = Plan.from_workload(w, precision=req.precision)
+            E0 = torch.from_numpy(w.E0_in).to(self.device).to(plan.field_dtype)
+            u = None
+            if w.u is not None:
+                u = torch.from_numpy(w.u).to(self.device)
+            elif "u_factors" in w.meta:
+                row, gz, gx, amp = w.meta["u_factors"]
+                row_t = torch.from_numpy(row).to(self.device)
+                gz_t = torch.from_numpy(gz).to(self.device)
+                gx_t = torch.from_numpy(gx).to(self.device)
+                # same operation order as the host generator
+                u = (row_t[None, :] + (amp * gz_t)[:, None] * gx_t[None, :]).contiguous()
+            req.device = Job(plan, E0, u)
+
+    def launch(self, reqs):
+        from . import propagate_batch
+        torch = self.torch
+        s = self.streams[self._k % len(self.streams)]
+        self._k += 1
+        with torch.cuda.stream(s):
+            propagate_batch([r.device for r in reqs], stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return ev
+
+    def poll(self, ev):
+        return True if ev.query() else None
+
+    def release(self, req):
+        # outputs stay with the request (device-resident); inputs and
+        # workspace go back to the caching allocator
+        j = req.device
+        if j is not None:
+            req.device = None
+            req.outputs = (j.E0_out, j.Eh_out)

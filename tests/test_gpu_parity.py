@@ -31,9 +31,9 @@ def tol64(Nz):
     return 1e-12 + 1e-14 * Nz
 
 
-def gpu_run(w, prec, slices=None, stream=None):
+def gpu_run(w, prec, slices=None, stream=None, schedule=None):
     from paper_2201_08500_amd import Plan
-    p = Plan.from_workload(w, precision=prec)
+    p = Plan.from_workload(w, precision=prec, schedule=schedule)
     dt = p.field_dtype
     E0 = torch.from_numpy(w.E0_in).to(dt).cuda()
     u = None if w.u is None else torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
@@ -54,8 +54,8 @@ def oracle_run(w, prec, slices=None):
     return O.march(O.Problem.from_workload(ws), E0, ws.u)
 
 
-def check(w, prec, slices=None, tol=None):
-    a, b = gpu_run(w, prec, slices)
+def check(w, prec, slices=None, tol=None, schedule=None):
+    a, b = gpu_run(w, prec, slices, schedule=schedule)
     ao, bo = oracle_run(w, prec, slices)
     r = report(a, b, ao, bo)
     print(f"\n{w.name} {prec}: {r}", flush=True)
@@ -67,12 +67,13 @@ def check(w, prec, slices=None, tol=None):
     return r
 
 
+@pytest.mark.parametrize("schedule", ["stockham", "fourstep"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32s", "fp32"])
 @pytest.mark.parametrize("Nx", [256, 512, 1024, 2048, 4096])
 @pytest.mark.parametrize("deformed", [True, False])
-def test_small_parity(Nx, prec, deformed):
+def test_small_parity(Nx, prec, deformed, schedule):
     w = W.small(Nx=Nx, Nz=37, Nomega=3, seed=Nx, deformed=deformed)
-    check(w, prec)
+    check(w, prec, schedule=schedule)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32s"])

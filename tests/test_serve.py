@@ -1,0 +1,185 @@
+"""Scheduling logic of the continuous-batching server, on the CPU with a
+simulated device (no GPU): admission by footprint in arrival order,
+continuous batching while earlier work runs, rejection of oversized
+requests, failure isolation, cancellation and latency statistics."""
+
+import threading
+import time
+
+import pytest
+
+from paper_2201_08500_amd.serve import Request, Server
+
+
+class FakeBackend:
+    """Each launch 'runs' for the sum of its requests' durations / speedup."""
+
+    def __init__(self, fail_launch=None, fail_materialize=None, speedup=1.0):
+        self.lock = threading.Lock()
+        self.launched = []            # list of (t, [rid...])
+        self.live = 0
+        self.max_live = 0
+        self.fail_launch = fail_launch or set()
+        self.fail_materialize = fail_materialize or set()
+        self.speedup = speedup
+        self.n = 0
+
+    def footprint(self, req):
+        return req.spec["bytes"]
+
+    def cell_updates(self, req):
+        return req.spec.get("cells", 1)
+
+    def materialize(self, req):
+        if req.spec.get("name") in self.fail_materialize:
+            raise RuntimeError("materialize failed")
+        req.device = object()
+
+    def launch(self, reqs):
+        with self.lock:
+            k = self.n
+            self.n += 1
+            self.live += 1
+            self.max_live = max(self.max_live, self.live)
+        if k in self.fail_launch:
+            with self.lock:
+                self.live -= 1
+            raise RuntimeError("launch failed")
+        dur = max(r.spec.get("dur", 0.01) for r in reqs) / self.speedup
+        self.launched.append((time.perf_counter(), [r.spec["name"] for r in reqs]))
+        return time.perf_counter() + dur
+
+    def poll(self, handle):
+        if time.perf_counter() >= handle:
+            with self.lock:
+                self.live -= 1
+            return True
+        return None
+
+    def release(self, req):
+        req.device = None
+
+
+def req(name, nbytes, dur=0.01):
+    return Request(spec=dict(name=name, bytes=nbytes, dur=dur))
+
+
+def test_admission_by_footprint_in_arrival_order():
+    be = FakeBackend()
+    srv = Server(be, budget_bytes=100, max_in_flight=4).start()
+    try:
+        a = req("a", 60, 0.15)
+        b = req("b", 60, 0.01)     # does not fit while a runs
+        c = req("c", 30, 0.01)     # would fit, but waits behind b (FIFO)
+        for r in (a, b, c):
+            srv.submit(r)
+            time.sleep(0.01)
+        assert srv.drain(timeout=5)
+        order = [names for _, names in be.launched]
+        assert order[0] == ["a"]
+        flat = [n for names in order for n in names]
+        assert flat.index("b") < flat.index("c")
+        assert srv.peak_used <= 100
+        assert b.admitted >= a.finished - 1e-3
+    finally:
+        srv.stop()
+
+
+def test_continuous_batching_packs_arrivals_while_others_run():
+    be = FakeBackend()
+    srv = Server(be, budget_bytes=1e9, max_in_flight=2).start()
+    try:
+        first = req("first", 10, 0.2)
+        srv.submit(first)
+        time.sleep(0.02)
+        later = [req(f"r{i}", 10, 0.05) for i in range(6)]
+        for r in later:
+            srv.submit(r)
+        assert srv.drain(timeout=5)
+        # the six late arrivals were launched while `first` was still running,
+        # packed into few launches
+        assert max(r.launched for r in later) < first.finished
+        assert len(be.launched) <= 3
+        assert be.max_live == 2
+        assert all(r.state == "done" for r in [first] + later)
+    finally:
+        srv.stop()
+
+
+def test_oversized_request_is_rejected_at_submit():
+    srv = Server(FakeBackend(), budget_bytes=100).start()
+    try:
+        r = req("big", 101)
+        f = srv.submit(r)
+        with pytest.raises(MemoryError):
+            f.result(timeout=1)
+        ok = req("ok", 50)
+        assert srv.submit(ok).result(timeout=5) is ok
+    finally:
+        srv.stop()
+
+
+def test_failed_launch_fails_only_its_requests():
+    be = FakeBackend(fail_launch={0})
+    srv = Server(be, budget_bytes=1e9, max_in_flight=1).start()
+    try:
+        a = req("a", 10)
+        fa = srv.submit(a)
+        with pytest.raises(RuntimeError):
+            fa.result(timeout=5)
+        b = req("b", 10)
+        assert srv.submit(b).result(timeout=5) is b
+        assert a.state == "failed" and b.state == "done"
+        assert srv.drain(timeout=5)
+        assert srv._used == 0
+    finally:
+        srv.stop()
+
+
+def test_failed_materialize_is_isolated():
+    be = FakeBackend(fail_materialize={"bad"})
+    srv = Server(be, budget_bytes=1e9).start()
+    try:
+        bad, good = req("bad", 10), req("good", 10)
+        fb, fg = srv.submit(bad), srv.submit(good)
+        with pytest.raises(RuntimeError):
+            fb.result(timeout=5)
+        assert fg.result(timeout=5) is good
+        assert srv.drain(timeout=5) and srv._used == 0
+    finally:
+        srv.stop()
+
+
+def test_cancel_before_admission():
+    be = FakeBackend()
+    srv = Server(be, budget_bytes=100, max_in_flight=1).start()
+    try:
+        a = req("a", 90, 0.2)
+        b = req("b", 90, 0.01)
+        srv.submit(a)
+        time.sleep(0.02)
+        fb = srv.submit(b)
+        assert srv.cancel(b)
+        assert fb.cancelled()
+        assert srv.drain(timeout=5)
+        assert all("b" not in names for _, names in be.launched)
+        assert not srv.cancel(a)           # already admitted
+    finally:
+        srv.stop()
+
+
+def test_latency_statistics():
+    be = FakeBackend()
+    srv = Server(be, budget_bytes=1e9, max_in_flight=4).start()
+    try:
+        rs = [Request(spec=dict(name=str(i), bytes=1, dur=0.01, cells=100))
+              for i in range(20)]
+        for r in rs:
+            srv.submit(r)
+        assert srv.drain(timeout=5)
+        st = srv.stats()
+        assert st["completed"] == 20 and st["failed"] == 0
+        assert 0 < st["p50_s"] <= st["p99_s"] <= st["max_s"]
+        assert st["cell_updates"] == 2000
+    finally:
+        srv.stop()
