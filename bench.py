@@ -229,6 +229,81 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
+def bench_serve(args):
+    """Served request stream: Poisson arrivals (seeded), sizes as the uneven
+    batch, half fp64 and half fp32-storage requests, admission by an HBM
+    footprint budget, continuous batching over in-flight slots.  Reports
+    p50/p99 latency (arrival to outputs ready) and cell-updates/s."""
+    import queue
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2201_08500_amd.serve import GpuBackend, Request, Server
+
+    torch.cuda.set_device(0)
+    trace = W.c5_request_trace(rate=args.serve_rate, duration=args.serve_duration,
+                               seed=5)
+    prec_map = {"fp64": "fp64", "fp32": args.serve_fp32}
+    if args.serve_all_fp64:
+        prec_map = {"fp64": "fp64", "fp32": "fp64"}
+    backend = GpuBackend(streams=args.serve_streams, keep_outputs=False)
+    srv = Server(backend, budget_bytes=args.serve_budget_gb * 1e9,
+                 max_in_flight=args.serve_streams)
+    # warm the kernels once outside the measured stream
+    for prec in set(prec_map.values()):
+        w0 = W.small(Nx=256, Nz=4, Nomega=1)
+        srv.backend.materialize(Request(spec=w0, precision=prec))
+    torch.cuda.synchronize()
+    srv.start()
+    pool = ThreadPoolExecutor(max_workers=6)
+    futs = [pool.submit(W.c4_problem, spec, False) for _, spec, _ in trace[:64]]
+    nxt = 64
+    t0 = time.perf_counter()
+    submitted = []
+    last_note = t0
+    for i, (t_arr, spec, prec) in enumerate(trace):
+        w = futs[i].result()
+        futs[i] = None
+        if nxt < len(trace):
+            futs.append(pool.submit(W.c4_problem, trace[nxt][1], False))
+            nxt += 1
+        delay = t0 + t_arr - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        r = Request(spec=w, precision=prec_map[prec])
+        srv.submit(r)
+        submitted.append(r)
+        if time.perf_counter() - last_note > 10:
+            last_note = time.perf_counter()
+            print(f"[bench] serve: {i + 1}/{len(trace)} submitted, "
+                  f"{len(srv.completed)} done", file=sys.stderr, flush=True)
+    lag = time.perf_counter() - t0 - trace[-1][0]
+    while not srv.drain(timeout=10):
+        print(f"[bench] serve: draining, {len(srv.completed)} done",
+              file=sys.stderr, flush=True)
+    srv.stop()
+    pool.shutdown()
+    st = srv.stats()
+    line = {
+        "metric": METRIC, "value": st["cell_updates_per_s"], "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": len(trace), "warmup": 0,
+        "ms_per_step": st["p50_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed f64" if not args.serve_all_fp64 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"served-stream-{args.serve_rate:g}rps-{args.serve_duration:g}s",
+                   "precisions": sorted(set(prec_map.values())),
+                   "budget_GB": args.serve_budget_gb, "streams": args.serve_streams},
+        "serve": dict(st, requests=len(trace), submit_lag_s=lag,
+                      offered_cell_updates_per_s=sum(
+                          s["Nx"] * s["Nz"] * s["Nomega"] for _, s, _ in trace)
+                      / args.serve_duration),
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,7 +317,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices-per-core", type=int, default=96)
     ap.add_argument("--workload", default="bent-crystal",
-                    choices=["bent-crystal", "batch"])
+                    choices=["bent-crystal", "batch", "serve"])
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-duration", type=float, default=60.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-fp32", default="fp32s", choices=["fp32s", "fp32"],
+                    help="precision used for the stream's FP32 requests")
+    ap.add_argument("--serve-all-fp64", action="store_true",
+                    help="run every request of the same trace in fp64")
     ap.add_argument("--batch-problems", type=int, default=512)
     ap.add_argument("--batch-compare", action="store_true",
                     help="also time the same jobs run one after another")
@@ -259,6 +342,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
 
     import numpy as np

@@ -68,8 +68,12 @@ enum {
  * STOCKHAM -- radix-R Stockham passes, one work-group barrier per pass;
  * FOURSTEP -- radix-W across the W wavefronts of a slice plus a Stockham
  * transform inside each wavefront, two barriers per z-step;
+ * SPLIT -- FOURSTEP with the two envelopes on separate wavefronts (twice the
+ * wavefronts, half the registers each) for Nx = 1024 and 2048, FOURSTEP
+ * otherwise;
  * AUTO -- the library's measured default for (precision, Nx). */
-enum { BPM_SCHED_AUTO = -1, BPM_SCHED_STOCKHAM = 0, BPM_SCHED_FOURSTEP = 1 };
+enum { BPM_SCHED_AUTO = -1, BPM_SCHED_STOCKHAM = 0, BPM_SCHED_FOURSTEP = 1,
+       BPM_SCHED_SPLIT = 2 };
 
 /* Create a plan for Nomega slices of an Nx-point window (Section 2.1 problem
  * statement: grid dx, step dz, Nz steps, susceptibilities chi0, chih,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbpm.so")
 
 BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_EUNSUPPORTED = 0, -1, -2, -3, -4
 PRECISION = {"fp64": 0, "fp32": 1, "fp32s": 2}
-SCHEDULE = {"auto": -1, "stockham": 0, "fourstep": 1}
+SCHEDULE = {"auto": -1, "stockham": 0, "fourstep": 1, "split": 2}
 _CODES = {BPM_EINVAL: "EINVAL", BPM_ENOMEM: "ENOMEM", BPM_EHIP: "EHIP",
           BPM_EUNSUPPORTED: "EUNSUPPORTED"}
 

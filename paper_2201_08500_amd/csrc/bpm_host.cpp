@@ -452,7 +452,7 @@ int bpm_plan_set_schedule(bpm_plan* p, int schedule) {
   int rc = check_mutable(p);
   if (rc) return rc;
   if (schedule != BPM_SCHED_AUTO && schedule != BPM_SCHED_STOCKHAM &&
-      schedule != BPM_SCHED_FOURSTEP)
+      schedule != BPM_SCHED_FOURSTEP && schedule != BPM_SCHED_SPLIT)
     return fail(BPM_EINVAL, "unknown schedule");
   p->schedule = schedule;
   return BPM_OK;

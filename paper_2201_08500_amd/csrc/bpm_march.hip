@@ -303,6 +303,7 @@ struct vec2<double> {
 
 template <int PREC, int N_, int R_, int... RADS>
 struct March {
+  static constexpr bool kSplit = false;
   static constexpr int N = N_;  // transform length
   static constexpr int R = R_;  // samples per thread per envelope
   using CT = typename Prec<PREC>::CT;
@@ -375,45 +376,39 @@ struct March {
   enum { kDouble = 0, kSingle = 1, kWave = 2 };
   static constexpr int kSync = NBUF == 2 ? kDouble : kSingle;
 
-  template <int P, bool INV, int SYNC = kSync>
-  __device__ static void pass(Reg& a, Reg& b, const cx<CT> (&tw)[NTW],
-                              SV* lds, int t, int& xbuf) {
+  // Stockham pass P over NE envelopes v[e] (LDS region e at lds + e kEnv).
+  template <int P, bool INV, int SYNC, int NE>
+  __device__ static void pass_n(cx<CT> (&v)[NE][R], const cx<CT> (&tw)[NTW],
+                                SV* lds, int t, int& xbuf) {
     constexpr int Rp = rad[P];
     constexpr int Ns = ns(P);
     constexpr int G = R / Rp;
     constexpr bool last = (P == NP - 1);
     constexpr int D = pad_div(P);
-    SV* la = lds + (SYNC == kDouble ? xbuf * 2 * kEnv : 0);
-    SV* lb = la + kEnv;
+    SV* base_lds = lds + (SYNC == kDouble ? xbuf * NE * kEnv : 0);
 #pragma unroll
     for (int s = 0; s < G; ++s) {
-      cx<CT> va[Rp], vb[Rp];
+      cx<CT> u[NE][Rp];
 #pragma unroll
-      for (int r = 0; r < Rp; ++r) {
-        va[r] = a[s + r * G];
-        vb[r] = b[s + r * G];
-      }
+      for (int e = 0; e < NE; ++e)
+#pragma unroll
+        for (int r = 0; r < Rp; ++r) u[e][r] = v[e][s + r * G];
       if constexpr (P > 0) {
 #pragma unroll
         for (int r = 1; r < Rp; ++r) {
           const cx<CT> w = tw[tw_off(P) + s * (Rp - 1) + (r - 1)];
-          if constexpr (INV) {
-            va[r] = cmulc(va[r], w);
-            vb[r] = cmulc(vb[r], w);
-          } else {
-            va[r] = cmul(va[r], w);
-            vb[r] = cmul(vb[r], w);
-          }
+#pragma unroll
+          for (int e = 0; e < NE; ++e)
+            u[e][r] = INV ? cmulc(u[e][r], w) : cmul(u[e][r], w);
         }
       }
-      dft<Rp, INV>(va);
-      dft<Rp, INV>(vb);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) dft<Rp, INV>(u[e]);
       if constexpr (last) {
 #pragma unroll
-        for (int r = 0; r < Rp; ++r) {
-          a[s + r * G] = va[r];
-          b[s + r * G] = vb[r];
-        }
+        for (int e = 0; e < NE; ++e)
+#pragma unroll
+          for (int r = 0; r < Rp; ++r) v[e][s + r * G] = u[e][r];
       } else {
         const int jb = t + s * T;
         const int base = (jb / Ns) * Ns * Rp + (jb % Ns);
@@ -421,8 +416,8 @@ struct March {
         for (int r = 0; r < Rp; ++r) {
           const int idx = base + r * Ns;
           const int slot = idx + Ns * (idx / D);
-          store(la, slot, va[r]);
-          store(lb, slot, vb[r]);
+#pragma unroll
+          for (int e = 0; e < NE; ++e) store(base_lds + e * kEnv, slot, u[e][r]);
         }
       }
     }
@@ -435,8 +430,8 @@ struct March {
       for (int i = 0; i < R; ++i) {
         const int idx = t + T * i;
         const int slot = idx + Ns * (idx / D);
-        a[i] = load(la, slot);
-        b[i] = load(lb, slot);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) v[e][i] = load(base_lds + e * kEnv, slot);
       }
       if constexpr (SYNC == kSingle) {
         lds_barrier();
@@ -448,17 +443,35 @@ struct March {
     }
   }
 
-  template <bool INV, int SYNC, int... P>
-  __device__ static void fft_impl(Reg& a, Reg& b, const cx<CT> (&tw)[NTW],
+  template <bool INV, int SYNC, int NE, int... P>
+  __device__ static void fft_impl(cx<CT> (&v)[NE][R], const cx<CT> (&tw)[NTW],
                                   SV* lds, int t, int& xbuf,
                                   std::integer_sequence<int, P...>) {
-    (pass<P, INV, SYNC>(a, b, tw, lds, t, xbuf), ...);
+    (pass_n<P, INV, SYNC, NE>(v, tw, lds, t, xbuf), ...);
   }
+  // In-place transform of NE envelopes.
+  template <bool INV, int SYNC, int NE>
+  __device__ static void fft_n(cx<CT> (&v)[NE][R], const cx<CT> (&tw)[NTW],
+                               SV* lds, int t, int& xbuf) {
+    fft_impl<INV, SYNC, NE>(v, tw, lds, t, xbuf,
+                            std::make_integer_sequence<int, NP>{});
+  }
+  // Both envelopes (psi~_+ in a, psi~_- in b).
   template <bool INV, int SYNC = kSync>
   __device__ static void fft(Reg& a, Reg& b, const cx<CT> (&tw)[NTW], SV* lds,
                              int t, int& xbuf) {
-    fft_impl<INV, SYNC>(a, b, tw, lds, t, xbuf,
-                        std::make_integer_sequence<int, NP>{});
+    cx<CT> v[2][R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      v[0][i] = a[i];
+      v[1][i] = b[i];
+    }
+    fft_n<INV, SYNC, 2>(v, tw, lds, t, xbuf);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      a[i] = v[0][i];
+      b[i] = v[1][i];
+    }
   }
 
   // Twiddles W_{Ns Rp}^{r (jb mod Ns)} of every pass after the first.
@@ -524,6 +537,7 @@ struct March {
 // lane l in wavefront w ends with bin K = w + W (l + 64 i).
 template <int PREC, int W, class In>
 struct FourStep {
+  static constexpr bool kSplit = false;
   using CT = typename Prec<PREC>::CT;
   using ST = typename Prec<PREC>::ST;
   using SV = typename vec2<ST>::type;
@@ -642,11 +656,166 @@ struct FourStep {
   }
 };
 
+// Envelope-split four-step march of one slice: 2 W wavefronts, wavefronts
+// 0..W-1 carry psi~_+ and W..2W-1 carry psi~_-, each with the radix-W
+// cross-wavefront step and an M-point in-wavefront transform of its own
+// envelope.  Twice the wavefronts of FourStep at half the registers each, so
+// two wavefronts share every SIMD and hide each other's LDS latency.  After
+// the inverse exchange every thread rebuilds BOTH envelopes at its x samples
+// (the cross-wavefront inverse DFT is done twice, a small cost) so that the
+// coupling needs no further exchange: two work-group barriers per z-step.
+template <int PREC, int W, class In>
+struct Split4 {
+  using CT = typename Prec<PREC>::CT;
+  using ST = typename Prec<PREC>::ST;
+  using SV = typename vec2<ST>::type;
+  static_assert(In::T == 64 && W >= 2, "split march needs W >= 2 wavefronts");
+  static constexpr bool kSplit = true;
+  static constexpr int M = In::N;
+  static constexpr int R = In::R;
+  static constexpr int N = W * M;
+  static constexpr int T0 = 64 * W;   // threads per envelope
+  static constexpr int T = 2 * T0;
+  static constexpr int J = R / W;
+  static_assert(R % W == 0, "");
+  static constexpr size_t kG = size_t(2) * W * In::kEnv;   // scratch + fwd
+  static constexpr size_t kGp = size_t(2) * W * M;          // inverse
+  static constexpr size_t kLdsBytes = (kG + kGp) * sizeof(SV);
+  static_assert(kLdsBytes <= 160 * 1024, "split march does not fit in LDS");
+
+  template <bool DEFORMED>
+  __device__ static void run(const MarchParams& p, int slice, int t, SV* lds) {
+    const int e = t >= T0 ? 1 : 0;     // 0: psi~_+, 1: psi~_-
+    const int t0 = t - e * T0;
+    const int wv = t0 >> 6, l = t0 & 63;
+    const SliceConst& sc = p.sc[slice];
+    const SV* in = static_cast<const SV*>(p.E0_in) + size_t(slice) * N;
+    SV* out = static_cast<SV*>(e ? p.Eh_out : p.E0_out) + size_t(slice) * N;
+    const SV* table = static_cast<const SV*>(p.table);
+    SV* G = lds;
+    SV* Gp = lds + kG;
+    SV* own = G + (e * W + wv) * In::kEnv;
+
+    typename In::Ctx ic;
+    In::init(ic, l);
+    cx<CT> twx[J * (W - 1)];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+      for (int k1 = 1; k1 < W; ++k1) {
+        double sn, cs;
+        sincospi(-2.0 * double((t0 + T0 * j) * k1) / double(N), &sn, &cs);
+        twx[j * (W - 1) + k1 - 1] = {static_cast<CT>(cs), static_cast<CT>(sn)};
+      }
+    // own band's propagator at the bins of (wavefront wv, lane l, slot i)
+    cx<double> P[R];
+    bool inside[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int k = wv + W * (l + 64 * i);
+      const int ks = k < N / 2 ? k : k - N;
+      P[i] = propagator(ks, N, p.dx, sc.k, p.h_half, e ? -1.0 : 1.0, p.dz);
+      const double x = static_cast<double>(t0 + T0 * i - N / 2) * p.dx;
+      inside[i] = (x >= p.x_front) && (x < p.x_end);
+    }
+    const cx<double> d0 = {sc.d[0][0], sc.d[0][1]};
+    // coefficient of the other envelope in this envelope's update
+    const cx<double> dx = e ? cx<double>{sc.d[0][4], sc.d[0][5]}
+                            : cx<double>{sc.d[0][2], sc.d[0][3]};
+
+    cx<CT> v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (e == 0) {
+        const SV s = in[t0 + T0 * i];
+        v[i] = {static_cast<CT>(s.x), static_cast<CT>(s.y)};
+      } else {
+        v[i] = {CT(0), CT(0)};
+      }
+    }
+
+    for (int n = 0; n < p.Nz; ++n) {
+      SV er[R];
+      if constexpr (DEFORMED) {
+        const SV* row = table + size_t(n) * N;
+#pragma unroll
+        for (int i = 0; i < R; ++i) er[i] = row[t0 + T0 * i];
+      }
+      // forward: radix-W across wavefronts of this envelope, exchange
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        cx<CT> u[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) u[q] = v[j + J * q];
+        dft<W, false>(u);
+#pragma unroll
+        for (int k1 = 0; k1 < W; ++k1) {
+          if (k1 > 0) u[k1] = cmul(u[k1], twx[j * (W - 1) + k1 - 1]);
+          In::store(G + (e * W + k1) * In::kEnv, t0 + T0 * j, u[k1]);
+        }
+      }
+      lds_barrier();
+      cx<CT> z[1][R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) z[0][i] = In::load(own, l + 64 * i);
+      wave_sync();
+      In::template fft_n<false, In::kWave, 1>(z, ic.tw, own, l, ic.xbuf);
+#pragma unroll
+      for (int i = 0; i < R; ++i) z[0][i] = conv<CT>(cmul(conv<double>(z[0][i]), P[i]));
+      In::template fft_n<true, In::kWave, 1>(z, ic.tw, own, l, ic.xbuf);
+#pragma unroll
+      for (int i = 0; i < R; ++i) In::store(Gp + (e * W + wv) * M, l + 64 * i, z[0][i]);
+      lds_barrier();
+      // inverse radix-W for both envelopes at this thread's x samples, and
+      // the coupling (Eq. fov10) of each group of W samples right away
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        cx<CT> ua[W], ub[W];
+#pragma unroll
+        for (int k1 = 0; k1 < W; ++k1) {
+          ua[k1] = In::load(Gp + k1 * M, t0 + T0 * j);
+          ub[k1] = In::load(Gp + (W + k1) * M, t0 + T0 * j);
+          if (k1 > 0) {
+            ua[k1] = cmulc(ua[k1], twx[j * (W - 1) + k1 - 1]);
+            ub[k1] = cmulc(ub[k1], twx[j * (W - 1) + k1 - 1]);
+          }
+        }
+        dft<W, true>(ua);
+        dft<W, true>(ub);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const int i = j + J * q;
+          const cx<CT> self = e ? ub[q] : ua[q];
+          const cx<CT> other = e ? ua[q] : ub[q];
+          v[i] = self;
+          if (inside[i]) {
+            cx<double> c = dx;
+            if constexpr (DEFORMED) {
+              const cx<double> ee = {static_cast<double>(er[i].x),
+                                     static_cast<double>(er[i].y)};
+              c = e ? cmulc(dx, ee) : cmul(dx, ee);
+            }
+            v[i] = conv<CT>(cmuladd(d0, conv<double>(self), c, conv<double>(other)));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      SV s;
+      s.x = static_cast<ST>(v[i].x);
+      s.y = static_cast<ST>(v[i].y);
+      out[t0 + T0 * i] = s;
+    }
+  }
+};
+
 // Whole march of one slice by threads t = 0..T-1 of the calling group, for
 // either transform (Eq. fov10 per step, first-order splitting).
+// March of one slice with both envelopes in every thread.
 template <class Tr, bool DEFORMED>
-__device__ void march_slice(const MarchParams& p, int slice, int t,
-                            typename Tr::SV* lds) {
+__device__ void march_slice_joint(const MarchParams& p, int slice, int t,
+                                  typename Tr::SV* lds) {
   using CT = typename Tr::CT;
   using ST = typename Tr::ST;
   using SV = typename Tr::SV;
@@ -735,6 +904,16 @@ __device__ void march_slice(const MarchParams& p, int slice, int t,
   }
 }
 
+template <class Tr, bool DEFORMED>
+__device__ void march_slice(const MarchParams& p, int slice, int t,
+                            typename Tr::SV* lds) {
+  if constexpr (Tr::kSplit) {
+    Tr::template run<DEFORMED>(p, slice, t, lds);
+  } else {
+    march_slice_joint<Tr, DEFORMED>(p, slice, t, lds);
+  }
+}
+
 template <class M, bool DEFORMED>
 __global__ void __launch_bounds__(M::T) march_kernel(MarchParams p) {
   __shared__ typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
@@ -811,6 +990,12 @@ template <int PREC> struct Choice<PREC, 512, 1> { using type = FourStep<PREC, 1,
 template <int PREC> struct Choice<PREC, 1024, 1> { using type = FourStep<PREC, 2, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 2048, 1> { using type = FourStep<PREC, 4, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 4096, 1> { using type = FourStep<PREC, 8, InWave512<PREC>>; };
+// 2 -- envelope-split four-step (2W wavefronts) where it fits, else four-step
+template <int PREC> struct Choice<PREC, 256, 2> { using type = typename Choice<PREC, 256, 1>::type; };
+template <int PREC> struct Choice<PREC, 512, 2> { using type = typename Choice<PREC, 512, 1>::type; };
+template <int PREC> struct Choice<PREC, 1024, 2> { using type = Split4<PREC, 2, InWave512<PREC>>; };
+template <int PREC> struct Choice<PREC, 2048, 2> { using type = Split4<PREC, 4, InWave512<PREC>>; };
+template <int PREC> struct Choice<PREC, 4096, 2> { using type = typename Choice<PREC, 4096, 1>::type; };
 
 // Calls f(M{}) with the transform of (precision, Nx, schedule).
 template <int PREC, int N, class F>
@@ -818,6 +1003,7 @@ int with_sched(int sched, F&& f) {
   switch (sched) {
     case 0: return f(typename Choice<PREC, N, 0>::type{});
     case 1: return f(typename Choice<PREC, N, 1>::type{});
+    case 2: return f(typename Choice<PREC, N, 2>::type{});
     default: return BPM_EUNSUPPORTED;
   }
 }
@@ -883,10 +1069,12 @@ int march_occupancy(int prec, int Nx, int sched, int* wg_per_cu,
   });
 }
 
+// Measured defaults (cell-updates/s on MI355X, Nz = 1000, >= 256 slices):
+// the envelope-split four-step is fastest where it exists (Nx 1024, 2048),
+// the four-step elsewhere.
 int default_schedule(int prec, int Nx) {
   (void)prec;
-  (void)Nx;
-  return 1;
+  return (Nx == 1024 || Nx == 2048) ? 2 : 1;
 }
 
 int launch_deform(int prec, int Nx, int Nz, double h, const double* u,

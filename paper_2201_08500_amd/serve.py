@@ -64,6 +64,7 @@ class Server:
         self._pending = collections.deque()
         self._in_flight = []                 # (handle, [requests])
         self._used = 0.0
+        self._active = 0                     # admitted and not finished
         self._next_id = 0
         self._t0 = time.perf_counter()
         self._stop = threading.Event()
@@ -117,7 +118,7 @@ class Server:
         t_end = None if timeout is None else time.perf_counter() + timeout
         while True:
             with self._lock:
-                busy = self._incoming or self._pending or self._in_flight
+                busy = self._incoming or self._pending or self._active
             if not busy:
                 return True
             if t_end is not None and time.perf_counter() > t_end:
@@ -167,8 +168,6 @@ class Server:
             for r in reqs:
                 r.finished = t
                 self.backend.release(r)
-                with self._lock:
-                    self._used -= r.footprint
                 if status is True:
                     r.state = "done"
                     self.completed.append(r)
@@ -177,6 +176,9 @@ class Server:
                     r.state = "failed"
                     self.failed.append(r)
                     r.future.set_exception(RuntimeError(str(status)))
+                with self._lock:
+                    self._used -= r.footprint
+                    self._active -= 1
         self._in_flight = still
         return done_any
 
@@ -191,6 +193,7 @@ class Server:
                    and self._used + self._pending[0].footprint <= self.budget):
                 r = self._pending.popleft()
                 self._used += r.footprint
+                self._active += 1
                 self.peak_used = max(self.peak_used, self._used)
                 r.admitted = self.now()
                 batch.append(r)
@@ -225,9 +228,10 @@ class Server:
         try:
             self.backend.release(r)
         finally:
+            self.failed.append(r)
             with self._lock:
                 self._used -= r.footprint
-            self.failed.append(r)
+                self._active -= 1
             r.future.set_exception(err if isinstance(err, Exception) else RuntimeError(str(err)))
 
 
@@ -239,8 +243,9 @@ class GpuBackend:
     host, `meta['u_factors'] = (row, gz, gx, amp)` describing
     u[n, j] = row[j] + (amp gz[n]) gx[j], or `u` as an array, or no u)."""
 
-    def __init__(self, streams: int = 4, device: int = 0):
+    def __init__(self, streams: int = 4, device: int = 0, keep_outputs=True):
         import torch
+        self.keep_outputs = keep_outputs
         self.torch = torch
         self.device = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
@@ -296,9 +301,9 @@ class GpuBackend:
         return True if ev.query() else None
 
     def release(self, req):
-        # outputs stay with the request (device-resident); inputs and
-        # workspace go back to the caching allocator
+        # inputs and workspace go back to the caching allocator; the outputs
+        # stay with the request (device-resident) unless keep_outputs is off
         j = req.device
         if j is not None:
             req.device = None
-            req.outputs = (j.E0_out, j.Eh_out)
+            req.outputs = (j.E0_out, j.Eh_out) if self.keep_outputs else None

@@ -67,7 +67,7 @@ def check(w, prec, slices=None, tol=None, schedule=None):
     return r
 
 
-@pytest.mark.parametrize("schedule", ["stockham", "fourstep"])
+@pytest.mark.parametrize("schedule", ["stockham", "fourstep", "split"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32s", "fp32"])
 @pytest.mark.parametrize("Nx", [256, 512, 1024, 2048, 4096])
 @pytest.mark.parametrize("deformed", [True, False])

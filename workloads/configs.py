@@ -114,11 +114,10 @@ def incident_envelope(Nx, dx, lam, theta_B, delta, theta_i, amp,
     k0 = 2.0 * math.pi / lam
     h = 2.0 * k0 * math.sin(theta_B)
     g = np.exp(-((x - x0) / w0) ** 2)
-    out = np.empty((len(delta), Nx), dtype=np.complex128)
-    for w, d in enumerate(delta):
-        tilt = k0 * (1.0 + d) * math.sin(theta_i) - 0.5 * h
-        out[w] = amp[w] * g * np.exp(1j * tilt * x)
-    return out
+    d = np.asarray(delta, dtype=np.float64)
+    tilt = k0 * (1.0 + d) * math.sin(theta_i) - 0.5 * h
+    amp = np.asarray(amp, dtype=np.complex128)
+    return (amp[:, None] * g[None, :]) * np.exp(1j * (tilt[:, None] * x[None, :]))
 
 
 def pulse_amplitudes(delta, lam, sigma_t, rng, phase_amp=0.1) -> np.ndarray:
