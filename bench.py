@@ -39,14 +39,33 @@ def flops_per_cell_update(Nx: int) -> float:
     return 4 * 5 * math.log2(Nx) + 2 * 6 + (6 * 6 + 2 * 2)
 
 
-def lds_bytes_per_cell_update(Nx: int, storage_bytes: int, passes: int) -> float:
-    """LDS traffic of the kernel design: every exchange between Stockham
-    passes writes and reads each complex sample once, for two envelopes and
-    two transform directions."""
-    return 2 * 2 * (passes - 1) * 2 * 2 * storage_bytes
+def lds_bytes_per_cell_update(Nx: int, storage_bytes: int) -> float:
+    """LDS bytes per cell-update of the default (envelope-split four-step)
+    schedule at Nx = 1024/2048: per envelope and z-step, two work-group
+    exchanges (each sample written and read once; the inverse exchange is
+    read by both envelopes' threads) and four wavefront-local Stockham
+    exchanges of the 512-point inner transform."""
+    accesses = 2 + 4 + 4 + 3   # fwd exchange, 2x2 local fwd, 2x2 local inv, inv exchange
+    return 2 * accesses * storage_bytes
 
 
-PASSES = {256: 4, 512: 3, 1024: 4, 2048: 4, 4096: 4}
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per march launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record (scaled by the reference copy), or None when that
+    record is missing or was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"march_{workload}_traffic.json")
+    src = os.path.join(ROOT, "paper_2201_08500_amd", "csrc", "bpm_march.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha or rec.get("precision") != precision:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def _cpu_worker(args):
@@ -361,11 +380,15 @@ def main():
         variants.insert(0, args.headline)
 
     if args.copy_probe_mib:
+        # reference device copy of known size for scaling HBM byte counters;
+        # a 1 GiB fill in between evicts the source from the 256 MB MALL
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        flush = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, flush
 
     results = {}
     for prec in variants:
@@ -408,7 +431,7 @@ def main():
     F = flops_per_cell_update(w.Nx)
     achieved = F * cells / (head["march_ms"] / 1e3) / 1e12
     peak = PEAK_TFLOPS[dtype]
-    lds_b = lds_bytes_per_cell_update(w.Nx, storage // 2, PASSES[w.Nx])
+    lds_b = lds_bytes_per_cell_update(w.Nx, storage)
     line = {
         "metric": METRIC,
         "value": cells * args.steps / head["total_s"],
@@ -426,7 +449,9 @@ def main():
                    "Nomega": w.Nomega, "precision": args.headline,
                    "storage": "complex64" if storage == 8 else "complex128"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(w.name, args.headline),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
                      "kernel": "march", "flops_per_cell_update": F,
                      "march_ms": head["march_ms"],
                      "lds_bytes_per_cell_update": lds_b,

@@ -181,6 +181,20 @@ void bpm_batch_destroy(bpm_batch* batch);
  * release the work lists on the stream. */
 int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream);
 
+/* Segment of the march (checkpoint / resume, z-resolved fields): starting
+ * from psi~_+ = E0_in and psi~_- = Eh_in (NULL: zero) at step n0, march
+ * steps n0 .. n0+nsteps-1 (deformation table rows n0.., table NULL for
+ * u = 0) and write the envelopes after them.  A step depends only on its
+ * index, so segments chained through their outputs reproduce bpm_march
+ * bitwise for BPM_PREC_FP64 and BPM_PREC_FP32 (register state = storage
+ * type); BPM_PREC_FP32S keeps FP64 registers, so each boundary adds one
+ * FP32 rounding of the state.  Outputs may overwrite their own envelope's
+ * input (in place);
+ * 0 <= n0, n0 + nsteps <= Nz. */
+int bpm_march_segment(const bpm_plan* plan, const void* E0_in,
+                      const void* Eh_in, const void* table, int n0, int nsteps,
+                      void* E0_out, void* Eh_out, void* stream);
+
 void bpm_plan_destroy(bpm_plan* plan);
 
 /* Message for the last error on the calling thread ("" if none). */

@@ -78,6 +78,9 @@ _SIGNATURES = [
     ("bpm_batch_destroy", None, [ctypes.c_void_p]),
     ("bpm_propagate_batch", ctypes.c_int,
      [ctypes.POINTER(bpm_job), ctypes.c_int, ctypes.c_void_p]),
+    ("bpm_march_segment", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("bpm_plan_destroy", None, [ctypes.c_void_p]),
     ("bpm_last_error", ctypes.c_char_p, []),
 ]
@@ -155,6 +158,9 @@ class Plan:
         if split_order != 1 or not zassenhaus:
             _check(L.bpm_plan_set_options(self._h, int(split_order),
                                           int(bool(zassenhaus))))
+        if schedule is None:
+            from .autotune import cached_choice
+            schedule = cached_choice(precision, Nx)
         if schedule is not None:
             _check(L.bpm_plan_set_schedule(self._h, SCHEDULE[schedule]
                                            if isinstance(schedule, str) else int(schedule)))
@@ -243,6 +249,20 @@ class Plan:
         self._check_field(Eh_out, "Eh_out")
         _check(lib().bpm_march(self._h, _ptr(E0_in), _ptr(table), _ptr(E0_out),
                                _ptr(Eh_out), _stream_handle(stream)))
+        return E0_out, Eh_out
+
+    def march_segment(self, E0_in, Eh_in, table, n0, nsteps, E0_out, Eh_out,
+                      stream=None):
+        """bpm_march_segment: steps n0 .. n0+nsteps-1 from (E0_in, Eh_in)."""
+        self._check_field(E0_in, "E0_in")
+        if Eh_in is not None:
+            self._check_field(Eh_in, "Eh_in")
+        self._check_field(E0_out, "E0_out")
+        self._check_field(Eh_out, "Eh_out")
+        _check(lib().bpm_march_segment(self._h, _ptr(E0_in), _ptr(Eh_in),
+                                       _ptr(table), int(n0), int(nsteps),
+                                       _ptr(E0_out), _ptr(Eh_out),
+                                       _stream_handle(stream)))
         return E0_out, Eh_out
 
     def close(self):

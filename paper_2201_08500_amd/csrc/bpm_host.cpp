@@ -524,6 +524,31 @@ int bpm_march(const bpm_plan* cp, const void* E0_in, const void* table,
   return BPM_OK;
 }
 
+int bpm_march_segment(const bpm_plan* cp, const void* E0_in, const void* Eh_in,
+                      const void* table, int n0, int nsteps, void* E0_out,
+                      void* Eh_out, void* stream) {
+  g_error.clear();
+  if (!cp) return fail(BPM_EINVAL, "plan is NULL");
+  if (!E0_in || !E0_out || !Eh_out)
+    return fail(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
+  if (E0_out == Eh_out || (Eh_in && (E0_out == Eh_in || Eh_out == E0_in)))
+    return fail(BPM_EINVAL, "outputs must not alias each other or the other envelope's input");
+  if (n0 < 0 || nsteps < 1 || n0 > cp->Nz - nsteps)
+    return fail(BPM_EINVAL, "steps [n0, n0 + nsteps) must lie in [0, Nz)");
+  bpm_plan* p = const_cast<bpm_plan*>(cp);
+  int rc = freeze(p);
+  if (rc) return rc;
+  bpm::MarchParams m = march_params(p, E0_in, table, E0_out, Eh_out);
+  m.Eh_in = Eh_in;
+  m.n0 = n0;
+  m.Nz = nsteps;
+  rc = bpm::launch_march(p->precision, p->Nx, plan_schedule(p), p->Nomega, m,
+                         static_cast<hipStream_t>(stream));
+  if (rc == BPM_EUNSUPPORTED) return fail(rc, "unsupported size/precision");
+  if (rc) return fail(rc, "march kernel launch failed");
+  return BPM_OK;
+}
+
 int bpm_propagate_ws(const bpm_plan* cp, const void* E0_in,
                      const double* u_field, void* E0_out, void* Eh_out,
                      void* workspace, void* stream) {

@@ -25,11 +25,13 @@ struct SliceConst {
 // Scalars of one launch of the march over a contiguous range of slices.
 struct MarchParams {
   const void* E0_in;        // [Nomega][Nx] complex (ST precision)
+  const void* Eh_in;        // psi~_- at the first step, or nullptr (zero)
   void* E0_out;
   void* Eh_out;
   const void* table;        // [Nz][Nx] exp(i h u), or nullptr (u == 0)
   const SliceConst* sc;     // [Nomega]
-  int Nz;
+  int Nz;                   // steps marched by this launch
+  int n0;                   // index of the first step (table row offset)
   int nsub;                 // B sub-steps per step (1, 2 or 4)
   double dx, dz;
   double h_half;            // h / 2

@@ -65,6 +65,38 @@ __device__ __forceinline__ cx<D> conv(cx<S> a) {
   return {static_cast<D>(a.x), static_cast<D>(a.y)};
 }
 
+// A twiddle factor w, held in FP64 for every precision.  A twiddle is the
+// same fixed number at every z-step, so a plain FP32 rounding of it (~3e-8)
+// is an error of the step operator itself: repeated Nz times, it grows
+// linearly (measured: relL2 1.8e-4 after 4000 steps in vacuum).  In FP32
+// arithmetic the product x w is therefore formed in FP64 and rounded once,
+// which leaves only the rounding of the data: that error does not add up
+// coherently and grows like sqrt(Nz) (9.7e-6 after 4000 steps).  On MI355X
+// the two conversions and four FP64 FMAs cost the same issue slots as an
+// unevaluated hi + lo FP32 pair, which in the compiled code did not remove
+// the drift.
+template <class T>
+struct Tw {
+  cx<double> w;
+  __device__ static Tw from(double c, double s) { return {{c, s}}; }
+  __device__ cx<T> mul(cx<T> x) const {
+    if constexpr (sizeof(T) == 8) {
+      return cmul(x, w);
+    } else {
+      const cx<double> r = cmul(cx<double>{x.x, x.y}, w);
+      return {static_cast<float>(r.x), static_cast<float>(r.y)};
+    }
+  }
+  __device__ cx<T> mulc(cx<T> x) const {
+    if constexpr (sizeof(T) == 8) {
+      return cmulc(x, w);
+    } else {
+      const cx<double> r = cmulc(cx<double>{x.x, x.y}, w);
+      return {static_cast<float>(r.x), static_cast<float>(r.y)};
+    }
+  }
+};
+
 // ------------------------------------------------------- small DFT kernels --
 // Forward kernel exp(-2 pi i n k / R), inverse exp(+2 pi i n k / R); no
 // scaling.  Outputs are in natural order.
@@ -90,9 +122,17 @@ __device__ __forceinline__ cx<T> tw16(cx<T> a) {
   } else {
     constexpr double c = kCos16[j];
     constexpr double s = kCos16[(j + 12) & 15];  // sin(2 pi j / 16)
-    const T wr = static_cast<T>(c);
-    const T wi = static_cast<T>(INV ? s : -s);
-    return {a.x * wr - a.y * wi, a.x * wi + a.y * wr};
+    constexpr double si = INV ? s : -s;
+    if constexpr (sizeof(T) == 4) {
+      // FP64 product rounded once, as for the pass twiddles (see Tw)
+      const double xr = a.x, xi = a.y;
+      return {static_cast<float>(xr * c - xi * si),
+              static_cast<float>(xr * si + xi * c)};
+    } else {
+      const T wr = static_cast<T>(c);
+      const T wi = static_cast<T>(si);
+      return {a.x * wr - a.y * wi, a.x * wi + a.y * wr};
+    }
   }
 }
 
@@ -378,7 +418,7 @@ struct March {
 
   // Stockham pass P over NE envelopes v[e] (LDS region e at lds + e kEnv).
   template <int P, bool INV, int SYNC, int NE>
-  __device__ static void pass_n(cx<CT> (&v)[NE][R], const cx<CT> (&tw)[NTW],
+  __device__ static void pass_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
                                 SV* lds, int t, int& xbuf) {
     constexpr int Rp = rad[P];
     constexpr int Ns = ns(P);
@@ -396,10 +436,10 @@ struct March {
       if constexpr (P > 0) {
 #pragma unroll
         for (int r = 1; r < Rp; ++r) {
-          const cx<CT> w = tw[tw_off(P) + s * (Rp - 1) + (r - 1)];
+          const Tw<CT> w = tw[tw_off(P) + s * (Rp - 1) + (r - 1)];
 #pragma unroll
           for (int e = 0; e < NE; ++e)
-            u[e][r] = INV ? cmulc(u[e][r], w) : cmul(u[e][r], w);
+            u[e][r] = INV ? w.mulc(u[e][r]) : w.mul(u[e][r]);
         }
       }
 #pragma unroll
@@ -444,21 +484,21 @@ struct March {
   }
 
   template <bool INV, int SYNC, int NE, int... P>
-  __device__ static void fft_impl(cx<CT> (&v)[NE][R], const cx<CT> (&tw)[NTW],
+  __device__ static void fft_impl(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
                                   SV* lds, int t, int& xbuf,
                                   std::integer_sequence<int, P...>) {
     (pass_n<P, INV, SYNC, NE>(v, tw, lds, t, xbuf), ...);
   }
   // In-place transform of NE envelopes.
   template <bool INV, int SYNC, int NE>
-  __device__ static void fft_n(cx<CT> (&v)[NE][R], const cx<CT> (&tw)[NTW],
+  __device__ static void fft_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
                                SV* lds, int t, int& xbuf) {
     fft_impl<INV, SYNC, NE>(v, tw, lds, t, xbuf,
                             std::make_integer_sequence<int, NP>{});
   }
   // Both envelopes (psi~_+ in a, psi~_- in b).
   template <bool INV, int SYNC = kSync>
-  __device__ static void fft(Reg& a, Reg& b, const cx<CT> (&tw)[NTW], SV* lds,
+  __device__ static void fft(Reg& a, Reg& b, const Tw<CT> (&tw)[NTW], SV* lds,
                              int t, int& xbuf) {
     cx<CT> v[2][R];
 #pragma unroll
@@ -476,7 +516,7 @@ struct March {
 
   // Twiddles W_{Ns Rp}^{r (jb mod Ns)} of every pass after the first.
   template <int P>
-  __device__ static void twiddles_pass(cx<CT> (&tw)[NTW], int t) {
+  __device__ static void twiddles_pass(Tw<CT> (&tw)[NTW], int t) {
     if constexpr (P > 0) {
       constexpr int Rp = rad[P];
       constexpr int Ns = ns(P);
@@ -490,14 +530,13 @@ struct March {
           // exp(-2 pi i r j / (Ns Rp)); sincospi keeps the argument exact
           double sn, cs;
           sincospi(-2.0 * double(r * j) / double(Ns * Rp), &sn, &cs);
-          tw[tw_off(P) + s * (Rp - 1) + (r - 1)] = {static_cast<CT>(cs),
-                                                    static_cast<CT>(sn)};
+          tw[tw_off(P) + s * (Rp - 1) + (r - 1)] = Tw<CT>::from(cs, sn);
         }
       }
     }
   }
   template <int... P>
-  __device__ static void twiddles_impl(cx<CT> (&tw)[NTW], int t,
+  __device__ static void twiddles_impl(Tw<CT> (&tw)[NTW], int t,
                                        std::integer_sequence<int, P...>) {
     (twiddles_pass<P>(tw, t), ...);
   }
@@ -506,7 +545,7 @@ struct March {
   // the DFT bin held in register slot i after forward(), and in-place
   // forward / inverse transforms of both envelopes.
   struct Ctx {
-    cx<CT> tw[NTW];
+    Tw<CT> tw[NTW];
     int xbuf;
   };
   __device__ static void init(Ctx& c, int t) {
@@ -560,7 +599,7 @@ struct FourStep {
 
   struct Ctx {
     typename In::Ctx in;
-    cx<CT> twx[NTWX];
+    Tw<CT> twx[NTWX];
   };
   __device__ static void init(Ctx& c, int t) {
     In::init(c.in, t & 63);
@@ -571,7 +610,7 @@ struct FourStep {
         for (int k1 = 1; k1 < W; ++k1) {
           double sn, cs;
           sincospi(-2.0 * double((t + T * j) * k1) / double(N), &sn, &cs);
-          c.twx[j * (W - 1) + k1 - 1] = {static_cast<CT>(cs), static_cast<CT>(sn)};
+          c.twx[j * (W - 1) + k1 - 1] = Tw<CT>::from(cs, sn);
         }
     }
   }
@@ -596,9 +635,9 @@ struct FourStep {
 #pragma unroll
         for (int k1 = 0; k1 < W; ++k1) {
           if (k1 > 0) {
-            const cx<CT> w = c.twx[j * (W - 1) + k1 - 1];
-            va[k1] = cmul(va[k1], w);
-            vb[k1] = cmul(vb[k1], w);
+            const Tw<CT> w = c.twx[j * (W - 1) + k1 - 1];
+            va[k1] = w.mul(va[k1]);
+            vb[k1] = w.mul(vb[k1]);
           }
           In::store(lds + k1 * kRegion, t + T * j, va[k1]);
           In::store(lds + k1 * kRegion + In::kEnv, t + T * j, vb[k1]);
@@ -638,9 +677,9 @@ struct FourStep {
           va[k1] = In::load(gp + k1 * kStride, t + T * j);
           vb[k1] = In::load(gp + k1 * kStride + kB, t + T * j);
           if (k1 > 0) {
-            const cx<CT> w = c.twx[j * (W - 1) + k1 - 1];
-            va[k1] = cmulc(va[k1], w);
-            vb[k1] = cmulc(vb[k1], w);
+            const Tw<CT> w = c.twx[j * (W - 1) + k1 - 1];
+            va[k1] = w.mulc(va[k1]);
+            vb[k1] = w.mulc(vb[k1]);
           }
         }
         dft<W, true>(va);
@@ -698,14 +737,14 @@ struct Split4 {
 
     typename In::Ctx ic;
     In::init(ic, l);
-    cx<CT> twx[J * (W - 1)];
+    Tw<CT> twx[J * (W - 1)];
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
       for (int k1 = 1; k1 < W; ++k1) {
         double sn, cs;
         sincospi(-2.0 * double((t0 + T0 * j) * k1) / double(N), &sn, &cs);
-        twx[j * (W - 1) + k1 - 1] = {static_cast<CT>(cs), static_cast<CT>(sn)};
+        twx[j * (W - 1) + k1 - 1] = Tw<CT>::from(cs, sn);
       }
     // own band's propagator at the bins of (wavefront wv, lane l, slot i)
     cx<double> P[R];
@@ -723,21 +762,23 @@ struct Split4 {
     const cx<double> dx = e ? cx<double>{sc.d[0][4], sc.d[0][5]}
                             : cx<double>{sc.d[0][2], sc.d[0][3]};
 
+    const SV* src = e == 0 ? in
+                           : (p.Eh_in ? static_cast<const SV*>(p.Eh_in) + size_t(slice) * N
+                                      : nullptr);
     cx<CT> v[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      if (e == 0) {
-        const SV s = in[t0 + T0 * i];
+      v[i] = {CT(0), CT(0)};
+      if (src) {
+        const SV s = src[t0 + T0 * i];
         v[i] = {static_cast<CT>(s.x), static_cast<CT>(s.y)};
-      } else {
-        v[i] = {CT(0), CT(0)};
       }
     }
 
     for (int n = 0; n < p.Nz; ++n) {
       SV er[R];
       if constexpr (DEFORMED) {
-        const SV* row = table + size_t(n) * N;
+        const SV* row = table + size_t(p.n0 + n) * N;
 #pragma unroll
         for (int i = 0; i < R; ++i) er[i] = row[t0 + T0 * i];
       }
@@ -750,7 +791,7 @@ struct Split4 {
         dft<W, false>(u);
 #pragma unroll
         for (int k1 = 0; k1 < W; ++k1) {
-          if (k1 > 0) u[k1] = cmul(u[k1], twx[j * (W - 1) + k1 - 1]);
+          if (k1 > 0) u[k1] = twx[j * (W - 1) + k1 - 1].mul(u[k1]);
           In::store(G + (e * W + k1) * In::kEnv, t0 + T0 * j, u[k1]);
         }
       }
@@ -776,8 +817,8 @@ struct Split4 {
           ua[k1] = In::load(Gp + k1 * M, t0 + T0 * j);
           ub[k1] = In::load(Gp + (W + k1) * M, t0 + T0 * j);
           if (k1 > 0) {
-            ua[k1] = cmulc(ua[k1], twx[j * (W - 1) + k1 - 1]);
-            ub[k1] = cmulc(ub[k1], twx[j * (W - 1) + k1 - 1]);
+            ua[k1] = twx[j * (W - 1) + k1 - 1].mulc(ua[k1]);
+            ub[k1] = twx[j * (W - 1) + k1 - 1].mulc(ub[k1]);
           }
         }
         dft<W, true>(ua);
@@ -846,20 +887,26 @@ __device__ void march_slice_joint(const MarchParams& p, int slice, int t,
   const cx<double> dp1 = {sc.d[0][2], sc.d[0][3]};
   const cx<double> dm1 = {sc.d[0][4], sc.d[0][5]};
 
+  const SV* in_b = p.Eh_in ? static_cast<const SV*>(p.Eh_in) + size_t(slice) * N
+                           : nullptr;
   cx<CT> a[R], b[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const SV v = in[t + T * i];
     a[i] = {static_cast<CT>(v.x), static_cast<CT>(v.y)};
     b[i] = {CT(0), CT(0)};
+    if (in_b) {
+      const SV w = in_b[t + T * i];
+      b[i] = {static_cast<CT>(w.x), static_cast<CT>(w.y)};
+    }
   }
 
   for (int n = 0; n < p.Nz; ++n) {
-    // Row n of exp(i h u), fetched at the start of the step and used by the
-    // coupling at its end, so its latency hides behind the transforms.
+    // Row n0 + n of exp(i h u), fetched at the start of the step and used by
+    // the coupling at its end, so its latency hides behind the transforms.
     SV e[R];
     if constexpr (DEFORMED) {
-      const SV* row = table + size_t(n) * N;
+      const SV* row = table + size_t(p.n0 + n) * N;
 #pragma unroll
       for (int i = 0; i < R; ++i) e[i] = row[t + T * i];
     }

@@ -170,3 +170,52 @@ def test_linearity():
                         (b2 - (2.0 - 1.5j) * b1).ravel()])
     assert np.linalg.norm(b2) > 1e-3 * np.linalg.norm(a2)   # reflection is present
     assert np.linalg.norm(d) <= 1e-14 * np.linalg.norm(s)
+
+
+@pytest.mark.parametrize("schedule", ["stockham", "fourstep", "split"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32s"])
+def test_segmented_march_equals_monolithic(prec, schedule):
+    """Checkpoint / resume: segments [0,13), [13,30), [30,41) chained through
+    their outputs (the last one in place) reproduce the 41-step march
+    bitwise; the checkpoint after 13 steps matches the oracle."""
+    from paper_2201_08500_amd import Plan
+    w = W.small(Nx=1024, Nz=41, Nomega=3, seed=5)
+    p = Plan.from_workload(w, precision=prec, schedule=schedule)
+    E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
+    u = torch.from_numpy(w.u).cuda()
+    table = torch.empty(p.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    p.deformation_table(u, table)
+    a, b = torch.empty_like(E0), torch.empty_like(E0)
+    p.march(E0, table, a, b)
+    a1, b1 = torch.empty_like(E0), torch.empty_like(E0)
+    p.march_segment(E0, None, table, 0, 13, a1, b1)
+    torch.cuda.synchronize()
+    ck_a, ck_b = a1.cpu().numpy().astype(np.complex128), b1.cpu().numpy().astype(np.complex128)
+    a2, b2 = torch.empty_like(E0), torch.empty_like(E0)
+    p.march_segment(a1, b1, table, 13, 17, a2, b2)
+    p.march_segment(a2, b2, table, 30, 11, a2, b2)      # in place
+    torch.cuda.synchronize()
+    if prec == "fp32s":
+        # FP64 register state, complex64 checkpoints: one FP32 rounding of
+        # the state per segment boundary
+        r = report(a2.cpu().numpy(), b2.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy())
+        assert r["rel_l2"] <= 1e-7, r
+    else:
+        assert torch.equal(a2, a) and torch.equal(b2, b)
+    Ein = w.E0_in if prec == "fp64" else w.E0_in.astype(np.complex64).astype(np.complex128)
+    ra, rb = O.march(O.Problem.from_workload(w), Ein, w.u, n_steps=13)
+    r = report(ck_a, ck_b, ra, rb)
+    assert r["rel_l2"] <= (tol64(13) if prec == "fp64" else 1e-5), r
+
+
+def test_segment_rejects_bad_ranges():
+    from paper_2201_08500_amd import BpmError, Plan
+    w = W.small(Nx=512, Nz=10, Nomega=1, seed=1, deformed=False)
+    p = Plan.from_workload(w, precision="fp64")
+    E0 = torch.from_numpy(w.E0_in).cuda()
+    a, b = torch.empty_like(E0), torch.empty_like(E0)
+    for n0, k in ((-1, 3), (0, 0), (8, 3), (10, 1)):
+        with pytest.raises(BpmError):
+            p.march_segment(E0, None, None, n0, k, a, b)
+    with pytest.raises(BpmError):
+        p.march_segment(E0, None, None, 0, 5, a, a)
