@@ -174,9 +174,9 @@ def bench_batch(args):
         row, gz, gx, amp = w.meta["u_factors"]
         p = Plan.from_workload(w, precision=args.headline)
         E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
-        row_t, gz_t, gx_t = (torch.from_numpy(v).cuda() for v in (row, gz, gx))
         # same operation order as the numpy generator: row + (amp gz) gx
-        u = (row_t[None, :] + (amp * gz_t)[:, None] * gx_t[None, :]).contiguous()
+        u = torch.outer(torch.from_numpy(amp * gz).cuda(), torch.from_numpy(gx).cuda())
+        u.add_(torch.from_numpy(row).cuda())
         jobs.append(Job(p, E0, u))
         works.append(w)
         cells += w.cell_updates
@@ -267,7 +267,9 @@ def bench_serve(args):
     prec_map = {"fp64": "fp64", "fp32": args.serve_fp32}
     if args.serve_all_fp64:
         prec_map = {"fp64": "fp64", "fp32": "fp64"}
-    backend = GpuBackend(streams=args.serve_streams, keep_outputs=False)
+    # 16 GiB of the device stay outside torch's allocator for the HIP runtime
+    backend = GpuBackend(streams=args.serve_streams, keep_outputs=False,
+                         headroom_bytes=16 * 2**30)
     srv = Server(backend, budget_bytes=args.serve_budget_gb * 1e9,
                  max_in_flight=args.serve_streams)
     # warm the kernels once outside the measured stream
@@ -299,10 +301,18 @@ def bench_serve(args):
             print(f"[bench] serve: {i + 1}/{len(trace)} submitted, "
                   f"{len(srv.completed)} done", file=sys.stderr, flush=True)
     lag = time.perf_counter() - t0 - trace[-1][0]
+    last, t_last = -1, time.perf_counter()
     while not srv.drain(timeout=10):
-        print(f"[bench] serve: draining, {len(srv.completed)} done",
-              file=sys.stderr, flush=True)
+        n = len(srv.completed)
+        print(f"[bench] serve: draining, {n} done", file=sys.stderr, flush=True)
+        if n != last:
+            last, t_last = n, time.perf_counter()
+        elif time.perf_counter() - t_last > 120:
+            srv.stop()
+            sys.exit("serve: no request completed for 120 s")
     srv.stop()
+    if srv.broken is not None:
+        sys.exit(f"serve: device error, {len(srv.failed)} requests failed: {srv.broken}")
     pool.shutdown()
     st = srv.stats()
     line = {

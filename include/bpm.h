@@ -187,9 +187,10 @@ int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream);
  * u = 0) and write the envelopes after them.  A step depends only on its
  * index, so segments chained through their outputs reproduce bpm_march
  * bitwise for BPM_PREC_FP64 and BPM_PREC_FP32 (register state = storage
- * type); BPM_PREC_FP32S keeps FP64 registers, so each boundary adds one
- * FP32 rounding of the state.  Outputs may overwrite their own envelope's
- * input (in place);
+ * type).  BPM_PREC_FP32S keeps FP64 registers, so each boundary rounds the
+ * state to FP32, after which the chained and monolithic marches round
+ * independently and differ at the level of the mode's rounding noise.
+ * Outputs may overwrite their own envelope's input (in place);
  * 0 <= n0, n0 + nsteps <= Nz. */
 int bpm_march_segment(const bpm_plan* plan, const void* E0_in,
                       const void* Eh_in, const void* table, int n0, int nsteps,

@@ -15,8 +15,19 @@ does not depend on what it was batched with.  Latency is arrival to outputs
 ready (completion event observed).  Outputs stay device-resident.
 
 The device side is a backend object, so the scheduling logic is testable on
-the CPU with a simulated device (tests/test_serve.py); GpuBackend drives
-libbpm.so.
+the CPU with a simulated device; GpuBackend drives libbpm.so.
+
+Failure handling:
+- a request larger than the whole budget fails at submit;
+- a backend that cannot place an admitted request right now (device memory
+  fragmented or held by the allocator) raises Retry: the request goes back to
+  the head of the queue and waits for running work to finish (it fails only
+  if nothing is running to wait for);
+- any other materialise or launch error fails only the requests concerned;
+- an error while polling a running launch (a device fault) is sticky: every
+  running, admitted and queued request fails with it, later submissions fail
+  at once, and drain() returns instead of waiting for work that can never
+  complete.
 """
 
 from __future__ import annotations
@@ -28,6 +39,11 @@ import time
 from concurrent.futures import Future
 from dataclasses import dataclass, field
 from typing import Any, Optional
+
+
+class Retry(Exception):
+    """Raised by a backend's materialize() when the request cannot be placed
+    now but may fit once running work releases its memory."""
 
 
 @dataclass
@@ -72,7 +88,9 @@ class Server:
         self.completed = []
         self.failed = []
         self.launches = 0
+        self.retries = 0
         self.peak_used = 0.0
+        self.broken = None                   # sticky device error, if any
 
     # ---------------------------------------------------------------- API --
     def now(self) -> float:
@@ -92,7 +110,11 @@ class Server:
             self._next_id += 1
             req.arrival = self.now()
             req.state = "queued"
-            if req.footprint > self.budget:
+            if self.broken is not None:
+                req.state = "failed"
+                req.future.set_exception(RuntimeError(f"server stopped: {self.broken}"))
+                self.failed.append(req)
+            elif req.footprint > self.budget:
                 req.state = "failed"
                 req.future.set_exception(MemoryError(
                     f"request {req.rid} needs {req.footprint} B, more than the "
@@ -142,7 +164,8 @@ class Server:
         span = (max(r.finished for r in done) - min(r.arrival for r in done)) if done else math.nan
         cells = sum(r.cell_updates for r in done)
         return dict(completed=len(done), failed=len(self.failed),
-                    launches=self.launches, p50_s=pct(50), p99_s=pct(99),
+                    launches=self.launches, retries=self.retries,
+                    p50_s=pct(50), p99_s=pct(99),
                     max_s=lat[-1] if lat else math.nan,
                     cell_updates=cells, span_s=span,
                     cell_updates_per_s=(cells / span) if done and span > 0 else math.nan,
@@ -151,15 +174,42 @@ class Server:
     # ---------------------------------------------------------- scheduler --
     def _run(self):
         while not self._stop.is_set():
-            progressed = self._poll() | self._admit_and_launch()
+            try:
+                progressed = self._poll() | self._admit_and_launch()
+            except Exception as e:          # noqa: BLE001 -- never leave waiters hanging
+                self._break(e)
+                progressed = False
             if not progressed:
                 time.sleep(self.tick)
+
+    def _break(self, err):
+        """Sticky failure: fail everything in flight, admitted or queued."""
+        if self.broken is None:
+            self.broken = err
+        for _, reqs in self._in_flight:
+            for r in reqs:
+                self._fail_now(r, err)
+        self._in_flight = []
+        with self._lock:
+            waiting = list(self._incoming) + list(self._pending)
+            self._incoming.clear()
+            self._pending.clear()
+        for r in waiting:
+            r.state = "failed"
+            r.finished = self.now()
+            self.failed.append(r)
+            r.future.set_exception(RuntimeError(f"server stopped: {err}"))
 
     def _poll(self) -> bool:
         done_any = False
         still = []
-        for handle, reqs in self._in_flight:
-            status = self.backend.poll(handle)
+        for k, (handle, reqs) in enumerate(self._in_flight):
+            try:
+                status = self.backend.poll(handle)
+            except Exception as e:          # noqa: BLE001 -- device fault: sticky
+                self._in_flight = still + self._in_flight[k:]
+                self._break(e)
+                return True
             if status is None:
                 still.append((handle, reqs))
                 continue
@@ -183,6 +233,9 @@ class Server:
         return done_any
 
     def _admit_and_launch(self) -> bool:
+        if self.broken is not None:
+            self._break(self.broken)
+            return False
         with self._lock:
             while self._incoming:
                 self._pending.append(self._incoming.popleft())
@@ -200,10 +253,25 @@ class Server:
         if not batch:
             return False
         ok = []
-        for r in batch:
+        for k, r in enumerate(batch):
             try:
                 self.backend.materialize(r)
                 ok.append(r)
+            except Retry as e:
+                if not self._in_flight and not ok:
+                    self._fail_now(r, MemoryError(str(e)))   # nothing to wait for
+                    continue
+                # back to the head of the queue, in order, with the rest of
+                # this batch; wait for running work to release memory
+                rest = batch[k:]
+                with self._lock:
+                    for q in reversed(rest):
+                        self._used -= q.footprint
+                        self._active -= 1
+                        q.admitted = math.nan
+                        self._pending.appendleft(q)
+                self.retries += 1
+                break
             except Exception as e:          # noqa: BLE001 -- reported per request
                 self._fail_now(r, e)
         if not ok:
@@ -243,11 +311,19 @@ class GpuBackend:
     host, `meta['u_factors'] = (row, gz, gx, amp)` describing
     u[n, j] = row[j] + (amp gz[n]) gx[j], or `u` as an array, or no u)."""
 
-    def __init__(self, streams: int = 4, device: int = 0, keep_outputs=True):
+    def __init__(self, streams: int = 4, device: int = 0, keep_outputs=True,
+                 headroom_bytes: float = 0.0):
+        """headroom_bytes > 0 caps torch's caching allocator at the device's
+        memory minus that much, so the HIP runtime (queues, kernel scratch)
+        can always allocate while the allocator holds cached blocks."""
         import torch
         self.keep_outputs = keep_outputs
         self.torch = torch
         self.device = torch.device("cuda", device)
+        if headroom_bytes > 0:
+            total = torch.cuda.get_device_properties(self.device).total_memory
+            torch.cuda.set_per_process_memory_fraction(
+                max(0.05, 1.0 - float(headroom_bytes) / total), self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self._k = 0
 
@@ -267,24 +343,34 @@ class GpuBackend:
         return w.Nx * w.Nz * w.Nomega
 
     def materialize(self, req):
+        """Device buffers of one request, with no device temporaries: E0 is
+        converted to the field type on the host, and u is formed in place
+        from its separable description (u[n, j] = row[j] + (amp gz[n]) gx[j],
+        the generator's operation order, so bitwise equal to it)."""
+        import numpy as np
         from . import Job, Plan
         torch = self.torch
         w = req.spec
         s = self.streams[self._k % len(self.streams)]
-        with torch.cuda.stream(s):
-            plan = Plan.from_workload(w, precision=req.precision)
-            E0 = torch.from_numpy(w.E0_in).to(self.device).to(plan.field_dtype)
-            u = None
-            if w.u is not None:
-                u = torch.from_numpy(w.u).to(self.device)
-            elif "u_factors" in w.meta:
-                row, gz, gx, amp = w.meta["u_factors"]
-                row_t = torch.from_numpy(row).to(self.device)
-                gz_t = torch.from_numpy(gz).to(self.device)
-                gx_t = torch.from_numpy(gx).to(self.device)
-                # same operation order as the host generator
-                u = (row_t[None, :] + (amp * gz_t)[:, None] * gx_t[None, :]).contiguous()
-            req.device = Job(plan, E0, u)
+        try:
+            with torch.cuda.stream(s):
+                plan = Plan.from_workload(w, precision=req.precision)
+                host_dtype = np.complex128 if plan.field_dtype == torch.complex128 \
+                    else np.complex64
+                E0 = torch.from_numpy(np.ascontiguousarray(
+                    w.E0_in, dtype=host_dtype)).to(self.device)
+                u = None
+                if w.u is not None:
+                    u = torch.from_numpy(w.u).to(self.device)
+                elif "u_factors" in w.meta:
+                    row, gz, gx, amp = w.meta["u_factors"]
+                    gzs = torch.from_numpy(amp * gz).to(self.device)
+                    u = torch.outer(gzs, torch.from_numpy(gx).to(self.device))
+                    u.add_(torch.from_numpy(row).to(self.device))
+                req.device = Job(plan, E0, u)
+        except torch.OutOfMemoryError as e:
+            req.device = None
+            raise Retry(str(e)) from e
 
     def launch(self, reqs):
         from . import propagate_batch

@@ -177,7 +177,8 @@ def test_linearity():
 def test_segmented_march_equals_monolithic(prec, schedule):
     """Checkpoint / resume: segments [0,13), [13,30), [30,41) chained through
     their outputs (the last one in place) reproduce the 41-step march
-    bitwise; the checkpoint after 13 steps matches the oracle."""
+    bitwise (fp64, fp32; fp32s to its rounding noise); the checkpoint after
+    13 steps matches the oracle."""
     from paper_2201_08500_amd import Plan
     w = W.small(Nx=1024, Nz=41, Nomega=3, seed=5)
     p = Plan.from_workload(w, precision=prec, schedule=schedule)
@@ -195,14 +196,20 @@ def test_segmented_march_equals_monolithic(prec, schedule):
     p.march_segment(a1, b1, table, 13, 17, a2, b2)
     p.march_segment(a2, b2, table, 30, 11, a2, b2)      # in place
     torch.cuda.synchronize()
+    Ein = w.E0_in if prec == "fp64" else w.E0_in.astype(np.complex64).astype(np.complex128)
     if prec == "fp32s":
-        # FP64 register state, complex64 checkpoints: one FP32 rounding of
-        # the state per segment boundary
+        # FP64 register state, complex64 checkpoints: the state is rounded
+        # to FP32 at each boundary, after which the two runs round
+        # independently; they differ by the mode's rounding noise, and the
+        # chained result meets the precision target against the oracle
         r = report(a2.cpu().numpy(), b2.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy())
-        assert r["rel_l2"] <= 1e-7, r
+        assert r["rel_l2"] <= 2e-6, r
+        fa, fb = O.march(O.Problem.from_workload(w), Ein, w.u)
+        r = report(a2.cpu().numpy().astype(np.complex128),
+                   b2.cpu().numpy().astype(np.complex128), fa, fb)
+        assert r["rel_l2"] <= 1e-5, r
     else:
         assert torch.equal(a2, a) and torch.equal(b2, b)
-    Ein = w.E0_in if prec == "fp64" else w.E0_in.astype(np.complex64).astype(np.complex128)
     ra, rb = O.march(O.Problem.from_workload(w), Ein, w.u, n_steps=13)
     r = report(ck_a, ck_b, ra, rb)
     assert r["rel_l2"] <= (tol64(13) if prec == "fp64" else 1e-5), r

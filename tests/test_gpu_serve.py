@@ -58,3 +58,27 @@ def test_served_results_equal_standalone(budget_mb):
     for r, (w, prec) in zip(rs, reqs):
         a, b = standalone(w, prec)
         assert torch.equal(r.outputs[0].cpu(), a) and torch.equal(r.outputs[1].cpu(), b), r.rid
+
+
+def test_served_separable_displacement_equals_host_u():
+    """Requests that describe u by its separable factors (formed on the
+    device) give the same results as the host-built u, bitwise."""
+    from paper_2201_08500_amd.serve import GpuBackend, Request, Server
+    specs = [dict(index=i, Nx=nx, Nz=nz, Nomega=nw, R=r, bump=bump, seed=40 + i)
+             for i, (nx, nz, nw, r, bump) in enumerate(
+                 [(512, 37, 2, 12.0, 7e-11), (1024, 25, 1, 80.0, 2e-11),
+                  (2048, 19, 3, 3.5, 9e-11)])]
+    reqs = [(W.c4_problem(s, with_u=False), prec) for s, prec in
+            zip(specs, ["fp64", "fp32s", "fp32"])]
+    srv = Server(GpuBackend(streams=2), budget_bytes=2**30, max_in_flight=2).start()
+    try:
+        rs = [Request(spec=w, precision=prec) for w, prec in reqs]
+        for r in rs:
+            srv.submit(r)
+        assert srv.drain(timeout=120)
+    finally:
+        srv.stop()
+    assert srv.stats()["completed"] == len(rs)
+    for r, s, (_, prec) in zip(rs, specs, reqs):
+        a, b = standalone(W.c4_problem(s, with_u=True), prec)
+        assert torch.equal(r.outputs[0].cpu(), a) and torch.equal(r.outputs[1].cpu(), b), r.rid

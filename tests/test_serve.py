@@ -8,14 +8,17 @@ import time
 
 import pytest
 
-from paper_2201_08500_amd.serve import Request, Server
+from paper_2201_08500_amd.serve import Request, Retry, Server
 
 
 class FakeBackend:
     """Each launch 'runs' for the sum of its requests' durations / speedup."""
 
-    def __init__(self, fail_launch=None, fail_materialize=None, speedup=1.0):
+    def __init__(self, fail_launch=None, fail_materialize=None, speedup=1.0,
+                 retry_materialize=None, poll_error_launch=None):
         self.lock = threading.Lock()
+        self.retry_materialize = dict(retry_materialize or {})   # name -> times
+        self.poll_error_launch = poll_error_launch
         self.launched = []            # list of (t, [rid...])
         self.live = 0
         self.max_live = 0
@@ -31,8 +34,12 @@ class FakeBackend:
         return req.spec.get("cells", 1)
 
     def materialize(self, req):
-        if req.spec.get("name") in self.fail_materialize:
+        name = req.spec.get("name")
+        if name in self.fail_materialize:
             raise RuntimeError("materialize failed")
+        if self.retry_materialize.get(name, 0) > 0:
+            self.retry_materialize[name] -= 1
+            raise Retry("no room yet")
         req.device = object()
 
     def launch(self, reqs):
@@ -47,10 +54,13 @@ class FakeBackend:
             raise RuntimeError("launch failed")
         dur = max(r.spec.get("dur", 0.01) for r in reqs) / self.speedup
         self.launched.append((time.perf_counter(), [r.spec["name"] for r in reqs]))
-        return time.perf_counter() + dur
+        return (k, time.perf_counter() + dur)
 
     def poll(self, handle):
-        if time.perf_counter() >= handle:
+        k, t_end = handle
+        if k == self.poll_error_launch and time.perf_counter() >= t_end:
+            raise RuntimeError("device fault")
+        if time.perf_counter() >= t_end:
             with self.lock:
                 self.live -= 1
             return True
@@ -181,5 +191,60 @@ def test_latency_statistics():
         assert st["completed"] == 20 and st["failed"] == 0
         assert 0 < st["p50_s"] <= st["p99_s"] <= st["max_s"]
         assert st["cell_updates"] == 2000
+    finally:
+        srv.stop()
+
+
+def test_retry_waits_for_running_work():
+    """A request the device cannot place yet goes back to the head of the
+    queue and is launched after running work completes, in order."""
+    be = FakeBackend(retry_materialize={"b": 1})
+    srv = Server(be, budget_bytes=1e9, max_in_flight=2).start()
+    try:
+        a = req("a", 10, 0.1)
+        srv.submit(a)
+        time.sleep(0.02)
+        b, c = req("b", 10), req("c", 10)
+        srv.submit(b)
+        srv.submit(c)
+        assert srv.drain(timeout=5)
+        assert a.state == b.state == c.state == "done"
+        flat = [n for _, names in be.launched for n in names]
+        assert flat.index("b") < flat.index("c")
+        assert srv.retries >= 1 and srv._used == 0
+    finally:
+        srv.stop()
+
+
+def test_retry_with_nothing_running_fails_the_request():
+    be = FakeBackend(retry_materialize={"x": 10})
+    srv = Server(be, budget_bytes=1e9).start()
+    try:
+        f = srv.submit(req("x", 10))
+        with pytest.raises(MemoryError):
+            f.result(timeout=5)
+        assert srv.submit(req("y", 10)).result(timeout=5).state == "done"
+    finally:
+        srv.stop()
+
+
+def test_device_fault_fails_everything_and_drain_returns():
+    """An error while polling a launch is sticky: running, queued and later
+    requests fail, and drain() returns instead of hanging."""
+    be = FakeBackend(poll_error_launch=0)
+    srv = Server(be, budget_bytes=100, max_in_flight=1).start()
+    try:
+        a = req("a", 60, 0.05)
+        fa = srv.submit(a)
+        time.sleep(0.01)
+        fb = srv.submit(req("b", 60))          # queued behind a (budget)
+        with pytest.raises(RuntimeError):
+            fa.result(timeout=5)
+        with pytest.raises(RuntimeError):
+            fb.result(timeout=5)
+        assert srv.drain(timeout=5)
+        assert srv.broken is not None
+        with pytest.raises(RuntimeError):
+            srv.submit(req("c", 1)).result(timeout=5)
     finally:
         srv.stop()
