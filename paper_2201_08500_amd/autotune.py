@@ -123,7 +123,7 @@ def main():
     ap.add_argument("--precisions", default=",".join(PRECISIONS))
     ap.add_argument("--sizes", default=",".join(str(s) for s in SIZES))
     ap.add_argument("--nz", type=int, default=400)
-    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=5)
     a = ap.parse_args()
     res = tune(a.precisions.split(","), [int(s) for s in a.sizes.split(",")],
                a.nz, a.reps, a.out)

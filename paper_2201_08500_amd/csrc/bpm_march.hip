@@ -18,6 +18,8 @@
 
 #include "bpm_internal.h"
 
+#define BPM_INLINE __device__ __forceinline__
+
 namespace bpm {
 namespace {
 
@@ -78,8 +80,8 @@ __device__ __forceinline__ cx<D> conv(cx<S> a) {
 template <class T>
 struct Tw {
   cx<double> w;
-  __device__ static Tw from(double c, double s) { return {{c, s}}; }
-  __device__ cx<T> mul(cx<T> x) const {
+  BPM_INLINE static Tw from(double c, double s) { return {{c, s}}; }
+  BPM_INLINE cx<T> mul(cx<T> x) const {
     if constexpr (sizeof(T) == 8) {
       return cmul(x, w);
     } else {
@@ -87,7 +89,7 @@ struct Tw {
       return {static_cast<float>(r.x), static_cast<float>(r.y)};
     }
   }
-  __device__ cx<T> mulc(cx<T> x) const {
+  BPM_INLINE cx<T> mulc(cx<T> x) const {
     if constexpr (sizeof(T) == 8) {
       return cmulc(x, w);
     } else {
@@ -394,13 +396,13 @@ struct March {
 
   using Reg = cx<CT>[R];
 
-  __device__ static void store(SV* lds, int idx, cx<CT> v) {
+  BPM_INLINE static void store(SV* lds, int idx, cx<CT> v) {
     SV s;
     s.x = static_cast<ST>(v.x);
     s.y = static_cast<ST>(v.y);
     lds[idx] = s;
   }
-  __device__ static cx<CT> load(const SV* lds, int idx) {
+  BPM_INLINE static cx<CT> load(const SV* lds, int idx) {
     const SV s = lds[idx];
     return {static_cast<CT>(s.x), static_cast<CT>(s.y)};
   }
@@ -418,7 +420,7 @@ struct March {
 
   // Stockham pass P over NE envelopes v[e] (LDS region e at lds + e kEnv).
   template <int P, bool INV, int SYNC, int NE>
-  __device__ static void pass_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
+  BPM_INLINE static void pass_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
                                 SV* lds, int t, int& xbuf) {
     constexpr int Rp = rad[P];
     constexpr int Ns = ns(P);
@@ -484,21 +486,21 @@ struct March {
   }
 
   template <bool INV, int SYNC, int NE, int... P>
-  __device__ static void fft_impl(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
+  BPM_INLINE static void fft_impl(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
                                   SV* lds, int t, int& xbuf,
                                   std::integer_sequence<int, P...>) {
     (pass_n<P, INV, SYNC, NE>(v, tw, lds, t, xbuf), ...);
   }
   // In-place transform of NE envelopes.
   template <bool INV, int SYNC, int NE>
-  __device__ static void fft_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
+  BPM_INLINE static void fft_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
                                SV* lds, int t, int& xbuf) {
     fft_impl<INV, SYNC, NE>(v, tw, lds, t, xbuf,
                             std::make_integer_sequence<int, NP>{});
   }
   // Both envelopes (psi~_+ in a, psi~_- in b).
   template <bool INV, int SYNC = kSync>
-  __device__ static void fft(Reg& a, Reg& b, const Tw<CT> (&tw)[NTW], SV* lds,
+  BPM_INLINE static void fft(Reg& a, Reg& b, const Tw<CT> (&tw)[NTW], SV* lds,
                              int t, int& xbuf) {
     cx<CT> v[2][R];
 #pragma unroll
@@ -552,11 +554,11 @@ struct March {
     twiddles_impl(c.tw, t, std::make_integer_sequence<int, NP>{});
     c.xbuf = 0;
   }
-  __device__ static int bin(int t, int i) { return t + T * i; }
-  __device__ static void forward(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
+  BPM_INLINE static int bin(int t, int i) { return t + T * i; }
+  BPM_INLINE static void forward(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
     fft<false>(a, b, c.tw, lds, t, c.xbuf);
   }
-  __device__ static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
+  BPM_INLINE static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
     fft<true>(a, b, c.tw, lds, t, c.xbuf);
   }
 };
@@ -614,11 +616,11 @@ struct FourStep {
         }
     }
   }
-  __device__ static int bin(int t, int i) {
+  BPM_INLINE static int bin(int t, int i) {
     return (t >> 6) + W * ((t & 63) + 64 * i);
   }
 
-  __device__ static void forward(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
+  BPM_INLINE static void forward(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
     const int wv = t >> 6, l = t & 63;
     SV* own = lds + wv * kRegion;
     if constexpr (W > 1) {
@@ -654,7 +656,7 @@ struct FourStep {
     In::template fft<false, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
   }
 
-  __device__ static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
+  BPM_INLINE static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
     const int wv = t >> 6, l = t & 63;
     SV* own = lds + wv * kRegion;
     In::template fft<true, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
@@ -703,11 +705,18 @@ struct FourStep {
 // the inverse exchange every thread rebuilds BOTH envelopes at its x samples
 // (the cross-wavefront inverse DFT is done twice, a small cost) so that the
 // coupling needs no further exchange: two work-group barriers per z-step.
+// The envelope is a template parameter of the per-wavefront code (every
+// wavefront holds one envelope), so no per-sample selects remain.
+//
+// LDS: 2W regions, one per wavefront, each the forward exchange target
+// (M samples) and afterwards that wavefront's in-wave exchange buffer, then
+// the inverse exchange (2W M samples).
 template <int PREC, int W, class In>
 struct Split4 {
   using CT = typename Prec<PREC>::CT;
   using ST = typename Prec<PREC>::ST;
   using SV = typename vec2<ST>::type;
+  using IV = typename In::SV;
   static_assert(In::T == 64 && W >= 2, "split march needs W >= 2 wavefronts");
   static constexpr bool kSplit = true;
   static constexpr int M = In::N;
@@ -717,23 +726,46 @@ struct Split4 {
   static constexpr int T = 2 * T0;
   static constexpr int J = R / W;
   static_assert(R % W == 0, "");
-  static constexpr size_t kG = size_t(2) * W * In::kEnv;   // scratch + fwd
-  static constexpr size_t kGp = size_t(2) * W * M;          // inverse
-  static constexpr size_t kLdsBytes = (kG + kGp) * sizeof(SV);
+  static constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+  static constexpr size_t kRegionBytes =
+      (cmax(size_t(M) * sizeof(SV), size_t(In::kEnv) * sizeof(IV)) + 15) / 16 * 16;
+  static constexpr size_t kGBytes = size_t(2) * W * kRegionBytes;
+  static constexpr size_t kLdsBytes = kGBytes + size_t(2) * W * M * sizeof(SV);
   static_assert(kLdsBytes <= 160 * 1024, "split march does not fit in LDS");
 
+  BPM_INLINE static void st(SV* q, int i, cx<CT> v) {
+    SV s;
+    s.x = static_cast<ST>(v.x);
+    s.y = static_cast<ST>(v.y);
+    q[i] = s;
+  }
+  BPM_INLINE static cx<CT> ld(const SV* q, int i) {
+    const SV s = q[i];
+    return {static_cast<CT>(s.x), static_cast<CT>(s.y)};
+  }
+  BPM_INLINE static SV* region(SV* lds, int r) {
+    return reinterpret_cast<SV*>(reinterpret_cast<char*>(lds) + size_t(r) * kRegionBytes);
+  }
+
   template <bool DEFORMED>
-  __device__ static void run(const MarchParams& p, int slice, int t, SV* lds) {
-    const int e = t >= T0 ? 1 : 0;     // 0: psi~_+, 1: psi~_-
-    const int t0 = t - e * T0;
+  BPM_INLINE static void run(const MarchParams& p, int slice, int t, SV* lds) {
+    // wave-uniform: T0 is a multiple of the wavefront size
+    if (__builtin_amdgcn_readfirstlane(t >= T0 ? 1 : 0))
+      run_env<DEFORMED, 1>(p, slice, t - T0, lds);
+    else
+      run_env<DEFORMED, 0>(p, slice, t, lds);
+  }
+
+  // Thread t0 of envelope E (0: psi~_+, 1: psi~_-).
+  template <bool DEFORMED, int E>
+  BPM_INLINE static void run_env(const MarchParams& p, int slice, int t0, SV* lds) {
     const int wv = t0 >> 6, l = t0 & 63;
     const SliceConst& sc = p.sc[slice];
-    const SV* in = static_cast<const SV*>(p.E0_in) + size_t(slice) * N;
-    SV* out = static_cast<SV*>(e ? p.Eh_out : p.E0_out) + size_t(slice) * N;
     const SV* table = static_cast<const SV*>(p.table);
-    SV* G = lds;
-    SV* Gp = lds + kG;
-    SV* own = G + (e * W + wv) * In::kEnv;
+    SV* out = static_cast<SV*>(E ? p.Eh_out : p.E0_out) + size_t(slice) * N;
+    SV* Gp = reinterpret_cast<SV*>(reinterpret_cast<char*>(lds) + kGBytes);
+    SV* own = region(lds, E * W + wv);
+    IV* scratch = reinterpret_cast<IV*>(own);
 
     typename In::Ctx ic;
     In::init(ic, l);
@@ -746,43 +778,39 @@ struct Split4 {
         sincospi(-2.0 * double((t0 + T0 * j) * k1) / double(N), &sn, &cs);
         twx[j * (W - 1) + k1 - 1] = Tw<CT>::from(cs, sn);
       }
-    // own band's propagator at the bins of (wavefront wv, lane l, slot i)
+    // own band's propagator at the bins of (wavefront wv, lane l, slot i);
+    // slab mask of the x samples t0 + T0 i
     cx<double> P[R];
     bool inside[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int k = wv + W * (l + 64 * i);
       const int ks = k < N / 2 ? k : k - N;
-      P[i] = propagator(ks, N, p.dx, sc.k, p.h_half, e ? -1.0 : 1.0, p.dz);
+      P[i] = propagator(ks, N, p.dx, sc.k, p.h_half, E ? -1.0 : 1.0, p.dz);
       const double x = static_cast<double>(t0 + T0 * i - N / 2) * p.dx;
       inside[i] = (x >= p.x_front) && (x < p.x_end);
     }
     const cx<double> d0 = {sc.d[0][0], sc.d[0][1]};
     // coefficient of the other envelope in this envelope's update
-    const cx<double> dx = e ? cx<double>{sc.d[0][4], sc.d[0][5]}
+    const cx<double> dx = E ? cx<double>{sc.d[0][4], sc.d[0][5]}
                             : cx<double>{sc.d[0][2], sc.d[0][3]};
 
-    const SV* src = e == 0 ? in
+    const SV* src = E == 0 ? static_cast<const SV*>(p.E0_in) + size_t(slice) * N
                            : (p.Eh_in ? static_cast<const SV*>(p.Eh_in) + size_t(slice) * N
                                       : nullptr);
     cx<CT> v[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      v[i] = {CT(0), CT(0)};
-      if (src) {
-        const SV s = src[t0 + T0 * i];
-        v[i] = {static_cast<CT>(s.x), static_cast<CT>(s.y)};
-      }
-    }
+    for (int i = 0; i < R; ++i) v[i] = src ? ld(src, t0 + T0 * i) : cx<CT>{CT(0), CT(0)};
 
     for (int n = 0; n < p.Nz; ++n) {
+      // deformation row of this step, fetched early for the coupling
       SV er[R];
       if constexpr (DEFORMED) {
         const SV* row = table + size_t(p.n0 + n) * N;
 #pragma unroll
         for (int i = 0; i < R; ++i) er[i] = row[t0 + T0 * i];
       }
-      // forward: radix-W across wavefronts of this envelope, exchange
+      // forward: radix-W across this envelope's wavefronts, exchange
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         cx<CT> u[W];
@@ -792,20 +820,20 @@ struct Split4 {
 #pragma unroll
         for (int k1 = 0; k1 < W; ++k1) {
           if (k1 > 0) u[k1] = twx[j * (W - 1) + k1 - 1].mul(u[k1]);
-          In::store(G + (e * W + k1) * In::kEnv, t0 + T0 * j, u[k1]);
+          st(region(lds, E * W + k1), t0 + T0 * j, u[k1]);
         }
       }
       lds_barrier();
       cx<CT> z[1][R];
 #pragma unroll
-      for (int i = 0; i < R; ++i) z[0][i] = In::load(own, l + 64 * i);
+      for (int i = 0; i < R; ++i) z[0][i] = ld(own, l + 64 * i);
       wave_sync();
-      In::template fft_n<false, In::kWave, 1>(z, ic.tw, own, l, ic.xbuf);
+      In::template fft_n<false, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
 #pragma unroll
       for (int i = 0; i < R; ++i) z[0][i] = conv<CT>(cmul(conv<double>(z[0][i]), P[i]));
-      In::template fft_n<true, In::kWave, 1>(z, ic.tw, own, l, ic.xbuf);
+      In::template fft_n<true, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
 #pragma unroll
-      for (int i = 0; i < R; ++i) In::store(Gp + (e * W + wv) * M, l + 64 * i, z[0][i]);
+      for (int i = 0; i < R; ++i) st(Gp + (E * W + wv) * M, l + 64 * i, z[0][i]);
       lds_barrier();
       // inverse radix-W for both envelopes at this thread's x samples, and
       // the coupling (Eq. fov10) of each group of W samples right away
@@ -814,8 +842,8 @@ struct Split4 {
         cx<CT> ua[W], ub[W];
 #pragma unroll
         for (int k1 = 0; k1 < W; ++k1) {
-          ua[k1] = In::load(Gp + k1 * M, t0 + T0 * j);
-          ub[k1] = In::load(Gp + (W + k1) * M, t0 + T0 * j);
+          ua[k1] = ld(Gp + k1 * M, t0 + T0 * j);
+          ub[k1] = ld(Gp + (W + k1) * M, t0 + T0 * j);
           if (k1 > 0) {
             ua[k1] = twx[j * (W - 1) + k1 - 1].mulc(ua[k1]);
             ub[k1] = twx[j * (W - 1) + k1 - 1].mulc(ub[k1]);
@@ -826,28 +854,24 @@ struct Split4 {
 #pragma unroll
         for (int q = 0; q < W; ++q) {
           const int i = j + J * q;
-          const cx<CT> self = e ? ub[q] : ua[q];
-          const cx<CT> other = e ? ua[q] : ub[q];
-          v[i] = self;
+          const cx<CT> self = E ? ub[q] : ua[q];
+          const cx<CT> other = E ? ua[q] : ub[q];
           if (inside[i]) {
             cx<double> c = dx;
             if constexpr (DEFORMED) {
               const cx<double> ee = {static_cast<double>(er[i].x),
                                      static_cast<double>(er[i].y)};
-              c = e ? cmulc(dx, ee) : cmul(dx, ee);
+              c = E ? cmulc(dx, ee) : cmul(dx, ee);
             }
             v[i] = conv<CT>(cmuladd(d0, conv<double>(self), c, conv<double>(other)));
+          } else {
+            v[i] = self;
           }
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      SV s;
-      s.x = static_cast<ST>(v[i].x);
-      s.y = static_cast<ST>(v[i].y);
-      out[t0 + T0 * i] = s;
-    }
+    for (int i = 0; i < R; ++i) st(out, t0 + T0 * i, v[i]);
   }
 };
 
@@ -855,7 +879,7 @@ struct Split4 {
 // either transform (Eq. fov10 per step, first-order splitting).
 // March of one slice with both envelopes in every thread.
 template <class Tr, bool DEFORMED>
-__device__ void march_slice_joint(const MarchParams& p, int slice, int t,
+BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
                                   typename Tr::SV* lds) {
   using CT = typename Tr::CT;
   using ST = typename Tr::ST;
@@ -952,7 +976,7 @@ __device__ void march_slice_joint(const MarchParams& p, int slice, int t,
 }
 
 template <class Tr, bool DEFORMED>
-__device__ void march_slice(const MarchParams& p, int slice, int t,
+BPM_INLINE void march_slice(const MarchParams& p, int slice, int t,
                             typename Tr::SV* lds) {
   if constexpr (Tr::kSplit) {
     Tr::template run<DEFORMED>(p, slice, t, lds);
@@ -963,7 +987,7 @@ __device__ void march_slice(const MarchParams& p, int slice, int t,
 
 template <class M, bool DEFORMED>
 __global__ void __launch_bounds__(M::T) march_kernel(MarchParams p) {
-  __shared__ typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
+  __shared__ __align__(16) typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
   march_slice<M, DEFORMED>(p, blockIdx.x, threadIdx.x, lds);
 }
 
@@ -975,7 +999,7 @@ template <class M>
 __global__ void __launch_bounds__(M::T)
     march_batch_kernel(const BatchItem* __restrict__ items,
                        const int* __restrict__ offsets) {
-  __shared__ typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
+  __shared__ __align__(16) typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
   const int k0 = offsets[blockIdx.x];
   const int k1 = offsets[blockIdx.x + 1];
   for (int k = k0; k < k1; ++k) {
@@ -1119,9 +1143,17 @@ int march_occupancy(int prec, int Nx, int sched, int* wg_per_cu,
 // Measured defaults (cell-updates/s on MI355X, Nz = 1000, >= 256 slices):
 // the envelope-split four-step is fastest where it exists (Nx 1024, 2048),
 // the four-step elsewhere.
+// Fastest schedule per (precision, Nx), measured on MI355X (march of >= 256
+// slices); 0 Stockham, 1 four-step, 2 envelope-split four-step.
 int default_schedule(int prec, int Nx) {
-  (void)prec;
-  return (Nx == 1024 || Nx == 2048) ? 2 : 1;
+  const int col = Nx == 256 ? 0 : Nx == 512 ? 1 : Nx == 1024 ? 2 : Nx == 2048 ? 3 : 4;
+  static const int kBest[3][5] = {
+      /* fp64  */ {0, 1, 2, 2, 1},
+      /* fp32  */ {0, 1, 2, 2, 0},
+      /* fp32s */ {1, 1, 2, 2, 1},
+  };
+  const int row = prec == BPM_PREC_FP64 ? 0 : prec == BPM_PREC_FP32 ? 1 : 2;
+  return kBest[row][col];
 }
 
 int launch_deform(int prec, int Nx, int Nz, double h, const double* u,
