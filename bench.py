@@ -49,21 +49,30 @@ def lds_bytes_per_cell_update(Nx: int, storage_bytes: int) -> float:
     return 2 * accesses * storage_bytes
 
 
+def kernel_source_sha256() -> str:
+    """sha256 over the device sources (csrc/*.h and *.hip, sorted by name):
+    the key under which hardware-counter records are valid."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2201_08500_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload: str, precision: str):
     """HBM bytes per march launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE record (scaled by the reference copy), or None when that
-    record is missing or was taken on a different kernel source."""
-    import hashlib
+    record is missing or was taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", f"march_{workload}_traffic.json")
-    src = os.path.join(ROOT, "paper_2201_08500_amd", "csrc", "bpm_march.hip")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if rec.get("source_sha256") != sha or rec.get("precision") != precision:
+    if rec.get("source_sha256") != kernel_source_sha256() or rec.get("precision") != precision:
         return None
     return float(rec["traffic_bytes_per_launch"])
 

@@ -97,7 +97,13 @@ int bpm_plan_set_crystal(bpm_plan* plan, double x_front, double thickness);
 /* Relative frequency offsets delta_w of the Nomega slices (host array,
  * copied). */
 int bpm_plan_set_detuning(bpm_plan* plan, const double* delta);
-/* split_order: 1 (Eq. fov4), 2 or 4 (Eq. split-op); zassenhaus: 0 or 1. */
+/* split_order: 1 -- A(dz) B(dz) per step (Eq. fov4); 2 -- B(dz/2) A(dz)
+ * B(dz/2); 4 -- B(t dz/2) A(t dz) B((1-t) dz/2) A((1-2t) dz) B((1-t) dz/2)
+ * A(t dz) B(t dz/2), t = 1/(2 - 2^(1/3)) (Eq. split-op).  A is the free
+ * propagation, B the coupling with the deformation row of the step.  Every
+ * schedule and precision supports all three; order 4 costs three transform
+ * round trips per step.  zassenhaus: 0 or 1 (the e^{q/8} factor of d0 per B
+ * sub-step, end of Section 2.1).  BPM_EINVAL for other values. */
 int bpm_plan_set_options(bpm_plan* plan, int split_order, int zassenhaus);
 
 /* Transform schedule (BPM_SCHED_*); default AUTO.  get returns the

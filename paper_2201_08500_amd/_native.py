@@ -153,7 +153,10 @@ class Plan:
                 self._h, float(0.0 if x_front is None else x_front),
                 float(math.inf if thickness is None else thickness)))
         if delta is not None:
-            arr = (ctypes.c_double * self.Nomega)(*[float(d) for d in delta])
+            delta = [float(d) for d in delta]
+            if len(delta) != self.Nomega:
+                raise ValueError(f"delta has {len(delta)} values for {self.Nomega} slices")
+            arr = (ctypes.c_double * self.Nomega)(*delta)
             _check(L.bpm_plan_set_detuning(self._h, arr))
         if split_order != 1 or not zassenhaus:
             _check(L.bpm_plan_set_options(self._h, int(split_order),

@@ -29,22 +29,28 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False, extra_flags=()) -> str:
-    """Compile every source and link libbpm.so; returns its path."""
+    """Compile every source (the kernel units in parallel) and link
+    libbpm.so; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = _hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     # host plan: strict FP64 evaluation order for the plan constants
     host_obj = os.path.join(objdir, "bpm_host.o")
-    _run([hipcc, "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-c",
-          os.path.join(CSRC, "bpm_host.cpp"), "-o", host_obj], verbose)
-    objs.append(host_obj)
+    jobs.append([hipcc, "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-c",
+                 os.path.join(CSRC, "bpm_host.cpp"), "-o", host_obj])
+    objs = [host_obj]
     for src in sorted(os.listdir(CSRC)):
         if src.endswith(".hip"):
             obj = os.path.join(objdir, src[:-4] + ".o")
-            _run([hipcc, *DEVICE_FLAGS, *extra_flags, "-c",
-                  os.path.join(CSRC, src), "-o", obj], verbose)
+            jobs.append([hipcc, *DEVICE_FLAGS, *extra_flags, "-c",
+                         os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(_run, cmd, verbose) for cmd in jobs]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o",
           tmp], verbose)

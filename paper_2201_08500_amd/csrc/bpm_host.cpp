@@ -90,7 +90,7 @@ int compute_slice_constants(bpm_plan* p) {
     const double c = std::sqrt(1.0 - sh * sh);
     s.k = k;
     for (int i = 0; i < nsub; ++i) {
-      const double dZ = b[i] * k * p->dz;
+      const double dZ = b[i] * (k * p->dz);
       const cplx q = dZ * dZ * p->chih * p->chihbar / (c * c);
       if (std::abs(q) > 16.0)
         return fail(BPM_EINVAL,
@@ -182,7 +182,7 @@ struct DeformJob {
 };
 
 struct BatchGroup {
-  int prec, Nx, sched;
+  int prec, Nx, sched, order;
   int n_groups;
   int n_items;
   bpm::BatchItem* d_items;
@@ -233,18 +233,18 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
 
   auto* b = new bpm_batch();
-  std::map<std::tuple<int, int, int>, std::vector<std::pair<int, int>>> by_variant;
+  std::map<std::tuple<int, int, int, int>, std::vector<std::pair<int, int>>> by_variant;
   for (int i = 0; i < njobs; ++i) {
     const bpm_plan* p = jobs[i].plan;
     if (jobs[i].u_field)
       b->deforms.push_back({p->precision, p->Nx, p->Nz, p->h, jobs[i].u_field,
                             jobs[i].workspace});
     for (int w = 0; w < p->Nomega; ++w)
-      by_variant[{p->precision, p->Nx, plan_schedule(p)}].push_back({i, w});
+      by_variant[{p->precision, p->Nx, plan_schedule(p), p->split_order}].push_back({i, w});
   }
   // Host work lists: per variant, items ordered by group, longest first.
   struct HostGroup {
-    int prec, Nx, sched, n_groups;
+    int prec, Nx, sched, order, n_groups;
     std::vector<bpm::BatchItem> items;
     std::vector<int> offsets;
   };
@@ -252,9 +252,10 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
   for (auto& kv : by_variant) {
     const int prec = std::get<0>(kv.first), Nx = std::get<1>(kv.first);
     const int sched = std::get<2>(kv.first);
+    const int order = std::get<3>(kv.first);
     auto& slices = kv.second;
     int per_cu = 0, threads = 0;
-    int rc = bpm::march_occupancy(prec, Nx, sched, &per_cu, &threads);
+    int rc = bpm::march_occupancy(prec, Nx, sched, order, &per_cu, &threads);
     if (rc) {
       delete b;
       return fail(rc, "occupancy query failed for Nx " + std::to_string(Nx));
@@ -276,7 +277,7 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
       l.first += jobs[s.first].plan->Nz;
       heap.push(l);
     }
-    HostGroup hg{prec, Nx, sched, G, {}, {0}};
+    HostGroup hg{prec, Nx, sched, order, G, {}, {0}};
     for (int g = 0; g < G; ++g) {
       for (auto& s : per_group[g]) {
         const bpm_job& j = jobs[s.first];
@@ -316,7 +317,8 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
     std::memcpy(staging->data() + offs_off[g], host[g].offsets.data(),
                 host[g].offsets.size() * sizeof(int));
     char* base = static_cast<char*>(b->d_mem);
-    b->groups.push_back({host[g].prec, host[g].Nx, host[g].sched, host[g].n_groups,
+    b->groups.push_back({host[g].prec, host[g].Nx, host[g].sched, host[g].order,
+                         host[g].n_groups,
                          static_cast<int>(host[g].items.size()),
                          reinterpret_cast<bpm::BatchItem*>(base + item_off[g]),
                          reinterpret_cast<int*>(base + offs_off[g])});
@@ -353,7 +355,7 @@ int batch_launch(const bpm_batch* b, hipStream_t s) {
     if (rc) return fail(rc, "deformation pre-pass launch failed");
   }
   for (const auto& g : b->groups) {
-    int rc = bpm::launch_march_batch(g.prec, g.Nx, g.sched, g.d_items,
+    int rc = bpm::launch_march_batch(g.prec, g.Nx, g.sched, g.order, g.d_items,
                                      g.d_offsets, g.n_groups, s);
     if (rc) return fail(rc, "persistent march launch failed");
   }
@@ -441,8 +443,6 @@ int bpm_plan_set_options(bpm_plan* p, int split_order, int zassenhaus) {
     return fail(BPM_EINVAL, "split_order must be 1, 2 or 4");
   if (zassenhaus != 0 && zassenhaus != 1)
     return fail(BPM_EINVAL, "zassenhaus must be 0 or 1");
-  if (split_order != 1)
-    return fail(BPM_EUNSUPPORTED, "only first-order splitting is implemented on the GPU");
   p->split_order = split_order;
   p->zassenhaus = zassenhaus;
   return BPM_OK;
@@ -517,7 +517,7 @@ int bpm_march(const bpm_plan* cp, const void* E0_in, const void* table,
   int rc = freeze(p);
   if (rc) return rc;
   const bpm::MarchParams m = march_params(p, E0_in, table, E0_out, Eh_out);
-  rc = bpm::launch_march(p->precision, p->Nx, plan_schedule(p), p->Nomega, m,
+  rc = bpm::launch_march(p->precision, p->Nx, plan_schedule(p), p->split_order, p->Nomega, m,
                          static_cast<hipStream_t>(stream));
   if (rc == BPM_EUNSUPPORTED) return fail(rc, "unsupported size/precision");
   if (rc) return fail(rc, "march kernel launch failed");
@@ -542,7 +542,7 @@ int bpm_march_segment(const bpm_plan* cp, const void* E0_in, const void* Eh_in,
   m.Eh_in = Eh_in;
   m.n0 = n0;
   m.Nz = nsteps;
-  rc = bpm::launch_march(p->precision, p->Nx, plan_schedule(p), p->Nomega, m,
+  rc = bpm::launch_march(p->precision, p->Nx, plan_schedule(p), p->split_order, p->Nomega, m,
                          static_cast<hipStream_t>(stream));
   if (rc == BPM_EUNSUPPORTED) return fail(rc, "unsupported size/precision");
   if (rc) return fail(rc, "march kernel launch failed");

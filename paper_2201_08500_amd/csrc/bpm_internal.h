@@ -1,5 +1,6 @@
 // Internal declarations shared by the host plan (bpm_host.cpp) and the
-// gfx950 kernels (bpm_march.hip).  Not part of the public ABI.
+// gfx950 kernels (bpm_device.h, bpm_march.hip, march_*.hip).  Not part of
+// the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,15 +49,26 @@ struct BatchItem {
 
 int launch_deform(int prec, int Nx, int Nz, double h, const double* u,
                   void* table, hipStream_t stream);
-// sched: transform schedule (0 Stockham, 1 four-step), see bpm.h.
-int launch_march(int prec, int Nx, int sched, int Nomega,
+// sched: transform schedule (0 Stockham, 1 four-step, 2 envelope-split);
+// order: splitting order 1, 2 or 4 (sub-steps of Eq. split-op).
+int launch_march(int prec, int Nx, int sched, int order, int Nomega,
                  const MarchParams& p, hipStream_t stream);
 // Persistent launch: n_groups work groups, group g runs
 // items[offsets[g] .. offsets[g+1]) (device arrays).
-int launch_march_batch(int prec, int Nx, int sched, const BatchItem* items,
+int launch_march_batch(int prec, int Nx, int sched, int order, const BatchItem* items,
                        const int* offsets, int n_groups, hipStream_t stream);
 // Resident work groups per CU and threads per group of a march variant.
-int march_occupancy(int prec, int Nx, int sched, int* wg_per_cu, int* threads);
+int march_occupancy(int prec, int Nx, int sched, int order, int* wg_per_cu,
+                    int* threads);
+// Per-precision kernel units (march_<precision>.hip).
+template <int PREC>
+int launch_march_p(int Nx, int sched, int order, int Nomega, const MarchParams& p,
+                   hipStream_t stream);
+template <int PREC>
+int launch_march_batch_p(int Nx, int sched, int order, const BatchItem* items,
+                         const int* offsets, int n_groups, hipStream_t stream);
+template <int PREC>
+int march_occupancy_p(int Nx, int sched, int order, int* wg_per_cu, int* threads);
 // Library default schedule of (precision, Nx).
 int default_schedule(int prec, int Nx);
 

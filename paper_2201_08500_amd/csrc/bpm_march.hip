@@ -1,1148 +1,54 @@
-// gfx950 kernels of the FFT beam-propagation z-march.
-//
-// One workgroup advances one frequency slice through all Nz split steps
-// (Eq. fov10, first-order splitting of Eq. fov4).  Both envelopes stay
-// on-chip for the whole march: thread t of T = Nx/R threads keeps the R
-// samples t + T*i (i = 0..R-1) of psi~_+ and of psi~_- in registers.  Each
-// FFT along x is a Stockham autosort transform: radix-Rp butterflies in
-// registers, one LDS exchange between passes (both envelopes exchanged under
-// a single barrier), natural-order output landing back in the same register
-// slots, so the propagator (a function of the bin K) and the coupling (a
-// function of x) are register-local and need no extra exchange.  HBM traffic
-// per slice-step is one row of the deformation table exp(i h u).
-//
-// There is no matrix-core work here: the step is FFT plus pointwise complex
-// arithmetic, bound by VALU and LDS throughput.
+// Host-side dispatch of the z-march kernels (one kernel unit per precision,
+// march_fp64.hip / march_fp32.hip / march_fp32s.hip) and the deformation
+// pre-pass exp(i h u) of Eq. Authier.
 
-#include <utility>
-
-#include "bpm_internal.h"
-
-#define BPM_INLINE __device__ __forceinline__
+#include "bpm_device.h"
 
 namespace bpm {
-namespace {
 
-// ---------------------------------------------------------------- complex --
+#define BPM_EXTERN_PREC(P)                                                         \
+  extern template int launch_march_p<P>(int, int, int, int, const MarchParams&,    \
+                                        hipStream_t);                              \
+  extern template int launch_march_batch_p<P>(int, int, int, const BatchItem*,     \
+                                              const int*, int, hipStream_t);       \
+  extern template int march_occupancy_p<P>(int, int, int, int*, int*);
+BPM_EXTERN_PREC(BPM_PREC_FP64)
+BPM_EXTERN_PREC(BPM_PREC_FP32)
+BPM_EXTERN_PREC(BPM_PREC_FP32S)
+#undef BPM_EXTERN_PREC
 
-template <class T>
-struct cx {
-  T x, y;
-};
-
-template <class T>
-__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
-  return {a.x + b.x, a.y + b.y};
-}
-template <class T>
-__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
-  return {a.x - b.x, a.y - b.y};
-}
-template <class T>
-__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-// a * conj(b)
-template <class T>
-__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
-  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
-}
-// p*x + q*y with the real parts and imaginary parts each one FMA chain
-template <class T>
-__device__ __forceinline__ cx<T> cmuladd(cx<T> p, cx<T> x, cx<T> q, cx<T> y) {
-  return {p.x * x.x - p.y * x.y + q.x * y.x - q.y * y.y,
-          p.x * x.y + p.y * x.x + q.x * y.y + q.y * y.x};
-}
-// multiply by -i (forward transform) or +i (inverse transform)
-template <bool INV, class T>
-__device__ __forceinline__ cx<T> rot(cx<T> a) {
-  if constexpr (INV)
-    return {-a.y, a.x};
-  else
-    return {a.y, -a.x};
-}
-
-template <class D, class S>
-__device__ __forceinline__ cx<D> conv(cx<S> a) {
-  return {static_cast<D>(a.x), static_cast<D>(a.y)};
-}
-
-// A twiddle factor w, held in FP64 for every precision.  A twiddle is the
-// same fixed number at every z-step, so a plain FP32 rounding of it (~3e-8)
-// is an error of the step operator itself: repeated Nz times, it grows
-// linearly (measured: relL2 1.8e-4 after 4000 steps in vacuum).  In FP32
-// arithmetic the product x w is therefore formed in FP64 and rounded once,
-// which leaves only the rounding of the data: that error does not add up
-// coherently and grows like sqrt(Nz) (9.7e-6 after 4000 steps).  On MI355X
-// the two conversions and four FP64 FMAs cost the same issue slots as an
-// unevaluated hi + lo FP32 pair, which in the compiled code did not remove
-// the drift.
-template <class T>
-struct Tw {
-  cx<double> w;
-  BPM_INLINE static Tw from(double c, double s) { return {{c, s}}; }
-  BPM_INLINE cx<T> mul(cx<T> x) const {
-    if constexpr (sizeof(T) == 8) {
-      return cmul(x, w);
-    } else {
-      const cx<double> r = cmul(cx<double>{x.x, x.y}, w);
-      return {static_cast<float>(r.x), static_cast<float>(r.y)};
-    }
-  }
-  BPM_INLINE cx<T> mulc(cx<T> x) const {
-    if constexpr (sizeof(T) == 8) {
-      return cmulc(x, w);
-    } else {
-      const cx<double> r = cmulc(cx<double>{x.x, x.y}, w);
-      return {static_cast<float>(r.x), static_cast<float>(r.y)};
-    }
-  }
-};
-
-// ------------------------------------------------------- small DFT kernels --
-// Forward kernel exp(-2 pi i n k / R), inverse exp(+2 pi i n k / R); no
-// scaling.  Outputs are in natural order.
-
-constexpr double kCos16[16] = {
-    1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
-    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
-    -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977,
-    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674};
-
-// a * W16^J with W16 = exp(-+2 pi i / 16)
-template <int J, bool INV, class T>
-__device__ __forceinline__ cx<T> tw16(cx<T> a) {
-  constexpr int j = J & 15;
-  if constexpr (j == 0) {
-    return a;
-  } else if constexpr (j == 4) {
-    return rot<INV>(a);
-  } else if constexpr (j == 8) {
-    return {-a.x, -a.y};
-  } else if constexpr (j == 12) {
-    return rot<!INV>(a);
-  } else {
-    constexpr double c = kCos16[j];
-    constexpr double s = kCos16[(j + 12) & 15];  // sin(2 pi j / 16)
-    constexpr double si = INV ? s : -s;
-    if constexpr (sizeof(T) == 4) {
-      // FP64 product rounded once, as for the pass twiddles (see Tw)
-      const double xr = a.x, xi = a.y;
-      return {static_cast<float>(xr * c - xi * si),
-              static_cast<float>(xr * si + xi * c)};
-    } else {
-      const T wr = static_cast<T>(c);
-      const T wi = static_cast<T>(si);
-      return {a.x * wr - a.y * wi, a.x * wi + a.y * wr};
-    }
-  }
-}
-
-template <bool INV, class T>
-__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
-  const cx<T> t = a;
-  a = t + b;
-  b = t - b;
-}
-
-template <bool INV, class T>
-__device__ __forceinline__ void dft4(cx<T>& x0, cx<T>& x1, cx<T>& x2,
-                                     cx<T>& x3) {
-  const cx<T> t0 = x0 + x2, t1 = x0 - x2, t2 = x1 + x3;
-  const cx<T> t3 = rot<INV>(x1 - x3);
-  x0 = t0 + t2;
-  x2 = t0 - t2;
-  x1 = t1 + t3;
-  x3 = t1 - t3;
-}
-
-template <int R, bool INV, class T>
-__device__ __forceinline__ void dft(cx<T> (&v)[R]) {
-  if constexpr (R == 2) {
-    dft2<INV>(v[0], v[1]);
-  } else if constexpr (R == 4) {
-    dft4<INV>(v[0], v[1], v[2], v[3]);
-  } else if constexpr (R == 8) {
-    // even/odd split: X_k = E_k + W8^k O_k, X_{k+4} = E_k - W8^k O_k
-    dft4<INV>(v[0], v[2], v[4], v[6]);
-    dft4<INV>(v[1], v[3], v[5], v[7]);
-    const cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-    const cx<T> o0 = v[1];
-    const cx<T> o1 = tw16<2, INV>(v[3]);
-    const cx<T> o2 = tw16<4, INV>(v[5]);
-    const cx<T> o3 = tw16<6, INV>(v[7]);
-    v[0] = e0 + o0;
-    v[4] = e0 - o0;
-    v[1] = e1 + o1;
-    v[5] = e1 - o1;
-    v[2] = e2 + o2;
-    v[6] = e2 - o2;
-    v[3] = e3 + o3;
-    v[7] = e3 - o3;
-  } else if constexpr (R == 16) {
-    // 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
-    v[5] = tw16<1, INV>(v[5]);
-    v[6] = tw16<2, INV>(v[6]);
-    v[7] = tw16<3, INV>(v[7]);
-    v[9] = tw16<2, INV>(v[9]);
-    v[10] = tw16<4, INV>(v[10]);
-    v[11] = tw16<6, INV>(v[11]);
-    v[13] = tw16<3, INV>(v[13]);
-    v[14] = tw16<6, INV>(v[14]);
-    v[15] = tw16<9, INV>(v[15]);
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
-    cx<T> o[16];
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-      for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = o[i];
-  } else {
-    static_assert(R == 2, "unsupported radix");
-  }
-}
-
-// ------------------------------------------------------ double-double math --
-// Used once per slice and bin to form the propagator phase dz*kz, which is
-// ~2.5e4 rad at typical sizes: a plain FP64 evaluation would carry ~1e-12 rad
-// of error that every one of the Nz steps repeats.  Evaluated to ~1e-30
-// relative and reduced modulo 2 pi before the final FP64 rounding.
-
-struct dd {
-  double hi, lo;
-};
-
-#pragma clang fp contract(off)
-
-__device__ __forceinline__ dd quick_two_sum(double a, double b) {
-  const double s = a + b;
-  return {s, b - (s - a)};
-}
-__device__ __forceinline__ dd two_sum(double a, double b) {
-  const double s = a + b;
-  const double bb = s - a;
-  return {s, (a - (s - bb)) + (b - bb)};
-}
-__device__ __forceinline__ dd two_prod(double a, double b) {
-  const double p = a * b;
-  return {p, __fma_rn(a, b, -p)};
-}
-__device__ __forceinline__ dd dd_add(dd a, dd b) {
-  dd s = two_sum(a.hi, b.hi);
-  const dd t = two_sum(a.lo, b.lo);
-  s.lo += t.hi;
-  s = quick_two_sum(s.hi, s.lo);
-  s.lo += t.lo;
-  return quick_two_sum(s.hi, s.lo);
-}
-__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
-__device__ __forceinline__ dd dd_mul(dd a, dd b) {
-  dd p = two_prod(a.hi, b.hi);
-  p.lo += a.hi * b.lo + a.lo * b.hi;
-  return quick_two_sum(p.hi, p.lo);
-}
-__device__ __forceinline__ dd dd_mul_d(dd a, double b) {
-  dd p = two_prod(a.hi, b);
-  p.lo += a.lo * b;
-  return quick_two_sum(p.hi, p.lo);
-}
-__device__ __forceinline__ dd dd_div_d(dd a, double b) {
-  const double q1 = a.hi / b;
-  const dd p = two_prod(q1, b);
-  const double r = ((a.hi - p.hi) - p.lo) + a.lo;
-  return quick_two_sum(q1, r / b);
-}
-__device__ __forceinline__ dd dd_sqrt(dd a) {
-  const double s = sqrt(a.hi);
-  const dd s2 = two_prod(s, s);
-  const double r = (((a.hi - s2.hi) - s2.lo) + a.lo) / (2.0 * s);
-  return quick_two_sum(s, r);
-}
-
-#pragma clang fp contract(fast)
-
-// 2 pi as a double-double
-constexpr double kTwoPiHi = 6.283185307179586232;
-constexpr double kTwoPiLo = 2.4492935982947064e-16;
-
-// exp(i frac dz sqrt(k^2 - (K_m + band h/2)^2)) / Nx for signed bin m,
-// K_m = 2 pi m / (Nx dx); principal root (decay) for evanescent waves.
-__device__ cx<double> propagator(int m, int Nx, double dx, double k,
-                                 double h_half, double band, double len) {
-  const dd two_pi = {kTwoPiHi, kTwoPiLo};
-  const dd K = dd_div_d(dd_mul_d(two_pi, static_cast<double>(m)),
-                        static_cast<double>(Nx) * dx);
-  const dd kp = dd_add(K, dd{band * h_half, 0.0});
-  const dd kz2 = dd_add(two_prod(k, k), dd_neg(dd_mul(kp, kp)));
-  const double inv_n = 1.0 / static_cast<double>(Nx);
-  if (kz2.hi < 0.0) {
-    const double decay = len * sqrt(-kz2.hi);
-    return {exp(-decay) * inv_n, 0.0};
-  }
-  dd phi = dd_mul_d(dd_sqrt(kz2), len);
-  const double n = floor(phi.hi / kTwoPiHi);
-  phi = dd_add(phi, dd_neg(dd_mul_d(two_pi, n)));
-  if (phi.hi < 0.0) phi = dd_add(phi, two_pi);
-  if (phi.hi >= kTwoPiHi) phi = dd_add(phi, dd_neg(two_pi));
-  const double r = phi.hi + phi.lo;
-  double s, c;
-  sincos(r, &s, &c);
-  return {c * inv_n, s * inv_n};
-}
-
-// ---------------------------------------------------------------- barrier --
-// Workgroup barrier ordering LDS traffic only: global loads in flight (the
-// prefetched deformation row) are not drained by it.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// Orders LDS accesses of one wavefront in the compiler only: the hardware
-// executes a wavefront's LDS instructions in program order.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// -------------------------------------------------------------- precision --
-
-template <int PREC>
-struct Prec;
-template <>
-struct Prec<BPM_PREC_FP64> {
-  using CT = double;  // butterfly arithmetic
-  using ST = double;  // LDS, fields and deformation table
-};
-template <>
-struct Prec<BPM_PREC_FP32> {
-  using CT = float;
-  using ST = float;
-};
-template <>
-struct Prec<BPM_PREC_FP32S> {
-  using CT = double;
-  using ST = float;
-};
-
-template <class T>
-struct vec2;
-template <>
-struct vec2<float> {
-  using type = float2;
-};
-template <>
-struct vec2<double> {
-  using type = double2;
-};
-
-// ------------------------------------------------------------- the march --
-
-template <int PREC, int N_, int R_, int... RADS>
-struct March {
-  static constexpr bool kSplit = false;
-  static constexpr int N = N_;  // transform length
-  static constexpr int R = R_;  // samples per thread per envelope
-  using CT = typename Prec<PREC>::CT;
-  using ST = typename Prec<PREC>::ST;
-  using SV = typename vec2<ST>::type;
-  static constexpr int T = N / R;             // threads per slice
-  static constexpr int NP = sizeof...(RADS);  // Stockham passes per FFT
-  static constexpr int rad[NP] = {RADS...};
-  static constexpr int prod_rad() {
-    int p = 1;
-    for (int i = 0; i < NP; ++i) p *= rad[i];
-    return p;
-  }
-  static_assert(prod_rad() == N, "radices must multiply to N");
-  static constexpr int ns(int p) {  // sub-transform length before pass p
-    int s = 1;
-    for (int i = 0; i < p; ++i) s *= rad[i];
-    return s;
-  }
-  static constexpr int tw_off(int p) {  // first twiddle of pass p
-    int o = 0;
-    for (int i = 1; i < p; ++i) o += (R / rad[i]) * (rad[i] - 1);
-    return o;
-  }
-  static constexpr int NTW = tw_off(NP) > 0 ? tw_off(NP) : 1;
-  // LDS address of sample idx in the exchange after pass p: one gap of Ns
-  // slots every max(Rp Ns, L) samples, L = samples per 128-byte bank row.
-  // The pass writes x[(Rp a + r) Ns + b] for consecutive butterflies
-  // (b = jb mod Ns, a = jb / Ns) and the next pass reads consecutive samples;
-  // with the gaps both hit distinct banks across each group of L lanes.
-  static constexpr int kL = 128 / int(sizeof(SV));
-  static constexpr int pad_div(int p) {
-    return rad[p] * ns(p) > kL ? rad[p] * ns(p) : kL;
-  }
-  static constexpr int env_slots() {
-    int m = N;
-    for (int p = 0; p + 1 < NP; ++p) {
-      const int e = N + ns(p) * ((N - 1) / pad_div(p)) ;
-      m = e > m ? e : m;
-    }
-    return m;
-  }
-  static constexpr int kEnv = env_slots();
-  // Two LDS buffers (one barrier per exchange) when they fit in 160 KiB.
-  static constexpr size_t kEnvBytes = size_t(kEnv) * sizeof(SV);
-  static constexpr int NBUF = (4 * kEnvBytes <= 160 * 1024) ? 2 : 1;
-  static constexpr size_t kLdsBytes = NBUF * 2 * kEnvBytes;
-
-  using Reg = cx<CT>[R];
-
-  BPM_INLINE static void store(SV* lds, int idx, cx<CT> v) {
-    SV s;
-    s.x = static_cast<ST>(v.x);
-    s.y = static_cast<ST>(v.y);
-    lds[idx] = s;
-  }
-  BPM_INLINE static cx<CT> load(const SV* lds, int idx) {
-    const SV s = lds[idx];
-    return {static_cast<CT>(s.x), static_cast<CT>(s.y)};
-  }
-
-  // Stockham pass P (radix rad[P], sub-length Ns): butterfly jb reads
-  // x[jb + r N/Rp], applies twiddles W_{Ns Rp}^{r (jb mod Ns)}, transforms,
-  // and writes x[(jb/Ns) Ns Rp + jb mod Ns + r Ns].  Thread t owns
-  // butterflies jb = t + s T and, on input, register slot s + r (R/Rp).
-  // Exchange synchronisation: kDouble / kSingle -- a work-group barrier per
-  // exchange with two / one LDS buffers; kWave -- the T threads are one
-  // wavefront, whose LDS operations execute in program order, so a
-  // compiler-only fence is enough and one buffer is reused.
-  enum { kDouble = 0, kSingle = 1, kWave = 2 };
-  static constexpr int kSync = NBUF == 2 ? kDouble : kSingle;
-
-  // Stockham pass P over NE envelopes v[e] (LDS region e at lds + e kEnv).
-  template <int P, bool INV, int SYNC, int NE>
-  BPM_INLINE static void pass_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
-                                SV* lds, int t, int& xbuf) {
-    constexpr int Rp = rad[P];
-    constexpr int Ns = ns(P);
-    constexpr int G = R / Rp;
-    constexpr bool last = (P == NP - 1);
-    constexpr int D = pad_div(P);
-    SV* base_lds = lds + (SYNC == kDouble ? xbuf * NE * kEnv : 0);
-#pragma unroll
-    for (int s = 0; s < G; ++s) {
-      cx<CT> u[NE][Rp];
-#pragma unroll
-      for (int e = 0; e < NE; ++e)
-#pragma unroll
-        for (int r = 0; r < Rp; ++r) u[e][r] = v[e][s + r * G];
-      if constexpr (P > 0) {
-#pragma unroll
-        for (int r = 1; r < Rp; ++r) {
-          const Tw<CT> w = tw[tw_off(P) + s * (Rp - 1) + (r - 1)];
-#pragma unroll
-          for (int e = 0; e < NE; ++e)
-            u[e][r] = INV ? w.mulc(u[e][r]) : w.mul(u[e][r]);
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < NE; ++e) dft<Rp, INV>(u[e]);
-      if constexpr (last) {
-#pragma unroll
-        for (int e = 0; e < NE; ++e)
-#pragma unroll
-          for (int r = 0; r < Rp; ++r) v[e][s + r * G] = u[e][r];
-      } else {
-        const int jb = t + s * T;
-        const int base = (jb / Ns) * Ns * Rp + (jb % Ns);
-#pragma unroll
-        for (int r = 0; r < Rp; ++r) {
-          const int idx = base + r * Ns;
-          const int slot = idx + Ns * (idx / D);
-#pragma unroll
-          for (int e = 0; e < NE; ++e) store(base_lds + e * kEnv, slot, u[e][r]);
-        }
-      }
-    }
-    if constexpr (!last) {
-      if constexpr (SYNC == kWave)
-        wave_sync();
-      else
-        lds_barrier();
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int idx = t + T * i;
-        const int slot = idx + Ns * (idx / D);
-#pragma unroll
-        for (int e = 0; e < NE; ++e) v[e][i] = load(base_lds + e * kEnv, slot);
-      }
-      if constexpr (SYNC == kSingle) {
-        lds_barrier();
-      } else if constexpr (SYNC == kWave) {
-        wave_sync();
-      } else {
-        xbuf ^= 1;
-      }
-    }
-  }
-
-  template <bool INV, int SYNC, int NE, int... P>
-  BPM_INLINE static void fft_impl(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
-                                  SV* lds, int t, int& xbuf,
-                                  std::integer_sequence<int, P...>) {
-    (pass_n<P, INV, SYNC, NE>(v, tw, lds, t, xbuf), ...);
-  }
-  // In-place transform of NE envelopes.
-  template <bool INV, int SYNC, int NE>
-  BPM_INLINE static void fft_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
-                               SV* lds, int t, int& xbuf) {
-    fft_impl<INV, SYNC, NE>(v, tw, lds, t, xbuf,
-                            std::make_integer_sequence<int, NP>{});
-  }
-  // Both envelopes (psi~_+ in a, psi~_- in b).
-  template <bool INV, int SYNC = kSync>
-  BPM_INLINE static void fft(Reg& a, Reg& b, const Tw<CT> (&tw)[NTW], SV* lds,
-                             int t, int& xbuf) {
-    cx<CT> v[2][R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      v[0][i] = a[i];
-      v[1][i] = b[i];
-    }
-    fft_n<INV, SYNC, 2>(v, tw, lds, t, xbuf);
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      a[i] = v[0][i];
-      b[i] = v[1][i];
-    }
-  }
-
-  // Twiddles W_{Ns Rp}^{r (jb mod Ns)} of every pass after the first.
-  template <int P>
-  __device__ static void twiddles_pass(Tw<CT> (&tw)[NTW], int t) {
-    if constexpr (P > 0) {
-      constexpr int Rp = rad[P];
-      constexpr int Ns = ns(P);
-      constexpr int G = R / Rp;
-#pragma unroll
-      for (int s = 0; s < G; ++s) {
-        const int jb = t + s * T;
-        const int j = jb % Ns;
-#pragma unroll
-        for (int r = 1; r < Rp; ++r) {
-          // exp(-2 pi i r j / (Ns Rp)); sincospi keeps the argument exact
-          double sn, cs;
-          sincospi(-2.0 * double(r * j) / double(Ns * Rp), &sn, &cs);
-          tw[tw_off(P) + s * (Rp - 1) + (r - 1)] = Tw<CT>::from(cs, sn);
-        }
-      }
-    }
-  }
-  template <int... P>
-  __device__ static void twiddles_impl(Tw<CT> (&tw)[NTW], int t,
-                                       std::integer_sequence<int, P...>) {
-    (twiddles_pass<P>(tw, t), ...);
-  }
-
-  // Transform interface used by march_slice: per-thread context (twiddles),
-  // the DFT bin held in register slot i after forward(), and in-place
-  // forward / inverse transforms of both envelopes.
-  struct Ctx {
-    Tw<CT> tw[NTW];
-    int xbuf;
-  };
-  __device__ static void init(Ctx& c, int t) {
-    twiddles_impl(c.tw, t, std::make_integer_sequence<int, NP>{});
-    c.xbuf = 0;
-  }
-  BPM_INLINE static int bin(int t, int i) { return t + T * i; }
-  BPM_INLINE static void forward(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
-    fft<false>(a, b, c.tw, lds, t, c.xbuf);
-  }
-  BPM_INLINE static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
-    fft<true>(a, b, c.tw, lds, t, c.xbuf);
-  }
-};
-
-// Four-step transform of N = W M: a radix-W DFT across the W wavefronts of
-// the slice (in registers), one work-group exchange per direction, and an
-// M-point Stockham transform inside each wavefront whose exchanges need no
-// work-group barrier.  Per z-step that is 2 barriers instead of one per
-// Stockham pass, and between them the wavefronts run independently, so one
-// wavefront's LDS traffic overlaps the others' arithmetic.
-//
-// Layouts.  x-space (input and output): thread t keeps x[t + T i], i < R,
-// the same as the Stockham path.  With m_j = t + T j (j < J = R/W) and
-// n = m + M q, slot j + J q holds x[m_j + M q].  Forward: DFT over q, twiddle
-// W_N^{m k1}, exchange so that wavefront k1 holds y[m][k1] for all m (lane l,
-// slot i -> m = l + 64 i), then the M-point transform over m.  Slot i of
-// lane l in wavefront w ends with bin K = w + W (l + 64 i).
-template <int PREC, int W, class In>
-struct FourStep {
-  static constexpr bool kSplit = false;
-  using CT = typename Prec<PREC>::CT;
-  using ST = typename Prec<PREC>::ST;
-  using SV = typename vec2<ST>::type;
-  static_assert(In::T == 64, "the in-wave transform must use one wavefront");
-  static constexpr int M = In::N;
-  static constexpr int R = In::R;
-  static constexpr int N = W * M;
-  static constexpr int T = 64 * W;
-  static constexpr int J = R / W;
-  static_assert(W == 1 || (R % W == 0 && W <= 8), "unsupported wave count");
-  static constexpr int kRegion = 2 * In::kEnv;  // per wavefront: a then b
-  static constexpr size_t kG = size_t(W) * kRegion;
-  static constexpr size_t kGp = W > 1 ? size_t(W) * 2 * M : 0;
-  // Separate forward and inverse exchange buffers when they fit; otherwise
-  // one buffer and two extra barriers per step.
-  static constexpr bool kAlias = (kG + kGp) * sizeof(SV) > 160 * 1024;
-  static constexpr size_t kLdsBytes = (kAlias ? kG : kG + kGp) * sizeof(SV);
-  static constexpr int NTWX = W > 1 ? J * (W - 1) : 1;
-  using Reg = cx<CT>[R];
-
-  struct Ctx {
-    typename In::Ctx in;
-    Tw<CT> twx[NTWX];
-  };
-  __device__ static void init(Ctx& c, int t) {
-    In::init(c.in, t & 63);
-    if constexpr (W > 1) {
-#pragma unroll
-      for (int j = 0; j < J; ++j)
-#pragma unroll
-        for (int k1 = 1; k1 < W; ++k1) {
-          double sn, cs;
-          sincospi(-2.0 * double((t + T * j) * k1) / double(N), &sn, &cs);
-          c.twx[j * (W - 1) + k1 - 1] = Tw<CT>::from(cs, sn);
-        }
-    }
-  }
-  BPM_INLINE static int bin(int t, int i) {
-    return (t >> 6) + W * ((t & 63) + 64 * i);
-  }
-
-  BPM_INLINE static void forward(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
-    const int wv = t >> 6, l = t & 63;
-    SV* own = lds + wv * kRegion;
-    if constexpr (W > 1) {
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        cx<CT> va[W], vb[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-          va[q] = a[j + J * q];
-          vb[q] = b[j + J * q];
-        }
-        dft<W, false>(va);
-        dft<W, false>(vb);
-#pragma unroll
-        for (int k1 = 0; k1 < W; ++k1) {
-          if (k1 > 0) {
-            const Tw<CT> w = c.twx[j * (W - 1) + k1 - 1];
-            va[k1] = w.mul(va[k1]);
-            vb[k1] = w.mul(vb[k1]);
-          }
-          In::store(lds + k1 * kRegion, t + T * j, va[k1]);
-          In::store(lds + k1 * kRegion + In::kEnv, t + T * j, vb[k1]);
-        }
-      }
-      lds_barrier();
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        a[i] = In::load(own, l + 64 * i);
-        b[i] = In::load(own + In::kEnv, l + 64 * i);
-      }
-      wave_sync();
-    }
-    In::template fft<false, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
-  }
-
-  BPM_INLINE static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
-    const int wv = t >> 6, l = t & 63;
-    SV* own = lds + wv * kRegion;
-    In::template fft<true, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
-    if constexpr (W > 1) {
-      SV* gp = kAlias ? lds : lds + kG;
-      constexpr int kStride = kAlias ? kRegion : 2 * M;
-      constexpr int kB = kAlias ? In::kEnv : M;
-      if constexpr (kAlias) lds_barrier();  // all wavefronts done with scratch
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        In::store(gp + wv * kStride, l + 64 * i, a[i]);
-        In::store(gp + wv * kStride + kB, l + 64 * i, b[i]);
-      }
-      lds_barrier();
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        cx<CT> va[W], vb[W];
-#pragma unroll
-        for (int k1 = 0; k1 < W; ++k1) {
-          va[k1] = In::load(gp + k1 * kStride, t + T * j);
-          vb[k1] = In::load(gp + k1 * kStride + kB, t + T * j);
-          if (k1 > 0) {
-            const Tw<CT> w = c.twx[j * (W - 1) + k1 - 1];
-            va[k1] = w.mulc(va[k1]);
-            vb[k1] = w.mulc(vb[k1]);
-          }
-        }
-        dft<W, true>(va);
-        dft<W, true>(vb);
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-          a[j + J * q] = va[q];
-          b[j + J * q] = vb[q];
-        }
-      }
-      if constexpr (kAlias) lds_barrier();  // exchange read before reuse
-    }
-  }
-};
-
-// Envelope-split four-step march of one slice: 2 W wavefronts, wavefronts
-// 0..W-1 carry psi~_+ and W..2W-1 carry psi~_-, each with the radix-W
-// cross-wavefront step and an M-point in-wavefront transform of its own
-// envelope.  Twice the wavefronts of FourStep at half the registers each, so
-// two wavefronts share every SIMD and hide each other's LDS latency.  After
-// the inverse exchange every thread rebuilds BOTH envelopes at its x samples
-// (the cross-wavefront inverse DFT is done twice, a small cost) so that the
-// coupling needs no further exchange: two work-group barriers per z-step.
-// The envelope is a template parameter of the per-wavefront code (every
-// wavefront holds one envelope), so no per-sample selects remain.
-//
-// LDS: 2W regions, one per wavefront, each the forward exchange target
-// (M samples) and afterwards that wavefront's in-wave exchange buffer, then
-// the inverse exchange (2W M samples).
-template <int PREC, int W, class In>
-struct Split4 {
-  using CT = typename Prec<PREC>::CT;
-  using ST = typename Prec<PREC>::ST;
-  using SV = typename vec2<ST>::type;
-  using IV = typename In::SV;
-  static_assert(In::T == 64 && W >= 2, "split march needs W >= 2 wavefronts");
-  static constexpr bool kSplit = true;
-  static constexpr int M = In::N;
-  static constexpr int R = In::R;
-  static constexpr int N = W * M;
-  static constexpr int T0 = 64 * W;   // threads per envelope
-  static constexpr int T = 2 * T0;
-  static constexpr int J = R / W;
-  static_assert(R % W == 0, "");
-  static constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-  static constexpr size_t kRegionBytes =
-      (cmax(size_t(M) * sizeof(SV), size_t(In::kEnv) * sizeof(IV)) + 15) / 16 * 16;
-  static constexpr size_t kGBytes = size_t(2) * W * kRegionBytes;
-  static constexpr size_t kLdsBytes = kGBytes + size_t(2) * W * M * sizeof(SV);
-  static_assert(kLdsBytes <= 160 * 1024, "split march does not fit in LDS");
-
-  BPM_INLINE static void st(SV* q, int i, cx<CT> v) {
-    SV s;
-    s.x = static_cast<ST>(v.x);
-    s.y = static_cast<ST>(v.y);
-    q[i] = s;
-  }
-  BPM_INLINE static cx<CT> ld(const SV* q, int i) {
-    const SV s = q[i];
-    return {static_cast<CT>(s.x), static_cast<CT>(s.y)};
-  }
-  BPM_INLINE static SV* region(SV* lds, int r) {
-    return reinterpret_cast<SV*>(reinterpret_cast<char*>(lds) + size_t(r) * kRegionBytes);
-  }
-
-  template <bool DEFORMED>
-  BPM_INLINE static void run(const MarchParams& p, int slice, int t, SV* lds) {
-    // wave-uniform: T0 is a multiple of the wavefront size
-    if (__builtin_amdgcn_readfirstlane(t >= T0 ? 1 : 0))
-      run_env<DEFORMED, 1>(p, slice, t - T0, lds);
-    else
-      run_env<DEFORMED, 0>(p, slice, t, lds);
-  }
-
-  // Thread t0 of envelope E (0: psi~_+, 1: psi~_-).
-  template <bool DEFORMED, int E>
-  BPM_INLINE static void run_env(const MarchParams& p, int slice, int t0, SV* lds) {
-    const int wv = t0 >> 6, l = t0 & 63;
-    const SliceConst& sc = p.sc[slice];
-    const SV* table = static_cast<const SV*>(p.table);
-    SV* out = static_cast<SV*>(E ? p.Eh_out : p.E0_out) + size_t(slice) * N;
-    SV* Gp = reinterpret_cast<SV*>(reinterpret_cast<char*>(lds) + kGBytes);
-    SV* own = region(lds, E * W + wv);
-    IV* scratch = reinterpret_cast<IV*>(own);
-
-    typename In::Ctx ic;
-    In::init(ic, l);
-    Tw<CT> twx[J * (W - 1)];
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-#pragma unroll
-      for (int k1 = 1; k1 < W; ++k1) {
-        double sn, cs;
-        sincospi(-2.0 * double((t0 + T0 * j) * k1) / double(N), &sn, &cs);
-        twx[j * (W - 1) + k1 - 1] = Tw<CT>::from(cs, sn);
-      }
-    // own band's propagator at the bins of (wavefront wv, lane l, slot i);
-    // slab mask of the x samples t0 + T0 i
-    cx<double> P[R];
-    bool inside[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int k = wv + W * (l + 64 * i);
-      const int ks = k < N / 2 ? k : k - N;
-      P[i] = propagator(ks, N, p.dx, sc.k, p.h_half, E ? -1.0 : 1.0, p.dz);
-      const double x = static_cast<double>(t0 + T0 * i - N / 2) * p.dx;
-      inside[i] = (x >= p.x_front) && (x < p.x_end);
-    }
-    const cx<double> d0 = {sc.d[0][0], sc.d[0][1]};
-    // coefficient of the other envelope in this envelope's update
-    const cx<double> dx = E ? cx<double>{sc.d[0][4], sc.d[0][5]}
-                            : cx<double>{sc.d[0][2], sc.d[0][3]};
-
-    const SV* src = E == 0 ? static_cast<const SV*>(p.E0_in) + size_t(slice) * N
-                           : (p.Eh_in ? static_cast<const SV*>(p.Eh_in) + size_t(slice) * N
-                                      : nullptr);
-    cx<CT> v[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = src ? ld(src, t0 + T0 * i) : cx<CT>{CT(0), CT(0)};
-
-    for (int n = 0; n < p.Nz; ++n) {
-      // deformation row of this step, fetched early for the coupling
-      SV er[R];
-      if constexpr (DEFORMED) {
-        const SV* row = table + size_t(p.n0 + n) * N;
-#pragma unroll
-        for (int i = 0; i < R; ++i) er[i] = row[t0 + T0 * i];
-      }
-      // forward: radix-W across this envelope's wavefronts, exchange
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        cx<CT> u[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) u[q] = v[j + J * q];
-        dft<W, false>(u);
-#pragma unroll
-        for (int k1 = 0; k1 < W; ++k1) {
-          if (k1 > 0) u[k1] = twx[j * (W - 1) + k1 - 1].mul(u[k1]);
-          st(region(lds, E * W + k1), t0 + T0 * j, u[k1]);
-        }
-      }
-      lds_barrier();
-      cx<CT> z[1][R];
-#pragma unroll
-      for (int i = 0; i < R; ++i) z[0][i] = ld(own, l + 64 * i);
-      wave_sync();
-      In::template fft_n<false, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
-#pragma unroll
-      for (int i = 0; i < R; ++i) z[0][i] = conv<CT>(cmul(conv<double>(z[0][i]), P[i]));
-      In::template fft_n<true, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
-#pragma unroll
-      for (int i = 0; i < R; ++i) st(Gp + (E * W + wv) * M, l + 64 * i, z[0][i]);
-      lds_barrier();
-      // inverse radix-W for both envelopes at this thread's x samples, and
-      // the coupling (Eq. fov10) of each group of W samples right away
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        cx<CT> ua[W], ub[W];
-#pragma unroll
-        for (int k1 = 0; k1 < W; ++k1) {
-          ua[k1] = ld(Gp + k1 * M, t0 + T0 * j);
-          ub[k1] = ld(Gp + (W + k1) * M, t0 + T0 * j);
-          if (k1 > 0) {
-            ua[k1] = twx[j * (W - 1) + k1 - 1].mulc(ua[k1]);
-            ub[k1] = twx[j * (W - 1) + k1 - 1].mulc(ub[k1]);
-          }
-        }
-        dft<W, true>(ua);
-        dft<W, true>(ub);
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-          const int i = j + J * q;
-          const cx<CT> self = E ? ub[q] : ua[q];
-          const cx<CT> other = E ? ua[q] : ub[q];
-          if (inside[i]) {
-            cx<double> c = dx;
-            if constexpr (DEFORMED) {
-              const cx<double> ee = {static_cast<double>(er[i].x),
-                                     static_cast<double>(er[i].y)};
-              c = E ? cmulc(dx, ee) : cmul(dx, ee);
-            }
-            v[i] = conv<CT>(cmuladd(d0, conv<double>(self), c, conv<double>(other)));
-          } else {
-            v[i] = self;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) st(out, t0 + T0 * i, v[i]);
-  }
-};
-
-// Whole march of one slice by threads t = 0..T-1 of the calling group, for
-// either transform (Eq. fov10 per step, first-order splitting).
-// March of one slice with both envelopes in every thread.
-template <class Tr, bool DEFORMED>
-BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
-                                  typename Tr::SV* lds) {
-  using CT = typename Tr::CT;
-  using ST = typename Tr::ST;
-  using SV = typename Tr::SV;
-  constexpr int N = Tr::N, R = Tr::R, T = Tr::T;
-  const SliceConst& sc = p.sc[slice];
-  const SV* in = static_cast<const SV*>(p.E0_in) + size_t(slice) * N;
-  SV* out_a = static_cast<SV*>(p.E0_out) + size_t(slice) * N;
-  SV* out_b = static_cast<SV*>(p.Eh_out) + size_t(slice) * N;
-  const SV* table = static_cast<const SV*>(p.table);
-
-  typename Tr::Ctx ctx;
-  Tr::init(ctx, t);
-
-  // Propagators of the bins this thread holds after a forward transform,
-  // 1/Nx of the inverse transform folded in; slab mask of its x samples.
-  cx<double> Pp[R], Pm[R];
-  bool inside[R];
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int k = Tr::bin(t, i);
-    const int ks = k < N / 2 ? k : k - N;
-    Pp[i] = propagator(ks, N, p.dx, sc.k, p.h_half, +1.0, p.dz);
-    Pm[i] = propagator(ks, N, p.dx, sc.k, p.h_half, -1.0, p.dz);
-    const double x = static_cast<double>(t + T * i - N / 2) * p.dx;
-    inside[i] = (x >= p.x_front) && (x < p.x_end);
-  }
-  const cx<double> d0 = {sc.d[0][0], sc.d[0][1]};
-  const cx<double> dp1 = {sc.d[0][2], sc.d[0][3]};
-  const cx<double> dm1 = {sc.d[0][4], sc.d[0][5]};
-
-  const SV* in_b = p.Eh_in ? static_cast<const SV*>(p.Eh_in) + size_t(slice) * N
-                           : nullptr;
-  cx<CT> a[R], b[R];
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const SV v = in[t + T * i];
-    a[i] = {static_cast<CT>(v.x), static_cast<CT>(v.y)};
-    b[i] = {CT(0), CT(0)};
-    if (in_b) {
-      const SV w = in_b[t + T * i];
-      b[i] = {static_cast<CT>(w.x), static_cast<CT>(w.y)};
-    }
-  }
-
-  for (int n = 0; n < p.Nz; ++n) {
-    // Row n0 + n of exp(i h u), fetched at the start of the step and used by
-    // the coupling at its end, so its latency hides behind the transforms.
-    SV e[R];
-    if constexpr (DEFORMED) {
-      const SV* row = table + size_t(p.n0 + n) * N;
-#pragma unroll
-      for (int i = 0; i < R; ++i) e[i] = row[t + T * i];
-    }
-
-    Tr::forward(a, b, ctx, lds, t);
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      a[i] = conv<CT>(cmul(conv<double>(a[i]), Pp[i]));
-      b[i] = conv<CT>(cmul(conv<double>(b[i]), Pm[i]));
-    }
-    Tr::inverse(a, b, ctx, lds, t);
-
-    // Coupling (Eq. fov10) in FP64 where the slab is; samples outside keep
-    // the propagated field (whole-wave vacuum groups branch past).
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      if (inside[i]) {
-        const cx<double> A = conv<double>(a[i]);
-        const cx<double> B = conv<double>(b[i]);
-        cx<double> cp = dp1, cm = dm1;
-        if constexpr (DEFORMED) {
-          const cx<double> ee = {static_cast<double>(e[i].x),
-                                 static_cast<double>(e[i].y)};
-          cp = cmul(dp1, ee);    // d+1 exp(+i h u)
-          cm = cmulc(dm1, ee);   // d-1 exp(-i h u)
-        }
-        a[i] = conv<CT>(cmuladd(d0, A, cp, B));
-        b[i] = conv<CT>(cmuladd(d0, B, cm, A));
-      }
-    }
-  }
-
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    SV va, vb;
-    va.x = static_cast<ST>(a[i].x);
-    va.y = static_cast<ST>(a[i].y);
-    vb.x = static_cast<ST>(b[i].x);
-    vb.y = static_cast<ST>(b[i].y);
-    out_a[t + T * i] = va;
-    out_b[t + T * i] = vb;
-  }
-}
-
-template <class Tr, bool DEFORMED>
-BPM_INLINE void march_slice(const MarchParams& p, int slice, int t,
-                            typename Tr::SV* lds) {
-  if constexpr (Tr::kSplit) {
-    Tr::template run<DEFORMED>(p, slice, t, lds);
-  } else {
-    march_slice_joint<Tr, DEFORMED>(p, slice, t, lds);
-  }
-}
-
-template <class M, bool DEFORMED>
-__global__ void __launch_bounds__(M::T) march_kernel(MarchParams p) {
-  __shared__ __align__(16) typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
-  march_slice<M, DEFORMED>(p, blockIdx.x, threadIdx.x, lds);
-}
-
-// Persistent march over a precomputed list of (problem, slice) items: work
-// group g runs items offsets[g] .. offsets[g+1]-1 one after another.  Each
-// item runs exactly the per-slice code of march_kernel, so results do not
-// depend on how items are packed.
-template <class M>
-__global__ void __launch_bounds__(M::T)
-    march_batch_kernel(const BatchItem* __restrict__ items,
-                       const int* __restrict__ offsets) {
-  __shared__ __align__(16) typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
-  const int k0 = offsets[blockIdx.x];
-  const int k1 = offsets[blockIdx.x + 1];
-  for (int k = k0; k < k1; ++k) {
-    const MarchParams p = items[k].p;
-    const int slice = items[k].slice;
-    if (p.table)
-      march_slice<M, true>(p, slice, threadIdx.x, lds);
-    else
-      march_slice<M, false>(p, slice, threadIdx.x, lds);
-    lds_barrier();   // LDS of this item fully consumed before the next one
-  }
-}
-
-// exp(i h u): FP64 sincos for FP64 tables; for FP32 tables h*u is reduced
-// modulo 2 pi in FP64 first, then rounded to FP32 for the sincos.  One
-// thread per cell, grid-stride.
-template <class ST>
-__global__ void deform_kernel(const double* __restrict__ u, size_t n, double h,
-                              typename vec2<ST>::type* __restrict__ out) {
-  const double two_pi = kTwoPiHi;
-  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
-       i += size_t(gridDim.x) * blockDim.x) {
-    typename vec2<ST>::type v;
-    if constexpr (sizeof(ST) == 4) {
-      double r = fmod(h * u[i], two_pi);
-      if (r < 0.0) r += two_pi;
-      float s, c;
-      sincosf(static_cast<float>(r), &s, &c);
-      v.x = c;
-      v.y = s;
-    } else {
-      double s, c;
-      sincos(h * u[i], &s, &c);
-      v.x = c;
-      v.y = s;
-    }
-    out[i] = v;
-  }
-}
-
-// ------------------------------------------------------------ dispatching --
-
-// Schedules of the z-march transform for each (precision, Nx):
-//   0 -- Stockham: R samples per thread per envelope, one work-group barrier
-//        per pass (radix lists multiply to N);
-//   1 -- four-step: radix-W across W wavefronts and a 256- or 512-point
-//        Stockham inside each wavefront, two barriers per step.
-template <int PREC, int N, int SCHED>
-struct Choice;
-template <int PREC> struct Choice<PREC, 256, 0> { using type = March<PREC, 256, 4, 4, 4, 4, 4>; };
-template <int PREC> struct Choice<PREC, 512, 0> { using type = March<PREC, 512, 8, 8, 8, 8>; };
-template <int PREC> struct Choice<PREC, 1024, 0> { using type = March<PREC, 1024, 8, 8, 8, 4, 4>; };
-template <int PREC> struct Choice<PREC, 2048, 0> { using type = March<PREC, 2048, 8, 8, 8, 8, 4>; };
-template <int PREC> struct Choice<PREC, 4096, 0> { using type = March<PREC, 4096, 8, 8, 8, 8, 8>; };
-template <int PREC> using InWave512 = March<PREC, 512, 8, 8, 8, 8>;
-template <int PREC> using InWave256 = March<PREC, 256, 4, 4, 4, 4, 4>;
-template <int PREC> struct Choice<PREC, 256, 1> { using type = FourStep<PREC, 1, InWave256<PREC>>; };
-template <int PREC> struct Choice<PREC, 512, 1> { using type = FourStep<PREC, 1, InWave512<PREC>>; };
-template <int PREC> struct Choice<PREC, 1024, 1> { using type = FourStep<PREC, 2, InWave512<PREC>>; };
-template <int PREC> struct Choice<PREC, 2048, 1> { using type = FourStep<PREC, 4, InWave512<PREC>>; };
-template <int PREC> struct Choice<PREC, 4096, 1> { using type = FourStep<PREC, 8, InWave512<PREC>>; };
-// 2 -- envelope-split four-step (2W wavefronts) where it fits, else four-step
-template <int PREC> struct Choice<PREC, 256, 2> { using type = typename Choice<PREC, 256, 1>::type; };
-template <int PREC> struct Choice<PREC, 512, 2> { using type = typename Choice<PREC, 512, 1>::type; };
-template <int PREC> struct Choice<PREC, 1024, 2> { using type = Split4<PREC, 2, InWave512<PREC>>; };
-template <int PREC> struct Choice<PREC, 2048, 2> { using type = Split4<PREC, 4, InWave512<PREC>>; };
-template <int PREC> struct Choice<PREC, 4096, 2> { using type = typename Choice<PREC, 4096, 1>::type; };
-
-// Calls f(M{}) with the transform of (precision, Nx, schedule).
-template <int PREC, int N, class F>
-int with_sched(int sched, F&& f) {
-  switch (sched) {
-    case 0: return f(typename Choice<PREC, N, 0>::type{});
-    case 1: return f(typename Choice<PREC, N, 1>::type{});
-    case 2: return f(typename Choice<PREC, N, 2>::type{});
-    default: return BPM_EUNSUPPORTED;
-  }
-}
-template <int PREC, class F>
-int with_n(int Nx, int sched, F&& f) {
-  switch (Nx) {
-    case 256: return with_sched<PREC, 256>(sched, f);
-    case 512: return with_sched<PREC, 512>(sched, f);
-    case 1024: return with_sched<PREC, 1024>(sched, f);
-    case 2048: return with_sched<PREC, 2048>(sched, f);
-    case 4096: return with_sched<PREC, 4096>(sched, f);
-    default: return BPM_EUNSUPPORTED;
-  }
-}
-template <class F>
-int with_variant(int prec, int Nx, int sched, F&& f) {
-  switch (prec) {
-    case BPM_PREC_FP64: return with_n<BPM_PREC_FP64>(Nx, sched, f);
-    case BPM_PREC_FP32: return with_n<BPM_PREC_FP32>(Nx, sched, f);
-    case BPM_PREC_FP32S: return with_n<BPM_PREC_FP32S>(Nx, sched, f);
-    default: return BPM_EUNSUPPORTED;
-  }
-}
-
-}  // namespace
-
-int launch_march(int prec, int Nx, int sched, int Nomega,
+int launch_march(int prec, int Nx, int sched, int order, int Nomega,
                  const MarchParams& p, hipStream_t stream) {
-  return with_variant(prec, Nx, sched, [&](auto m) {
-    using M = decltype(m);
-    if (p.table)
-      hipLaunchKernelGGL((march_kernel<M, true>), dim3(Nomega), dim3(M::T), 0,
-                         stream, p);
-    else
-      hipLaunchKernelGGL((march_kernel<M, false>), dim3(Nomega), dim3(M::T), 0,
-                         stream, p);
-    return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
-  });
+  switch (prec) {
+    case BPM_PREC_FP64: return launch_march_p<BPM_PREC_FP64>(Nx, sched, order, Nomega, p, stream);
+    case BPM_PREC_FP32: return launch_march_p<BPM_PREC_FP32>(Nx, sched, order, Nomega, p, stream);
+    case BPM_PREC_FP32S: return launch_march_p<BPM_PREC_FP32S>(Nx, sched, order, Nomega, p, stream);
+    default: return BPM_EUNSUPPORTED;
+  }
 }
 
-int launch_march_batch(int prec, int Nx, int sched, const BatchItem* items,
+int launch_march_batch(int prec, int Nx, int sched, int order, const BatchItem* items,
                        const int* offsets, int n_groups, hipStream_t stream) {
-  return with_variant(prec, Nx, sched, [&](auto m) {
-    using M = decltype(m);
-    hipLaunchKernelGGL((march_batch_kernel<M>), dim3(n_groups), dim3(M::T), 0,
-                       stream, items, offsets);
-    return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
-  });
+  switch (prec) {
+    case BPM_PREC_FP64:
+      return launch_march_batch_p<BPM_PREC_FP64>(Nx, sched, order, items, offsets, n_groups, stream);
+    case BPM_PREC_FP32:
+      return launch_march_batch_p<BPM_PREC_FP32>(Nx, sched, order, items, offsets, n_groups, stream);
+    case BPM_PREC_FP32S:
+      return launch_march_batch_p<BPM_PREC_FP32S>(Nx, sched, order, items, offsets, n_groups, stream);
+    default: return BPM_EUNSUPPORTED;
+  }
 }
 
-int march_occupancy(int prec, int Nx, int sched, int* wg_per_cu,
-                    int* threads) {
-  return with_variant(prec, Nx, sched, [&](auto m) {
-    using M = decltype(m);
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(&march_batch_kernel<M>), M::T,
-            0) != hipSuccess)
-      return BPM_EHIP;
-    *wg_per_cu = n;
-    *threads = M::T;
-    return BPM_OK;
-  });
+int march_occupancy(int prec, int Nx, int sched, int order, int* wg_per_cu, int* threads) {
+  switch (prec) {
+    case BPM_PREC_FP64: return march_occupancy_p<BPM_PREC_FP64>(Nx, sched, order, wg_per_cu, threads);
+    case BPM_PREC_FP32: return march_occupancy_p<BPM_PREC_FP32>(Nx, sched, order, wg_per_cu, threads);
+    case BPM_PREC_FP32S: return march_occupancy_p<BPM_PREC_FP32S>(Nx, sched, order, wg_per_cu, threads);
+    default: return BPM_EUNSUPPORTED;
+  }
 }
 
-// Measured defaults (cell-updates/s on MI355X, Nz = 1000, >= 256 slices):
-// the envelope-split four-step is fastest where it exists (Nx 1024, 2048),
-// the four-step elsewhere.
 // Fastest schedule per (precision, Nx), measured on MI355X (march of >= 256
 // slices); 0 Stockham, 1 four-step, 2 envelope-split four-step.
 int default_schedule(int prec, int Nx) {

@@ -79,6 +79,8 @@ def test_setters_validate_and_freeze_rules():
     assert L.bpm_plan_set_options(p.handle, 3, 1) == -1
     assert L.bpm_plan_set_options(p.handle, 1, 2) == -1
     assert L.bpm_plan_set_options(p.handle, 1, 0) == 0
+    assert L.bpm_plan_set_options(p.handle, 2, 1) == 0
+    assert L.bpm_plan_set_options(p.handle, 4, 1) == 0
     bad = (ctypes.c_double * 4)(0.0, -2.0, 0.0, 0.0)
     assert L.bpm_plan_set_detuning(p.handle, bad) == -1
     assert L.bpm_plan_set_detuning(p.handle, None) == -1
@@ -123,6 +125,25 @@ def test_plan_constants_match_oracle(chihbar, zas):
         ko, co, _ = O.slice_constants(po, d)
         d0, dp1, dm1 = O.coupling_constants(po, d)
         assert abs(k / ko - 1) < 1e-15 and abs(c / co - 1) < 1e-15
+        assert abs(complex(d0r, d0i) - d0) < 2e-15
+        assert abs(complex(dpr, dpi) - dp1) < 2e-15 * abs(dp1) + 1e-17
+        assert abs(complex(dmr, dmi) - dm1) < 2e-15 * abs(dm1) + 1e-17
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_substep_constants_match_oracle(order):
+    """First B sub-step of the second- and fourth-order schemes (length
+    b_0 dz, Eq. split-op) against the oracle's coupling constants."""
+    import oracle as O
+    N = _lib()
+    deltas = np.array([-3e-5, 0.0, 1.5e-5, 4e-5])
+    p = plan(N, delta=deltas, split_order=order)
+    po = O.Problem(1024, 0.5e-6, 0.5e-6, 10, C["chi0"], C["chih"], C["chih"],
+                   math.pi / 4, 1.24e-10, deltas, split_order=order)
+    b0 = O.split_coefficients(order)[1][0]
+    for w, d in enumerate(deltas):
+        _, _, d0r, d0i, dpr, dpi, dmr, dmi = p.constants(w)
+        d0, dp1, dm1 = O.coupling_constants(po, d, b0)
         assert abs(complex(d0r, d0i) - d0) < 2e-15
         assert abs(complex(dpr, dpi) - dp1) < 2e-15 * abs(dp1) + 1e-17
         assert abs(complex(dmr, dmi) - dm1) < 2e-15 * abs(dm1) + 1e-17
