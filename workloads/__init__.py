@@ -16,5 +16,6 @@ from .configs import (  # noqa: F401
     c5_request_trace,
     darwin_relative_width,
     detuning_grid,
+    pulse_field,
     by_name,
 )

@@ -120,6 +120,24 @@ def incident_envelope(Nx, dx, lam, theta_B, delta, theta_i, amp,
     return (amp[:, None] * g[None, :]) * np.exp(1j * (tilt[:, None] * x[None, :]))
 
 
+def pulse_field(Nx, dx, N, dt, lam, theta_B, theta_i, sigma_t, x0=X0, w0=W0,
+                t0=0.0) -> np.ndarray:
+    """Incident pulse in the time domain, [N][Nx] on t_i = (i - N/2) dt:
+    a Gaussian of rms duration sigma_t (Eq. tdp, read with the minus sign,
+    normalised by 1/(sqrt(2 pi) sigma_t)) times the beam exp(-(x-x0)^2/W0^2),
+    travelling at glancing angle theta_i, so that its front reaches x at
+    t0 + (x - x0) sin(theta_i)/c, with the carrier exp(i h x/2),
+    h = 2 k0 sin(theta_B), removed."""
+    x = x_grid(Nx, dx)
+    t = (np.arange(N) - N // 2) * float(dt)
+    k0 = 2.0 * math.pi / lam
+    h = 2.0 * k0 * math.sin(theta_B)
+    tau = t[:, None] - t0 - (x[None, :] - x0) * math.sin(theta_i) / C_LIGHT
+    g = np.exp(-0.5 * (tau / sigma_t) ** 2) / (math.sqrt(2.0 * math.pi) * sigma_t)
+    beam = np.exp(-((x - x0) / w0) ** 2) * np.exp(1j * (k0 * math.sin(theta_i) - 0.5 * h) * x)
+    return g * beam[None, :]
+
+
 def pulse_amplitudes(delta, lam, sigma_t, rng, phase_amp=0.1) -> np.ndarray:
     """Spectral amplitudes of a Gaussian pulse of rms duration sigma_t with a
     seeded random spectral phase of amplitude phase_amp (radians)."""
