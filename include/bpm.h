@@ -97,6 +97,13 @@ int bpm_plan_set_crystal(bpm_plan* plan, double x_front, double thickness);
 /* Relative frequency offsets delta_w of the Nomega slices (host array,
  * copied). */
 int bpm_plan_set_detuning(bpm_plan* plan, const double* delta);
+/* Pulse grid (Section 3, Eq. tdp): the Nomega slices become the discrete
+ * Fourier partners of Nomega time samples t_i = (i - N/2) dt, i.e. slice j
+ * gets the detuning delta_j = Omega_j / omega_0 with Omega_j = (j - N/2)
+ * 2 pi / (N dt) and omega_0 = 2 pi c / lambda (replaces any detuning set).
+ * Needs Nomega a power of two in [256, 4096]; BPM_EINVAL otherwise or for
+ * dt <= 0.  Enables bpm_time_to_frequency / bpm_frequency_to_time. */
+int bpm_plan_set_time_grid(bpm_plan* plan, double dt);
 /* split_order: 1 -- A(dz) B(dz) per step (Eq. fov4); 2 -- B(dz/2) A(dz)
  * B(dz/2); 4 -- B(t dz/2) A(t dz) B((1-t) dz/2) A((1-2t) dz) B((1-t) dz/2)
  * A(t dz) B(t dz/2), t = 1/(2 - 2^(1/3)) (Eq. split-op).  A is the free
@@ -186,6 +193,21 @@ void bpm_batch_destroy(bpm_batch* batch);
 /* One-shot batch: create (work lists allocated stream-ordered), launch and
  * release the work lists on the stream. */
 int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream);
+
+/* Time <-> frequency transform of a pulse along the slice axis (Section 3,
+ * Eq. tdp), on the grid of bpm_plan_set_time_grid:
+ *   bpm_time_to_frequency:  psi(Omega_j, x) = dt sum_i psi(t_i, x) exp(+i Omega_j t_i)
+ *   bpm_frequency_to_time:  psi(t_i, x) = 1/(N dt) sum_j psi(Omega_j, x) exp(-i Omega_j t_i)
+ * (the inverse with dOmega / 2 pi, so the pair is the identity).  Fields are
+ * device [Nomega][Nx] interleaved complex of the plan's field type (time or
+ * frequency index first); the input may be the output (in place).  A pulse
+ * is propagated as bpm_time_to_frequency of the incident envelope,
+ * bpm_propagate, then bpm_frequency_to_time of both outputs.  Asynchronous on
+ * the stream; BPM_EINVAL for NULL pointers or a plan without a time grid. */
+int bpm_time_to_frequency(const bpm_plan* plan, const void* field_t, void* field_w,
+                          void* stream);
+int bpm_frequency_to_time(const bpm_plan* plan, const void* field_w, void* field_t,
+                          void* stream);
 
 /* Segment of the march (checkpoint / resume, z-resolved fields): starting
  * from psi~_+ = E0_in and psi~_- = Eh_in (NULL: zero) at step n0, march

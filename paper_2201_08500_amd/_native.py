@@ -55,6 +55,11 @@ _SIGNATURES = [
     ("bpm_plan_set_options", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     ("bpm_plan_set_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("bpm_plan_set_time_grid", ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    ("bpm_time_to_frequency", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("bpm_frequency_to_time", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("bpm_plan_get_schedule", ctypes.c_int, [ctypes.c_void_p]),
     ("bpm_plan_get_constants", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
@@ -136,7 +141,8 @@ class Plan:
 
     def __init__(self, Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam,
                  Nomega, precision="fp64", x_front=None, thickness=None,
-                 delta=None, split_order=1, zassenhaus=True, schedule=None):
+                 delta=None, split_order=1, zassenhaus=True, schedule=None,
+                 time_step=None):
         L = lib()
         self._h = None
         h = L.bpm_plan_create(int(Nx), float(dx), float(dz), int(Nz),
@@ -158,6 +164,12 @@ class Plan:
                 raise ValueError(f"delta has {len(delta)} values for {self.Nomega} slices")
             arr = (ctypes.c_double * self.Nomega)(*delta)
             _check(L.bpm_plan_set_detuning(self._h, arr))
+        self.time_step = None
+        if time_step is not None:
+            if delta is not None:
+                raise ValueError("time_step sets the detuning grid; do not pass delta too")
+            _check(L.bpm_plan_set_time_grid(self._h, float(time_step)))
+            self.time_step = float(time_step)
         if split_order != 1 or not zassenhaus:
             _check(L.bpm_plan_set_options(self._h, int(split_order),
                                           int(bool(zassenhaus))))
@@ -267,6 +279,36 @@ class Plan:
                                        _ptr(E0_out), _ptr(Eh_out),
                                        _stream_handle(stream)))
         return E0_out, Eh_out
+
+    def to_frequency(self, field_t, out=None, stream=None):
+        """bpm_time_to_frequency of a [Nomega][Nx] pulse field (time first)."""
+        import torch
+        self._check_field(field_t, "field_t")
+        out = torch.empty_like(field_t) if out is None else out
+        self._check_field(out, "out")
+        _check(lib().bpm_time_to_frequency(self._h, _ptr(field_t), _ptr(out),
+                                           _stream_handle(stream)))
+        return out
+
+    def to_time(self, field_w, out=None, stream=None):
+        """bpm_frequency_to_time of a [Nomega][Nx] field (frequency first)."""
+        import torch
+        self._check_field(field_w, "field_w")
+        out = torch.empty_like(field_w) if out is None else out
+        self._check_field(out, "out")
+        _check(lib().bpm_frequency_to_time(self._h, _ptr(field_w), _ptr(out),
+                                           _stream_handle(stream)))
+        return out
+
+    def propagate_pulse(self, field_t, u=None, stream=None):
+        """Incident pulse in time -> (transmitted, reflected) pulses in time:
+        bpm_time_to_frequency, bpm_propagate, bpm_frequency_to_time (both
+        outputs transformed in place)."""
+        E0 = self.to_frequency(field_t, stream=stream)
+        a, b = self.propagate(E0, u, stream=stream)
+        self.to_time(a, out=a, stream=stream)
+        self.to_time(b, out=b, stream=stream)
+        return a, b
 
     def close(self):
         if self._h is not None and _lib is not None:

@@ -1134,6 +1134,57 @@ __global__ void __launch_bounds__(M::T)
   }
 }
 
+// Time <-> frequency transform of a pulse along the slice axis (Section 3,
+// Eq. tdp) on centred grids t_i = (i - N/2) dt, Omega_j = (j - N/2) dOmega,
+// dOmega = 2 pi / (N dt).  With Omega_j t_i = 2 pi (j - N/2)(i - N/2) / N the
+// pair factors into (-1)^i, an N-point DFT and (-1)^j (N a multiple of 4):
+//   TO_FREQ:  out_j = dt (-1)^j sum_i (-1)^i in_i exp(+2 pi i ij/N)
+//   !TO_FREQ: out_i = (-1)^i / (N dt) sum_j (-1)^j in_j exp(-2 pi i ij/N)
+// Fields are [N][Nx]; work group b transforms columns 2b and 2b+1 with the
+// Stockham transform of M (both columns under one set of barriers).  A
+// column is read completely before it is written, so in place is allowed.
+template <class M, bool TO_FREQ>
+__global__ void __launch_bounds__(M::T)
+    pulse_kernel(const typename M::SV* __restrict__ in, typename M::SV* out,
+                 int Nx, double scale) {
+  using CT = typename M::CT;
+  using ST = typename M::ST;
+  using SV = typename M::SV;
+  constexpr int N = M::N, R = M::R, T = M::T;
+  __shared__ __align__(16) SV lds[M::kLdsBytes / sizeof(SV)];
+  const int t = threadIdx.x;
+  const size_t x0 = size_t(2) * blockIdx.x;
+  typename M::Ctx ctx;
+  M::init(ctx, t);
+  cx<CT> a[R], b[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = t + T * r;
+    const SV va = in[size_t(i) * Nx + x0];
+    const SV vb = in[size_t(i) * Nx + x0 + 1];
+    const CT sg = (i & 1) ? CT(-1) : CT(1);
+    a[r] = {sg * static_cast<CT>(va.x), sg * static_cast<CT>(va.y)};
+    b[r] = {sg * static_cast<CT>(vb.x), sg * static_cast<CT>(vb.y)};
+  }
+  // exp(+i) kernel: the transform's inverse direction (no 1/N inside)
+  if constexpr (TO_FREQ)
+    M::inverse(a, b, ctx, lds, t);
+  else
+    M::forward(a, b, ctx, lds, t);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = M::bin(t, r);
+    const double sg = (j & 1) ? -scale : scale;
+    SV va, vb;
+    va.x = static_cast<ST>(sg * static_cast<double>(a[r].x));
+    va.y = static_cast<ST>(sg * static_cast<double>(a[r].y));
+    vb.x = static_cast<ST>(sg * static_cast<double>(b[r].x));
+    vb.y = static_cast<ST>(sg * static_cast<double>(b[r].y));
+    out[size_t(j) * Nx + x0] = va;
+    out[size_t(j) * Nx + x0 + 1] = vb;
+  }
+}
+
 // exp(i h u): FP64 sincos for FP64 tables; for FP32 tables h*u is reduced
 // modulo 2 pi in FP64 first, then rounded to FP32 for the sincos.  One
 // thread per cell, grid-stride.
@@ -1252,6 +1303,34 @@ int launch_march_batch_p(int Nx, int sched, int order, const BatchItem* items,
       return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
     });
   });
+}
+
+// Pulse transform of [N][Nx] fields: FP64 butterflies for every
+// precision (complex64 storage for the FP32 modes).
+template <int PREC>
+int launch_pulse_p(int N, int Nx, bool to_freq, double dt, const void* in, void* out,
+                   hipStream_t stream) {
+  constexpr int SP = PREC == BPM_PREC_FP64 ? BPM_PREC_FP64 : BPM_PREC_FP32S;
+  auto run = [&](auto m) {
+    using M = decltype(m);
+    using SV = typename M::SV;
+    const double scale = to_freq ? dt : 1.0 / (double(N) * dt);
+    if (to_freq)
+      hipLaunchKernelGGL((pulse_kernel<M, true>), dim3(Nx / 2), dim3(M::T), 0, stream,
+                         static_cast<const SV*>(in), static_cast<SV*>(out), Nx, scale);
+    else
+      hipLaunchKernelGGL((pulse_kernel<M, false>), dim3(Nx / 2), dim3(M::T), 0, stream,
+                         static_cast<const SV*>(in), static_cast<SV*>(out), Nx, scale);
+    return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
+  };
+  switch (N) {   // Stockham transform of length N
+    case 256: return run(typename Choice<SP, 256, 0>::type{});
+    case 512: return run(typename Choice<SP, 512, 0>::type{});
+    case 1024: return run(typename Choice<SP, 1024, 0>::type{});
+    case 2048: return run(typename Choice<SP, 2048, 0>::type{});
+    case 4096: return run(typename Choice<SP, 4096, 0>::type{});
+    default: return BPM_EUNSUPPORTED;
+  }
 }
 
 template <int PREC>

@@ -436,6 +436,29 @@ int bpm_plan_set_detuning(bpm_plan* p, const double* delta) {
   return BPM_OK;
 }
 
+int bpm_plan_set_time_grid(bpm_plan* p, double dt) {
+  int rc = check_mutable(p);
+  if (rc) return rc;
+  if (!std::isfinite(dt) || !(dt > 0.0)) return fail(BPM_EINVAL, "dt must be finite and > 0");
+  const int N = p->Nomega;
+  if (!is_pow2(N) || N < 256 || N > 4096)
+    return fail(BPM_EINVAL, "a pulse grid needs Nomega a power of two in [256, 4096]");
+  // delta_j = Omega_j / omega_0, Omega_j = (j - N/2) 2 pi / (N dt),
+  // omega_0 = 2 pi c / lambda (Section 3, Eq. tdp)
+  const double c_light = 299792458.0;
+  const double two_pi = 2.0 * 3.14159265358979323846;
+  const double dOmega = two_pi / (N * dt);
+  const double omega0 = two_pi * c_light / p->lambda;
+  std::vector<double> d(N);
+  for (int j = 0; j < N; ++j) {
+    d[j] = double(j - N / 2) * dOmega / omega0;
+    if (!(d[j] > -1.0)) return fail(BPM_EINVAL, "dt too small: a slice has k <= 0");
+  }
+  p->delta = d;
+  p->dt = dt;
+  return BPM_OK;
+}
+
 int bpm_plan_set_options(bpm_plan* p, int split_order, int zassenhaus) {
   int rc = check_mutable(p);
   if (rc) return rc;
@@ -488,6 +511,28 @@ size_t bpm_workspace_bytes(const bpm_plan* p) {
   if (!p) return 0;
   const size_t cell = p->precision == BPM_PREC_FP64 ? 16 : 8;
   return size_t(p->Nx) * size_t(p->Nz) * cell;
+}
+
+static int pulse_transform(const bpm_plan* p, const void* in, void* out, void* stream,
+                           bool to_freq) {
+  g_error.clear();
+  if (!p) return fail(BPM_EINVAL, "plan is NULL");
+  if (!in || !out) return fail(BPM_EINVAL, "input and output must be non-NULL");
+  if (!(p->dt > 0.0)) return fail(BPM_EINVAL, "the plan has no time grid (bpm_plan_set_time_grid)");
+  int rc = bpm::launch_pulse(p->precision, p->Nomega, p->Nx, to_freq, p->dt, in, out,
+                             static_cast<hipStream_t>(stream));
+  if (rc) return fail(rc, "pulse transform launch failed");
+  return BPM_OK;
+}
+
+int bpm_time_to_frequency(const bpm_plan* plan, const void* field_t, void* field_w,
+                          void* stream) {
+  return pulse_transform(plan, field_t, field_w, stream, true);
+}
+
+int bpm_frequency_to_time(const bpm_plan* plan, const void* field_w, void* field_t,
+                          void* stream) {
+  return pulse_transform(plan, field_w, field_t, stream, false);
 }
 
 int bpm_deformation_table(const bpm_plan* cp, const double* u_field,

@@ -69,6 +69,12 @@ int launch_march_batch_p(int Nx, int sched, int order, const BatchItem* items,
                          const int* offsets, int n_groups, hipStream_t stream);
 template <int PREC>
 int march_occupancy_p(int Nx, int sched, int order, int* wg_per_cu, int* threads);
+template <int PREC>
+int launch_pulse_p(int N, int Nx, bool to_freq, double dt, const void* in, void* out,
+                   hipStream_t stream);
+// Time <-> frequency transform of [N][Nx] pulse fields along the slice axis.
+int launch_pulse(int prec, int N, int Nx, bool to_freq, double dt, const void* in,
+                 void* out, hipStream_t stream);
 // Library default schedule of (precision, Nx).
 int default_schedule(int prec, int Nx);
 
@@ -83,6 +89,7 @@ struct bpm_plan {
   double x_front = 0.0, thickness = HUGE_VAL;
   int split_order = 1, zassenhaus = 1;
   int schedule = -1;  // BPM_SCHED_AUTO
+  double dt = 0.0;     // time step of the pulse grid (0: none set)
   std::vector<double> delta;
   // derived (FP64)
   double k0 = 0, h = 0;

@@ -11,7 +11,9 @@ namespace bpm {
                                         hipStream_t);                              \
   extern template int launch_march_batch_p<P>(int, int, int, const BatchItem*,     \
                                               const int*, int, hipStream_t);       \
-  extern template int march_occupancy_p<P>(int, int, int, int*, int*);
+  extern template int march_occupancy_p<P>(int, int, int, int*, int*);              \
+  extern template int launch_pulse_p<P>(int, int, bool, double, const void*, void*,  \
+                                        hipStream_t);
 BPM_EXTERN_PREC(BPM_PREC_FP64)
 BPM_EXTERN_PREC(BPM_PREC_FP32)
 BPM_EXTERN_PREC(BPM_PREC_FP32S)
@@ -45,6 +47,16 @@ int march_occupancy(int prec, int Nx, int sched, int order, int* wg_per_cu, int*
     case BPM_PREC_FP64: return march_occupancy_p<BPM_PREC_FP64>(Nx, sched, order, wg_per_cu, threads);
     case BPM_PREC_FP32: return march_occupancy_p<BPM_PREC_FP32>(Nx, sched, order, wg_per_cu, threads);
     case BPM_PREC_FP32S: return march_occupancy_p<BPM_PREC_FP32S>(Nx, sched, order, wg_per_cu, threads);
+    default: return BPM_EUNSUPPORTED;
+  }
+}
+
+int launch_pulse(int prec, int N, int Nx, bool to_freq, double dt, const void* in,
+                 void* out, hipStream_t stream) {
+  switch (prec) {
+    case BPM_PREC_FP64: return launch_pulse_p<BPM_PREC_FP64>(N, Nx, to_freq, dt, in, out, stream);
+    case BPM_PREC_FP32: return launch_pulse_p<BPM_PREC_FP32>(N, Nx, to_freq, dt, in, out, stream);
+    case BPM_PREC_FP32S: return launch_pulse_p<BPM_PREC_FP32S>(N, Nx, to_freq, dt, in, out, stream);
     default: return BPM_EUNSUPPORTED;
   }
 }

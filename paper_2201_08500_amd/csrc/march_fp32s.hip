@@ -10,5 +10,6 @@ template int launch_march_p<BPM_PREC_FP32S>(int, int, int, int, const MarchParam
 template int launch_march_batch_p<BPM_PREC_FP32S>(int, int, int, const BatchItem*, const int*, int,
                                           hipStream_t);
 template int march_occupancy_p<BPM_PREC_FP32S>(int, int, int, int*, int*);
+template int launch_pulse_p<BPM_PREC_FP32S>(int, int, bool, double, const void*, void*, hipStream_t);
 
 }  // namespace bpm

@@ -13,6 +13,7 @@ import pytest
 import oracle as O
 from oracle import pulse as P
 import workloads.configs as W
+from pulse_analysis import wake_slope
 
 C = P.C_LIGHT
 
@@ -98,33 +99,10 @@ def test_vacuum_pulse_arrives_after_group_delay_at_walked_off_position():
 
 
 def _wake_slope(theta_deg, Nz):
-    """Beam-frame displacement rate of the reflected wake: delay
-    tau = t - t0 + (x - xc) sin(theta)/c and cross-section coordinate
-    x_perp = (x - xc) cos(theta) of the reflected beam (unit vector
-    (cos theta, sin theta), towards the crystal side), fitted over the first
-    ~120 fs after the reflection peak."""
     theta = math.radians(theta_deg)
     Nx, N, dt, sig = 1024, 512, 1e-15, 2e-15
     _, b = _march_pulse(Nx, Nz, N, dt, sig, 20e-6, -40e-6, theta)
-    x = W.x_grid(Nx, 0.5e-6)
-    t = P.time_grid(N, dt)
-    T = N * dt
-    I = np.abs(b) ** 2
-    it0, ix0 = np.unravel_index(I.argmax(), I.shape)
-    sel = np.abs(x - x[ix0]) < 140e-6
-    xs, Is = x[sel], I[:, sel]
-    tau = (t[:, None] - t[it0]) + (xs[None, :] - x[ix0]) * math.sin(theta) / C
-    tau = np.mod(tau + T / 4, T) - T / 4
-    xp = np.broadcast_to(((xs - x[ix0]) * math.cos(theta))[None, :], Is.shape)
-    edges = np.arange(12e-15, 124e-15, 4e-15)
-    k = np.digitize(tau.ravel(), edges)
-    taus, cents = [], []
-    for j in range(1, len(edges)):
-        m = k == j
-        p = Is.ravel()[m].sum()
-        taus.append(edges[j - 1])
-        cents.append((Is.ravel()[m] * xp.ravel()[m]).sum() / p)
-    return np.polyfit(taus, cents, 1)[0]
+    return wake_slope(b, W.x_grid(Nx, 0.5e-6), P.time_grid(N, dt), theta)
 
 
 @pytest.mark.slow
