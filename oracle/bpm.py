@@ -65,7 +65,7 @@ class Problem:
 
     def __init__(self, Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam,
                  delta, x_front=0.0, thickness=math.inf, zassenhaus=True,
-                 split_order=1):
+                 split_order=1, mask=None):
         self.Nx = int(Nx)
         self.dx = float(dx)
         self.dz = float(dz)
@@ -80,6 +80,9 @@ class Problem:
         self.thickness = float(thickness)
         self.zassenhaus = bool(zassenhaus)
         self.split_order = int(split_order)
+        # optional general crystal mask Pi[n][j] (bool, Nz x Nx) replacing
+        # the slab: any crystal shape in the (x, z) plane
+        self.mask = None if mask is None else np.asarray(mask, dtype=bool).reshape(Nz, Nx)
 
     @classmethod
     def from_workload(cls, w, **over):
@@ -160,9 +163,12 @@ def propagator(p: Problem, delta: float, band: int, frac: float = 1.0):
     return np.exp(1j * phi - decay.astype(np.float64))
 
 
-def crystal_mask(p: Problem) -> np.ndarray:
-    """Pi_j = 1 inside the slab x_front <= x_j < x_front + thickness,
-    x_j = (j - Nx/2) dx."""
+def crystal_mask(p: Problem, n: int = 0) -> np.ndarray:
+    """Pi_j of step n: the general mask row p.mask[n] when one is given,
+    otherwise the slab x_front <= x_j < x_front + thickness, x_j = (j - Nx/2) dx
+    (the same for every step)."""
+    if p.mask is not None:
+        return p.mask[n]
     x = (np.arange(p.Nx) - p.Nx // 2) * p.dx
     return (x >= p.x_front) & (x < p.x_front + p.thickness)
 
@@ -216,11 +222,11 @@ def march(p: Problem, E0_in, u=None, n_steps=None, Eh_in=None,
     for bi in Bc:
         cc = np.array([coupling_constants(p, d, bi) for d in p.delta])
         coup.append((cc[:, 0:1], cc[:, 1:2], cc[:, 2:3]))
-    mask = crystal_mask(p)[None, :]
 
     hist = []
     for n in range(n_steps):
         e = None if u is None else deformation_factor(p, u[n])[None, :]
+        mask = crystal_mask(p, n)[None, :]
         for i in range(len(A)):
             if props[i] is not None:
                 Pp, Pm = props[i]
