@@ -97,6 +97,13 @@ int bpm_plan_set_crystal(bpm_plan* plan, double x_front, double thickness);
 /* Relative frequency offsets delta_w of the Nomega slices (host array,
  * copied). */
 int bpm_plan_set_detuning(bpm_plan* plan, const double* delta);
+/* General crystal mask Pi(x, z) replacing the slab (asymmetric Bragg, Laue,
+ * wedges, any shape in the (x, z) plane): host array [Nz][Nx] of bytes,
+ * nonzero = crystal, row n used by every sub-step of step n; copied into
+ * the plan (uploaded to the device once, on first use); NULL returns to the
+ * slab of bpm_plan_set_crystal.  Outside the crystal the coupling is the
+ * identity (Section 2.1, the susceptibility vanishes in vacuum). */
+int bpm_plan_set_mask(bpm_plan* plan, const unsigned char* mask);
 /* Pulse grid (Section 3, Eq. tdp): the Nomega slices become the discrete
  * Fourier partners of Nomega time samples t_i = (i - N/2) dt, i.e. slice j
  * gets the detuning delta_j = Omega_j / omega_0 with Omega_j = (j - N/2)

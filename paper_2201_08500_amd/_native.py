@@ -56,6 +56,7 @@ _SIGNATURES = [
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     ("bpm_plan_set_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bpm_plan_set_time_grid", ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    ("bpm_plan_set_mask", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("bpm_time_to_frequency", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("bpm_frequency_to_time", ctypes.c_int,
@@ -142,7 +143,7 @@ class Plan:
     def __init__(self, Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam,
                  Nomega, precision="fp64", x_front=None, thickness=None,
                  delta=None, split_order=1, zassenhaus=True, schedule=None,
-                 time_step=None):
+                 time_step=None, mask=None):
         L = lib()
         self._h = None
         h = L.bpm_plan_create(int(Nx), float(dx), float(dz), int(Nz),
@@ -170,6 +171,12 @@ class Plan:
                 raise ValueError("time_step sets the detuning grid; do not pass delta too")
             _check(L.bpm_plan_set_time_grid(self._h, float(time_step)))
             self.time_step = float(time_step)
+        if mask is not None:
+            import numpy as np
+            m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+            if m.shape != (self.Nz, self.Nx):
+                raise ValueError(f"mask must have shape ({self.Nz}, {self.Nx})")
+            _check(L.bpm_plan_set_mask(self._h, m.ctypes.data_as(ctypes.c_void_p)))
         if split_order != 1 or not zassenhaus:
             _check(L.bpm_plan_set_options(self._h, int(split_order),
                                           int(bool(zassenhaus))))

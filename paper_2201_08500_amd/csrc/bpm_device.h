@@ -365,6 +365,21 @@ struct vec2<double> {
 //   order 4: B(t dz/2) A(t dz) B((1-t) dz/2) A((1-2t) dz) B((1-t) dz/2)
 //            A(t dz) B(t dz/2),  t = 1/(2 - 2^(1/3))
 // The a_s are MarchParams::a_frac and the B constants SliceConst::d[s].
+// Crystal flags of step `row` at this thread's x samples first + stride i:
+// the general mask row when the plan has one, else the slab flags.
+template <int R, int N, bool MASKED>
+BPM_INLINE void crystal_row(const MarchParams& p, int row, int first, int stride,
+                            const bool (&slab)[R], bool (&out)[R]) {
+  if constexpr (MASKED) {
+    const unsigned char* m = p.mask + size_t(row) * N + first;
+#pragma unroll
+    for (int i = 0; i < R; ++i) out[i] = m[stride * i] != 0;
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) out[i] = slab[i];
+  }
+}
+
 template <int ORDER>
 struct Scheme {
   static_assert(ORDER == 1 || ORDER == 2 || ORDER == 4, "split order 1, 2 or 4");
@@ -782,13 +797,13 @@ struct Split4 {
     return reinterpret_cast<SV*>(reinterpret_cast<char*>(lds) + size_t(r) * kRegionBytes);
   }
 
-  template <bool DEFORMED, int ORDER>
+  template <bool DEFORMED, int ORDER, bool MASKED>
   BPM_INLINE static void run(const MarchParams& p, int slice, int t, SV* lds) {
     // wave-uniform: T0 is a multiple of the wavefront size
     if (__builtin_amdgcn_readfirstlane(t >= T0 ? 1 : 0))
-      run_env<DEFORMED, 1, ORDER>(p, slice, t - T0, lds);
+      run_env<DEFORMED, 1, ORDER, MASKED>(p, slice, t - T0, lds);
     else
-      run_env<DEFORMED, 0, ORDER>(p, slice, t, lds);
+      run_env<DEFORMED, 0, ORDER, MASKED>(p, slice, t, lds);
   }
 
   // Coupling of one B sub-step (Eq. fov10) for envelope F at one sample:
@@ -812,7 +827,7 @@ struct Split4 {
   // (no A before it) runs right after the last B sub-step of the previous
   // step (both envelopes updated by the first, this envelope by the
   // second), and before the first step on the input fields.
-  template <bool DEFORMED, int E, int ORDER>
+  template <bool DEFORMED, int E, int ORDER, bool MASKED>
   BPM_INLINE static void run_env(const MarchParams& p, int slice, int t0, SV* lds) {
     using S = Scheme<ORDER>;
     const int wv = t0 >> 6, l = t0 & 63;
@@ -866,20 +881,22 @@ struct Split4 {
     for (int i = 0; i < R; ++i) v[i] = src ? ld(src, t0 + T0 * i) : cx<CT>{CT(0), CT(0)};
 
     // deformation rows: er of the current step (ORDER > 1: prefetched one
-    // step ahead into er_next)
+    // step ahead into er_next); crystal flags of the current and next step
     SV er[R], er_next[R];
+    bool in_cur[R], in_next[R];
     if constexpr (ORDER > 1 && DEFORMED) {
       const SV* row = table + size_t(p.n0) * N;
 #pragma unroll
       for (int i = 0; i < R; ++i) er[i] = er_next[i] = row[t0 + T0 * i];
     }
     if constexpr (ORDER > 1) {
+      crystal_row<R, N, MASKED>(p, p.n0, t0, T0, inside, in_cur);
       // first B sub-step of the first step, on the input fields
       const SV* osrc = E == 0 ? in_b : in_a;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const cx<CT> other = osrc ? ld(osrc, t0 + T0 * i) : cx<CT>{CT(0), CT(0)};
-        if (inside[i]) v[i] = couple<DEFORMED, E>(d[0], er[i], v[i], other);
+        if (in_cur[i]) v[i] = couple<DEFORMED, E>(d[0], er[i], v[i], other);
       }
     }
 
@@ -891,13 +908,15 @@ struct Split4 {
 #pragma unroll
           for (int i = 0; i < R; ++i) er[i] = row[t0 + T0 * i];
         }
+        crystal_row<R, N, MASKED>(p, p.n0 + n, t0, T0, inside, in_cur);
       } else {
-        if constexpr (DEFORMED) {
-          if (n + 1 < p.Nz) {
+        if (n + 1 < p.Nz) {
+          if constexpr (DEFORMED) {
             const SV* row = table + size_t(p.n0 + n + 1) * N;
 #pragma unroll
             for (int i = 0; i < R; ++i) er_next[i] = row[t0 + T0 * i];
           }
+          crystal_row<R, N, MASKED>(p, p.n0 + n + 1, t0, T0, inside, in_next);
         }
       }
 #pragma unroll
@@ -951,30 +970,28 @@ struct Split4 {
               const int i = j + J * q;
               const cx<CT> self = E ? ub[q] : ua[q];
               const cx<CT> other = E ? ua[q] : ub[q];
-              if (inside[i]) {
-                if constexpr (ORDER == 1) {
-                  v[i] = couple<DEFORMED, E>(d[s], er[i], self, other);
-                } else {
-                  if (chain) {
-                    // last B of step n (both envelopes, as each envelope's
-                    // own thread computes it), then the first B of step n+1
-                    const cx<CT> s1 = couple<DEFORMED, E>(d[s], er[i], self, other);
-                    const cx<CT> o1 = couple<DEFORMED, 1 - E>(d[s], er[i], other, self);
-                    v[i] = couple<DEFORMED, E>(d[0], er_next[i], s1, o1);
-                  } else {
-                    v[i] = couple<DEFORMED, E>(d[s], er[i], self, other);
-                  }
+              if (ORDER > 1 && chain) {
+                // last B of step n (both envelopes, as each envelope's own
+                // thread computes it), then the first B of step n+1
+                cx<CT> s1 = self, o1 = other;
+                if (in_cur[i]) {
+                  s1 = couple<DEFORMED, E>(d[s], er[i], self, other);
+                  o1 = couple<DEFORMED, 1 - E>(d[s], er[i], other, self);
                 }
+                v[i] = in_next[i] ? couple<DEFORMED, E>(d[0], er_next[i], s1, o1) : s1;
               } else {
-                v[i] = self;
+                v[i] = in_cur[i] ? couple<DEFORMED, E>(d[s], er[i], self, other) : self;
               }
             }
           }
         }
       }
-      if constexpr (ORDER > 1 && DEFORMED) {
+      if constexpr (ORDER > 1) {
 #pragma unroll
-        for (int i = 0; i < R; ++i) er[i] = er_next[i];
+        for (int i = 0; i < R; ++i) {
+          if constexpr (DEFORMED) er[i] = er_next[i];
+          in_cur[i] = in_next[i];
+        }
       }
     }
 #pragma unroll
@@ -985,7 +1002,7 @@ struct Split4 {
 // Whole march of one slice by threads t = 0..T-1 of the calling group, with
 // both envelopes in every thread (Stockham and four-step transforms).  Each
 // step runs the sub-steps of Scheme<ORDER> (Eq. fov10 per sub-step).
-template <class Tr, bool DEFORMED, int ORDER>
+template <class Tr, bool DEFORMED, int ORDER, bool MASKED>
 BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
                                   typename Tr::SV* lds) {
   using CT = typename Tr::CT;
@@ -1052,6 +1069,8 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
 #pragma unroll
       for (int i = 0; i < R; ++i) e[i] = row[t + T * i];
     }
+    bool in_cur[R];
+    crystal_row<R, N, MASKED>(p, p.n0 + n, t, T, inside, in_cur);
 #pragma unroll
     for (int s = 0; s < S::NS; ++s) {
       if (S::has_a(s)) {
@@ -1067,7 +1086,7 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
       // (whole-wave vacuum groups branch past).
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        if (inside[i]) {
+        if (in_cur[i]) {
           const cx<double> A = conv<double>(a[i]);
           const cx<double> B = conv<double>(b[i]);
           cx<double> cp = dp1[s], cm = dm1[s];
@@ -1096,27 +1115,30 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
   }
 }
 
-template <class Tr, bool DEFORMED, int ORDER>
+template <class Tr, bool DEFORMED, int ORDER, bool MASKED>
 BPM_INLINE void march_slice(const MarchParams& p, int slice, int t,
                             typename Tr::SV* lds) {
   if constexpr (Tr::kSplit) {
-    Tr::template run<DEFORMED, ORDER>(p, slice, t, lds);
+    Tr::template run<DEFORMED, ORDER, MASKED>(p, slice, t, lds);
   } else {
-    march_slice_joint<Tr, DEFORMED, ORDER>(p, slice, t, lds);
+    march_slice_joint<Tr, DEFORMED, ORDER, MASKED>(p, slice, t, lds);
   }
 }
 
-template <class M, bool DEFORMED, int ORDER>
+// MASKED: the crystal is the general mask p.mask (a row per step) instead
+// of the slab; a separate instantiation, so the slab kernels carry no
+// per-step mask work.
+template <class M, bool DEFORMED, int ORDER, bool MASKED>
 __global__ void __launch_bounds__(M::T) march_kernel(MarchParams p) {
   __shared__ __align__(16) typename M::SV lds[M::kLdsBytes / sizeof(typename M::SV)];
-  march_slice<M, DEFORMED, ORDER>(p, blockIdx.x, threadIdx.x, lds);
+  march_slice<M, DEFORMED, ORDER, MASKED>(p, blockIdx.x, threadIdx.x, lds);
 }
 
 // Persistent march over a precomputed list of (problem, slice) items: work
 // group g runs items offsets[g] .. offsets[g+1]-1 one after another.  Each
 // item runs exactly the per-slice code of march_kernel, so results do not
 // depend on how items are packed.
-template <class M, int ORDER>
+template <class M, int ORDER, bool MASKED>
 __global__ void __launch_bounds__(M::T)
     march_batch_kernel(const BatchItem* __restrict__ items,
                        const int* __restrict__ offsets) {
@@ -1127,9 +1149,9 @@ __global__ void __launch_bounds__(M::T)
     const MarchParams p = items[k].p;
     const int slice = items[k].slice;
     if (p.table)
-      march_slice<M, true, ORDER>(p, slice, threadIdx.x, lds);
+      march_slice<M, true, ORDER, MASKED>(p, slice, threadIdx.x, lds);
     else
-      march_slice<M, false, ORDER>(p, slice, threadIdx.x, lds);
+      march_slice<M, false, ORDER, MASKED>(p, slice, threadIdx.x, lds);
     lds_barrier();   // LDS of this item fully consumed before the next one
   }
 }
@@ -1273,7 +1295,7 @@ int with_order(int order, F&& f) {
 
 }  // namespace
 
-template <int PREC>
+template <int PREC, bool MASKED>
 int launch_march_p(int Nx, int sched, int order, int Nomega, const MarchParams& p,
                    hipStream_t stream) {
   return with_n<PREC>(Nx, sched, [&](auto m) {
@@ -1281,25 +1303,25 @@ int launch_march_p(int Nx, int sched, int order, int Nomega, const MarchParams& 
     return with_order(order, [&](auto o) {
       constexpr int ORDER = decltype(o)::value;
       if (p.table)
-        hipLaunchKernelGGL((march_kernel<M, true, ORDER>), dim3(Nomega), dim3(M::T),
-                           0, stream, p);
+        hipLaunchKernelGGL((march_kernel<M, true, ORDER, MASKED>), dim3(Nomega),
+                           dim3(M::T), 0, stream, p);
       else
-        hipLaunchKernelGGL((march_kernel<M, false, ORDER>), dim3(Nomega), dim3(M::T),
-                           0, stream, p);
+        hipLaunchKernelGGL((march_kernel<M, false, ORDER, MASKED>), dim3(Nomega),
+                           dim3(M::T), 0, stream, p);
       return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
     });
   });
 }
 
-template <int PREC>
+template <int PREC, bool MASKED>
 int launch_march_batch_p(int Nx, int sched, int order, const BatchItem* items,
                          const int* offsets, int n_groups, hipStream_t stream) {
   return with_n<PREC>(Nx, sched, [&](auto m) {
     using M = decltype(m);
     return with_order(order, [&](auto o) {
       constexpr int ORDER = decltype(o)::value;
-      hipLaunchKernelGGL((march_batch_kernel<M, ORDER>), dim3(n_groups), dim3(M::T),
-                         0, stream, items, offsets);
+      hipLaunchKernelGGL((march_batch_kernel<M, ORDER, MASKED>), dim3(n_groups),
+                         dim3(M::T), 0, stream, items, offsets);
       return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
     });
   });
@@ -1333,7 +1355,7 @@ int launch_pulse_p(int N, int Nx, bool to_freq, double dt, const void* in, void*
   }
 }
 
-template <int PREC>
+template <int PREC, bool MASKED>
 int march_occupancy_p(int Nx, int sched, int order, int* wg_per_cu, int* threads) {
   return with_n<PREC>(Nx, sched, [&](auto m) {
     using M = decltype(m);
@@ -1341,7 +1363,7 @@ int march_occupancy_p(int Nx, int sched, int order, int* wg_per_cu, int* threads
       constexpr int ORDER = decltype(o)::value;
       int n = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &n, reinterpret_cast<const void*>(&march_batch_kernel<M, ORDER>), M::T,
+              &n, reinterpret_cast<const void*>(&march_batch_kernel<M, ORDER, MASKED>), M::T,
               0) != hipSuccess)
         return BPM_EHIP;
       *wg_per_cu = n;

@@ -129,6 +129,15 @@ int freeze(bpm_plan* p) {
   e = hipMemcpy(p->dev_sc, p->sc.data(), sizeof(bpm::SliceConst) * p->Nomega,
                 hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan constants)");
+  if (!p->mask.empty()) {
+    e = hipMalloc(&p->dev_mask, p->mask.size());
+    if (e != hipSuccess) {
+      p->dev_mask = nullptr;
+      return fail(BPM_ENOMEM, std::string("hipMalloc(crystal mask): ") + hipGetErrorString(e));
+    }
+    e = hipMemcpy(p->dev_mask, p->mask.data(), p->mask.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(crystal mask)");
+  }
   p->frozen = true;
   return BPM_OK;
 }
@@ -171,6 +180,7 @@ bpm::MarchParams march_params(const bpm_plan* p, const void* E0_in,
   m.h_half = 0.5 * p->h;
   m.x_front = p->x_front;
   m.x_end = p->x_front + p->thickness;
+  m.mask = p->dev_mask;
   return m;
 }
 
@@ -183,6 +193,7 @@ struct DeformJob {
 
 struct BatchGroup {
   int prec, Nx, sched, order;
+  bool masked;
   int n_groups;
   int n_items;
   bpm::BatchItem* d_items;
@@ -233,18 +244,21 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
 
   auto* b = new bpm_batch();
-  std::map<std::tuple<int, int, int, int>, std::vector<std::pair<int, int>>> by_variant;
+  std::map<std::tuple<int, int, int, int, bool>, std::vector<std::pair<int, int>>> by_variant;
   for (int i = 0; i < njobs; ++i) {
     const bpm_plan* p = jobs[i].plan;
     if (jobs[i].u_field)
       b->deforms.push_back({p->precision, p->Nx, p->Nz, p->h, jobs[i].u_field,
                             jobs[i].workspace});
     for (int w = 0; w < p->Nomega; ++w)
-      by_variant[{p->precision, p->Nx, plan_schedule(p), p->split_order}].push_back({i, w});
+      by_variant[{p->precision, p->Nx, plan_schedule(p), p->split_order,
+                  p->dev_mask != nullptr}].push_back({i, w});
   }
   // Host work lists: per variant, items ordered by group, longest first.
   struct HostGroup {
-    int prec, Nx, sched, order, n_groups;
+    int prec, Nx, sched, order;
+    bool masked;
+    int n_groups;
     std::vector<bpm::BatchItem> items;
     std::vector<int> offsets;
   };
@@ -253,9 +267,10 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
     const int prec = std::get<0>(kv.first), Nx = std::get<1>(kv.first);
     const int sched = std::get<2>(kv.first);
     const int order = std::get<3>(kv.first);
+    const bool masked = std::get<4>(kv.first);
     auto& slices = kv.second;
     int per_cu = 0, threads = 0;
-    int rc = bpm::march_occupancy(prec, Nx, sched, order, &per_cu, &threads);
+    int rc = bpm::march_occupancy(prec, Nx, sched, order, masked, &per_cu, &threads);
     if (rc) {
       delete b;
       return fail(rc, "occupancy query failed for Nx " + std::to_string(Nx));
@@ -277,7 +292,7 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
       l.first += jobs[s.first].plan->Nz;
       heap.push(l);
     }
-    HostGroup hg{prec, Nx, sched, order, G, {}, {0}};
+    HostGroup hg{prec, Nx, sched, order, masked, G, {}, {0}};
     for (int g = 0; g < G; ++g) {
       for (auto& s : per_group[g]) {
         const bpm_job& j = jobs[s.first];
@@ -318,7 +333,7 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
                 host[g].offsets.size() * sizeof(int));
     char* base = static_cast<char*>(b->d_mem);
     b->groups.push_back({host[g].prec, host[g].Nx, host[g].sched, host[g].order,
-                         host[g].n_groups,
+                         host[g].masked, host[g].n_groups,
                          static_cast<int>(host[g].items.size()),
                          reinterpret_cast<bpm::BatchItem*>(base + item_off[g]),
                          reinterpret_cast<int*>(base + offs_off[g])});
@@ -355,7 +370,7 @@ int batch_launch(const bpm_batch* b, hipStream_t s) {
     if (rc) return fail(rc, "deformation pre-pass launch failed");
   }
   for (const auto& g : b->groups) {
-    int rc = bpm::launch_march_batch(g.prec, g.Nx, g.sched, g.order, g.d_items,
+    int rc = bpm::launch_march_batch(g.prec, g.Nx, g.sched, g.order, g.masked, g.d_items,
                                      g.d_offsets, g.n_groups, s);
     if (rc) return fail(rc, "persistent march launch failed");
   }
@@ -433,6 +448,19 @@ int bpm_plan_set_detuning(bpm_plan* p, const double* delta) {
     if (!std::isfinite(delta[j]) || !(delta[j] > -1.0))
       return fail(BPM_EINVAL, "delta must be finite and > -1");
   p->delta.assign(delta, delta + p->Nomega);
+  return BPM_OK;
+}
+
+int bpm_plan_set_mask(bpm_plan* p, const unsigned char* mask) {
+  int rc = check_mutable(p);
+  if (rc) return rc;
+  if (!mask) {
+    p->mask.clear();
+    return BPM_OK;
+  }
+  const size_t n = size_t(p->Nx) * size_t(p->Nz);
+  p->mask.resize(n);
+  for (size_t i = 0; i < n; ++i) p->mask[i] = mask[i] ? 1 : 0;
   return BPM_OK;
 }
 
@@ -684,6 +712,7 @@ int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream) {
 void bpm_plan_destroy(bpm_plan* p) {
   if (!p) return;
   if (p->dev_sc) (void)hipFree(p->dev_sc);
+  if (p->dev_mask) (void)hipFree(p->dev_mask);
   delete p;
 }
 

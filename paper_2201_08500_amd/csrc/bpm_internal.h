@@ -38,6 +38,8 @@ struct MarchParams {
   double h_half;            // h / 2
   double x_front, x_end;    // slab [x_front, x_end)
   double a_frac[4];         // A sub-step fractions (0 = skip)
+  const unsigned char* mask;  // [Nz][Nx] crystal mask (nonzero = crystal), or
+                              // nullptr: the slab [x_front, x_end)
 };
 
 // One unit of batched work: one slice of one problem.
@@ -50,24 +52,27 @@ struct BatchItem {
 int launch_deform(int prec, int Nx, int Nz, double h, const double* u,
                   void* table, hipStream_t stream);
 // sched: transform schedule (0 Stockham, 1 four-step, 2 envelope-split);
-// order: splitting order 1, 2 or 4 (sub-steps of Eq. split-op).
+// order: splitting order 1, 2 or 4 (sub-steps of Eq. split-op); p.mask
+// selects the general-mask kernels.
 int launch_march(int prec, int Nx, int sched, int order, int Nomega,
                  const MarchParams& p, hipStream_t stream);
 // Persistent launch: n_groups work groups, group g runs
-// items[offsets[g] .. offsets[g+1]) (device arrays).
-int launch_march_batch(int prec, int Nx, int sched, int order, const BatchItem* items,
-                       const int* offsets, int n_groups, hipStream_t stream);
+// items[offsets[g] .. offsets[g+1]) (device arrays); masked: every item has
+// a general mask (else none has).
+int launch_march_batch(int prec, int Nx, int sched, int order, bool masked,
+                       const BatchItem* items, const int* offsets, int n_groups,
+                       hipStream_t stream);
 // Resident work groups per CU and threads per group of a march variant.
-int march_occupancy(int prec, int Nx, int sched, int order, int* wg_per_cu,
-                    int* threads);
-// Per-precision kernel units (march_<precision>.hip).
-template <int PREC>
+int march_occupancy(int prec, int Nx, int sched, int order, bool masked,
+                    int* wg_per_cu, int* threads);
+// Kernel units, one per (precision, masked): march_<precision>[_mask].hip.
+template <int PREC, bool MASKED>
 int launch_march_p(int Nx, int sched, int order, int Nomega, const MarchParams& p,
                    hipStream_t stream);
-template <int PREC>
+template <int PREC, bool MASKED>
 int launch_march_batch_p(int Nx, int sched, int order, const BatchItem* items,
                          const int* offsets, int n_groups, hipStream_t stream);
-template <int PREC>
+template <int PREC, bool MASKED>
 int march_occupancy_p(int Nx, int sched, int order, int* wg_per_cu, int* threads);
 template <int PREC>
 int launch_pulse_p(int N, int Nx, bool to_freq, double dt, const void* in, void* out,
@@ -90,6 +95,8 @@ struct bpm_plan {
   int split_order = 1, zassenhaus = 1;
   int schedule = -1;  // BPM_SCHED_AUTO
   double dt = 0.0;     // time step of the pulse grid (0: none set)
+  std::vector<unsigned char> mask;       // general crystal mask (empty: slab)
+  unsigned char* dev_mask = nullptr;
   std::vector<double> delta;
   // derived (FP64)
   double k0 = 0, h = 0;

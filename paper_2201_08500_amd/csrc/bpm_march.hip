@@ -6,49 +6,69 @@
 
 namespace bpm {
 
-#define BPM_EXTERN_PREC(P)                                                         \
-  extern template int launch_march_p<P>(int, int, int, int, const MarchParams&,    \
-                                        hipStream_t);                              \
-  extern template int launch_march_batch_p<P>(int, int, int, const BatchItem*,     \
-                                              const int*, int, hipStream_t);       \
-  extern template int march_occupancy_p<P>(int, int, int, int*, int*);              \
-  extern template int launch_pulse_p<P>(int, int, bool, double, const void*, void*,  \
-                                        hipStream_t);
-BPM_EXTERN_PREC(BPM_PREC_FP64)
-BPM_EXTERN_PREC(BPM_PREC_FP32)
-BPM_EXTERN_PREC(BPM_PREC_FP32S)
+#define BPM_EXTERN_PREC(P, M)                                                      \
+  extern template int launch_march_p<P, M>(int, int, int, int, const MarchParams&, \
+                                           hipStream_t);                           \
+  extern template int launch_march_batch_p<P, M>(int, int, int, const BatchItem*,  \
+                                                 const int*, int, hipStream_t);    \
+  extern template int march_occupancy_p<P, M>(int, int, int, int*, int*);
+BPM_EXTERN_PREC(BPM_PREC_FP64, false)
+BPM_EXTERN_PREC(BPM_PREC_FP32, false)
+BPM_EXTERN_PREC(BPM_PREC_FP32S, false)
+BPM_EXTERN_PREC(BPM_PREC_FP64, true)
+BPM_EXTERN_PREC(BPM_PREC_FP32, true)
+BPM_EXTERN_PREC(BPM_PREC_FP32S, true)
 #undef BPM_EXTERN_PREC
+extern template int launch_pulse_p<BPM_PREC_FP64>(int, int, bool, double, const void*, void*,
+                                                  hipStream_t);
+extern template int launch_pulse_p<BPM_PREC_FP32>(int, int, bool, double, const void*, void*,
+                                                  hipStream_t);
+extern template int launch_pulse_p<BPM_PREC_FP32S>(int, int, bool, double, const void*,
+                                                   void*, hipStream_t);
+
+namespace {
+// f(std::integral_constant<int, PREC>, std::bool_constant<MASKED>) for the
+// runtime (prec, masked)
+template <class F>
+int with_prec_mask(int prec, bool masked, F&& f) {
+  using I = std::integral_constant<int, BPM_PREC_FP64>;
+  using S = std::integral_constant<int, BPM_PREC_FP32>;
+  using SS = std::integral_constant<int, BPM_PREC_FP32S>;
+  switch (prec) {
+    case BPM_PREC_FP64:
+      return masked ? f(I{}, std::true_type{}) : f(I{}, std::false_type{});
+    case BPM_PREC_FP32:
+      return masked ? f(S{}, std::true_type{}) : f(S{}, std::false_type{});
+    case BPM_PREC_FP32S:
+      return masked ? f(SS{}, std::true_type{}) : f(SS{}, std::false_type{});
+    default: return BPM_EUNSUPPORTED;
+  }
+}
+}  // namespace
 
 int launch_march(int prec, int Nx, int sched, int order, int Nomega,
                  const MarchParams& p, hipStream_t stream) {
-  switch (prec) {
-    case BPM_PREC_FP64: return launch_march_p<BPM_PREC_FP64>(Nx, sched, order, Nomega, p, stream);
-    case BPM_PREC_FP32: return launch_march_p<BPM_PREC_FP32>(Nx, sched, order, Nomega, p, stream);
-    case BPM_PREC_FP32S: return launch_march_p<BPM_PREC_FP32S>(Nx, sched, order, Nomega, p, stream);
-    default: return BPM_EUNSUPPORTED;
-  }
+  return with_prec_mask(prec, p.mask != nullptr, [&](auto P, auto M) {
+    return launch_march_p<decltype(P)::value, decltype(M)::value>(Nx, sched, order, Nomega,
+                                                                  p, stream);
+  });
 }
 
-int launch_march_batch(int prec, int Nx, int sched, int order, const BatchItem* items,
-                       const int* offsets, int n_groups, hipStream_t stream) {
-  switch (prec) {
-    case BPM_PREC_FP64:
-      return launch_march_batch_p<BPM_PREC_FP64>(Nx, sched, order, items, offsets, n_groups, stream);
-    case BPM_PREC_FP32:
-      return launch_march_batch_p<BPM_PREC_FP32>(Nx, sched, order, items, offsets, n_groups, stream);
-    case BPM_PREC_FP32S:
-      return launch_march_batch_p<BPM_PREC_FP32S>(Nx, sched, order, items, offsets, n_groups, stream);
-    default: return BPM_EUNSUPPORTED;
-  }
+int launch_march_batch(int prec, int Nx, int sched, int order, bool masked,
+                       const BatchItem* items, const int* offsets, int n_groups,
+                       hipStream_t stream) {
+  return with_prec_mask(prec, masked, [&](auto P, auto M) {
+    return launch_march_batch_p<decltype(P)::value, decltype(M)::value>(
+        Nx, sched, order, items, offsets, n_groups, stream);
+  });
 }
 
-int march_occupancy(int prec, int Nx, int sched, int order, int* wg_per_cu, int* threads) {
-  switch (prec) {
-    case BPM_PREC_FP64: return march_occupancy_p<BPM_PREC_FP64>(Nx, sched, order, wg_per_cu, threads);
-    case BPM_PREC_FP32: return march_occupancy_p<BPM_PREC_FP32>(Nx, sched, order, wg_per_cu, threads);
-    case BPM_PREC_FP32S: return march_occupancy_p<BPM_PREC_FP32S>(Nx, sched, order, wg_per_cu, threads);
-    default: return BPM_EUNSUPPORTED;
-  }
+int march_occupancy(int prec, int Nx, int sched, int order, bool masked, int* wg_per_cu,
+                    int* threads) {
+  return with_prec_mask(prec, masked, [&](auto P, auto M) {
+    return march_occupancy_p<decltype(P)::value, decltype(M)::value>(Nx, sched, order,
+                                                                     wg_per_cu, threads);
+  });
 }
 
 int launch_pulse(int prec, int N, int Nx, bool to_freq, double dt, const void* in,

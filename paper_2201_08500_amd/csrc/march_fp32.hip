@@ -1,15 +1,16 @@
-// z-march kernels of one precision (fp32): every transform schedule, Nx
-// and splitting order, instantiated here so that the precisions compile in
-// parallel.
+// z-march kernels of one precision (fp32, slab crystal): every
+// transform schedule, Nx and splitting order, instantiated here so that the
+// kernel units compile in parallel.
 
 #include "bpm_device.h"
 
 namespace bpm {
 
-template int launch_march_p<BPM_PREC_FP32>(int, int, int, int, const MarchParams&, hipStream_t);
-template int launch_march_batch_p<BPM_PREC_FP32>(int, int, int, const BatchItem*, const int*, int,
-                                          hipStream_t);
-template int march_occupancy_p<BPM_PREC_FP32>(int, int, int, int*, int*);
+template int launch_march_p<BPM_PREC_FP32, false>(int, int, int, int, const MarchParams&,
+                                        hipStream_t);
+template int launch_march_batch_p<BPM_PREC_FP32, false>(int, int, int, const BatchItem*, const int*,
+                                              int, hipStream_t);
+template int march_occupancy_p<BPM_PREC_FP32, false>(int, int, int, int*, int*);
 template int launch_pulse_p<BPM_PREC_FP32>(int, int, bool, double, const void*, void*, hipStream_t);
 
 }  // namespace bpm

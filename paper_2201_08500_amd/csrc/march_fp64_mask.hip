@@ -1,0 +1,15 @@
+// z-march kernels of one precision (fp64, general-mask crystal): every
+// transform schedule, Nx and splitting order, instantiated here so that the
+// kernel units compile in parallel.
+
+#include "bpm_device.h"
+
+namespace bpm {
+
+template int launch_march_p<BPM_PREC_FP64, true>(int, int, int, int, const MarchParams&,
+                                        hipStream_t);
+template int launch_march_batch_p<BPM_PREC_FP64, true>(int, int, int, const BatchItem*, const int*,
+                                              int, hipStream_t);
+template int march_occupancy_p<BPM_PREC_FP64, true>(int, int, int, int*, int*);
+
+}  // namespace bpm

@@ -81,6 +81,11 @@ def test_setters_validate_and_freeze_rules():
     assert L.bpm_plan_set_options(p.handle, 1, 0) == 0
     assert L.bpm_plan_set_options(p.handle, 2, 1) == 0
     assert L.bpm_plan_set_options(p.handle, 4, 1) == 0
+    m = np.zeros((10, 1024), np.uint8)
+    assert L.bpm_plan_set_mask(p.handle, m.ctypes.data_as(ctypes.c_void_p)) == 0
+    assert L.bpm_plan_set_mask(p.handle, None) == 0
+    assert L.bpm_plan_set_time_grid(p.handle, 1e-15) == -1        # Nomega = 4
+    assert L.bpm_plan_set_time_grid(p.handle, -1.0) == -1
     bad = (ctypes.c_double * 4)(0.0, -2.0, 0.0, 0.0)
     assert L.bpm_plan_set_detuning(p.handle, bad) == -1
     assert L.bpm_plan_set_detuning(p.handle, None) == -1
