@@ -50,13 +50,15 @@ def lds_bytes_per_cell_update(Nx: int, storage_bytes: int) -> float:
 
 
 def kernel_source_sha256() -> str:
-    """sha256 over the device sources (csrc/*.h and *.hip, sorted by name):
-    the key under which hardware-counter records are valid."""
+    """sha256 over the sources that define the kernels (csrc/bpm_device.h,
+    bpm_internal.h and the kernel units march_*.hip, sorted by name): the key
+    under which hardware-counter records are valid.  Host-side dispatch
+    (bpm_march.hip, bpm_host.cpp) is not part of it."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2201_08500_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
+        if name.endswith(".h") or (name.startswith("march_") and name.endswith(".hip")):
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()

@@ -87,7 +87,7 @@ int default_schedule(int prec, int Nx) {
   const int col = Nx == 256 ? 0 : Nx == 512 ? 1 : Nx == 1024 ? 2 : Nx == 2048 ? 3 : 4;
   static const int kBest[3][5] = {
       /* fp64  */ {0, 1, 2, 2, 1},
-      /* fp32  */ {0, 1, 2, 2, 0},
+      /* fp32  */ {0, 1, 2, 2, 1},
       /* fp32s */ {1, 1, 2, 2, 1},
   };
   const int row = prec == BPM_PREC_FP64 ? 0 : prec == BPM_PREC_FP32 ? 1 : 2;
