@@ -180,17 +180,32 @@ __device__ __forceinline__ void dft(cx<T> (&v)[R]) {
     dft4<INV>(v[1], v[3], v[5], v[7]);
     const cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
     const cx<T> o0 = v[1];
-    const cx<T> o1 = tw16<2, INV>(v[3]);
     const cx<T> o2 = tw16<4, INV>(v[5]);
-    const cx<T> o3 = tw16<6, INV>(v[7]);
     v[0] = e0 + o0;
     v[4] = e0 - o0;
-    v[1] = e1 + o1;
-    v[5] = e1 - o1;
     v[2] = e2 + o2;
     v[6] = e2 - o2;
-    v[3] = e3 + o3;
-    v[7] = e3 - o3;
+    if constexpr (sizeof(T) == 8) {
+      // W8^{+-1} = r (1 -+ i) and W8^{+-3} = r (-1 -+ i), r = 1/sqrt(2):
+      // e +- W o = e +- r t with t = (o.x -+ ..., ...), so each output is
+      // one multiply-add (two adds and four FMAs per pair instead of eight
+      // operations)
+      constexpr T r = T(0.70710678118654752440);
+      const cx<T> a = v[3], b = v[7];
+      const cx<T> t1 = INV ? cx<T>{a.x - a.y, a.y + a.x} : cx<T>{a.x + a.y, a.y - a.x};
+      const cx<T> t3 = INV ? cx<T>{-b.x - b.y, b.x - b.y} : cx<T>{b.y - b.x, -b.x - b.y};
+      v[1] = {e1.x + r * t1.x, e1.y + r * t1.y};
+      v[5] = {e1.x - r * t1.x, e1.y - r * t1.y};
+      v[3] = {e3.x + r * t3.x, e3.y + r * t3.y};
+      v[7] = {e3.x - r * t3.x, e3.y - r * t3.y};
+    } else {
+      const cx<T> o1 = tw16<2, INV>(v[3]);
+      const cx<T> o3 = tw16<6, INV>(v[7]);
+      v[1] = e1 + o1;
+      v[5] = e1 - o1;
+      v[3] = e3 + o3;
+      v[7] = e3 - o3;
+    }
   } else if constexpr (R == 16) {
     // 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
 #pragma unroll
@@ -396,6 +411,7 @@ struct Scheme {
 template <int PREC, int N_, int R_, int... RADS>
 struct March {
   static constexpr bool kSplit = false;
+  static constexpr bool kLateRow = false;
   static constexpr int N = N_;  // transform length
   static constexpr int R = R_;  // samples per thread per envelope
   using CT = typename Prec<PREC>::CT;
@@ -469,8 +485,9 @@ struct March {
   static constexpr int kSync = NBUF == 2 ? kDouble : kSingle;
 
   // Stockham pass P over NE envelopes v[e] (LDS region e at lds + e kEnv).
-  template <int P, bool INV, int SYNC, int NE>
-  BPM_INLINE static void pass_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
+  // tw: the pass twiddles, a register array Tw<CT>[NTW] or a TwTable.
+  template <int P, bool INV, int SYNC, int NE, class TWS>
+  BPM_INLINE static void pass_n(cx<CT> (&v)[NE][R], const TWS& tw,
                                 SV* lds, int t, int& xbuf) {
     constexpr int Rp = rad[P];
     constexpr int Ns = ns(P);
@@ -535,22 +552,22 @@ struct March {
     }
   }
 
-  template <bool INV, int SYNC, int NE, int... P>
-  BPM_INLINE static void fft_impl(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
+  template <bool INV, int SYNC, int NE, class TWS, int... P>
+  BPM_INLINE static void fft_impl(cx<CT> (&v)[NE][R], const TWS& tw,
                                   SV* lds, int t, int& xbuf,
                                   std::integer_sequence<int, P...>) {
     (pass_n<P, INV, SYNC, NE>(v, tw, lds, t, xbuf), ...);
   }
   // In-place transform of NE envelopes.
-  template <bool INV, int SYNC, int NE>
-  BPM_INLINE static void fft_n(cx<CT> (&v)[NE][R], const Tw<CT> (&tw)[NTW],
+  template <bool INV, int SYNC, int NE, class TWS>
+  BPM_INLINE static void fft_n(cx<CT> (&v)[NE][R], const TWS& tw,
                                SV* lds, int t, int& xbuf) {
     fft_impl<INV, SYNC, NE>(v, tw, lds, t, xbuf,
                             std::make_integer_sequence<int, NP>{});
   }
   // Both envelopes (psi~_+ in a, psi~_- in b).
-  template <bool INV, int SYNC = kSync>
-  BPM_INLINE static void fft(Reg& a, Reg& b, const Tw<CT> (&tw)[NTW], SV* lds,
+  template <bool INV, int SYNC = kSync, class TWS>
+  BPM_INLINE static void fft(Reg& a, Reg& b, const TWS& tw, SV* lds,
                              int t, int& xbuf) {
     cx<CT> v[2][R];
 #pragma unroll
@@ -593,6 +610,23 @@ struct March {
     (twiddles_pass<P>(tw, t), ...);
   }
 
+  // Twiddles of a one-wavefront transform (T = 64) kept in LDS instead of
+  // registers: a table [NTW][64] of FP64 values (they depend on the lane
+  // only), shared by every wavefront of the work group.
+  static constexpr size_t kTableBytes = size_t(NTW) * 64 * sizeof(cx<double>);
+  struct TwTable {
+    const cx<double>* base;
+    int lane;
+    BPM_INLINE Tw<CT> operator[](int k) const { return Tw<CT>{base[k * 64 + lane]}; }
+  };
+  __device__ static void fill_table(cx<double>* table, int lane) {
+    static_assert(T == 64, "a twiddle table serves one-wavefront transforms");
+    Tw<CT> tw[NTW];
+    twiddles_impl(tw, lane, std::make_integer_sequence<int, NP>{});
+#pragma unroll
+    for (int k = 0; k < NTW; ++k) table[k * 64 + lane] = tw[k].w;
+  }
+
   // Transform interface used by march_slice: per-thread context (twiddles),
   // the DFT bin held in register slot i after forward(), and in-place
   // forward / inverse transforms of both envelopes.
@@ -600,7 +634,7 @@ struct March {
     Tw<CT> tw[NTW];
     int xbuf;
   };
-  __device__ static void init(Ctx& c, int t) {
+  __device__ static void init(Ctx& c, int t, SV* = nullptr) {
     twiddles_impl(c.tw, t, std::make_integer_sequence<int, NP>{});
     c.xbuf = 0;
   }
@@ -626,9 +660,12 @@ struct March {
 // W_N^{m k1}, exchange so that wavefront k1 holds y[m][k1] for all m (lane l,
 // slot i -> m = l + 64 i), then the M-point transform over m.  Slot i of
 // lane l in wavefront w ends with bin K = w + W (l + 64 i).
-template <int PREC, int W, class In>
+template <int PREC, int W, class In, bool TWL = false>
 struct FourStep {
   static constexpr bool kSplit = false;
+  // fetch the deformation row after the forward transform (fewer live
+  // registers across it) where the register file is the limit
+  static constexpr bool kLateRow = TWL;
   using CT = typename Prec<PREC>::CT;
   using ST = typename Prec<PREC>::ST;
   using SV = typename vec2<ST>::type;
@@ -644,8 +681,13 @@ struct FourStep {
   static constexpr size_t kGp = W > 1 ? size_t(W) * 2 * M : 0;
   // Separate forward and inverse exchange buffers when they fit; otherwise
   // one buffer and two extra barriers per step.
-  static constexpr bool kAlias = (kG + kGp) * sizeof(SV) > 160 * 1024;
-  static constexpr size_t kLdsBytes = (kAlias ? kG : kG + kGp) * sizeof(SV);
+  static constexpr bool kAlias = (kG + kGp) * sizeof(SV) + (TWL ? In::kTableBytes : 0) >
+                                 160 * 1024;
+  // TWL: the in-wavefront twiddles live in an LDS table after the exchange
+  // buffers (frees their registers where the state fills the register file)
+  static constexpr size_t kTabOff = ((kAlias ? kG : kG + kGp) * sizeof(SV) + 15) / 16 * 16;
+  static constexpr size_t kLdsBytes = kTabOff + (TWL ? In::kTableBytes : 0);
+  static_assert(kLdsBytes <= 160 * 1024, "four-step march does not fit in LDS");
   static constexpr int NTWX = W > 1 ? J * (W - 1) : 1;
   using Reg = cx<CT>[R];
 
@@ -653,8 +695,17 @@ struct FourStep {
     typename In::Ctx in;
     Tw<CT> twx[NTWX];
   };
-  __device__ static void init(Ctx& c, int t) {
-    In::init(c.in, t & 63);
+  BPM_INLINE static cx<double>* table(SV* lds) {
+    return reinterpret_cast<cx<double>*>(reinterpret_cast<char*>(lds) + kTabOff);
+  }
+  __device__ static void init(Ctx& c, int t, SV* lds) {
+    if constexpr (TWL) {
+      if (t < 64) In::fill_table(table(lds), t);
+      c.in.xbuf = 0;
+      lds_barrier();
+    } else {
+      In::init(c.in, t & 63);
+    }
     if constexpr (W > 1) {
 #pragma unroll
       for (int j = 0; j < J; ++j)
@@ -703,13 +754,21 @@ struct FourStep {
       }
       wave_sync();
     }
-    In::template fft<false, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
+    if constexpr (TWL)
+      In::template fft<false, In::kWave>(a, b, typename In::TwTable{table(lds), l}, own, l,
+                                         c.in.xbuf);
+    else
+      In::template fft<false, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
   }
 
   BPM_INLINE static void inverse(Reg& a, Reg& b, Ctx& c, SV* lds, int t) {
     const int wv = t >> 6, l = t & 63;
     SV* own = lds + wv * kRegion;
-    In::template fft<true, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
+    if constexpr (TWL)
+      In::template fft<true, In::kWave>(a, b, typename In::TwTable{table(lds), l}, own, l,
+                                        c.in.xbuf);
+    else
+      In::template fft<true, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
     if constexpr (W > 1) {
       SV* gp = kAlias ? lds : lds + kG;
       constexpr int kStride = kAlias ? kRegion : 2 * M;
@@ -1017,7 +1076,7 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
   const SV* table = static_cast<const SV*>(p.table);
 
   typename Tr::Ctx ctx;
-  Tr::init(ctx, t);
+  Tr::init(ctx, t, lds);
 
   // Propagators of the bins this thread holds after a forward transform,
   // 1/Nx of the inverse transform folded in; slab mask of its x samples.
@@ -1063,8 +1122,11 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
   for (int n = 0; n < p.Nz; ++n) {
     // Row n0 + n of exp(i h u), fetched at the start of the step and used by
     // the couplings, so its latency hides behind the transforms.
+    // late: fetch the row after the forward transform (first order only:
+    // the higher orders couple before their first transform)
+    constexpr bool late = Tr::kLateRow && ORDER == 1;
     SV e[R];
-    if constexpr (DEFORMED) {
+    if constexpr (DEFORMED && !late) {
       const SV* row = table + size_t(p.n0 + n) * N;
 #pragma unroll
       for (int i = 0; i < R; ++i) e[i] = row[t + T * i];
@@ -1075,6 +1137,11 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
     for (int s = 0; s < S::NS; ++s) {
       if (S::has_a(s)) {
         Tr::forward(a, b, ctx, lds, t);
+        if constexpr (DEFORMED && late) {
+          const SV* row = table + size_t(p.n0 + n) * N;
+#pragma unroll
+          for (int i = 0; i < R; ++i) e[i] = row[t + T * i];
+        }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           a[i] = conv<CT>(cmul(conv<double>(a[i]), Pp[S::pset(s)][i]));
@@ -1254,7 +1321,11 @@ template <int PREC> struct Choice<PREC, 256, 1> { using type = FourStep<PREC, 1,
 template <int PREC> struct Choice<PREC, 512, 1> { using type = FourStep<PREC, 1, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 1024, 1> { using type = FourStep<PREC, 2, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 2048, 1> { using type = FourStep<PREC, 4, InWave512<PREC>>; };
-template <int PREC> struct Choice<PREC, 4096, 1> { using type = FourStep<PREC, 8, InWave512<PREC>>; };
+// 4096: in-wavefront twiddles from an LDS table where the FP64 state fills
+// the register file (fp64, fp32s); fp32 keeps them in registers (faster there)
+template <int PREC> struct Choice<PREC, 4096, 1> {
+  using type = FourStep<PREC, 8, InWave512<PREC>, PREC != BPM_PREC_FP32>;
+};
 // 2 -- envelope-split four-step (2W wavefronts) where it fits, else four-step
 template <int PREC> struct Choice<PREC, 256, 2> { using type = typename Choice<PREC, 256, 1>::type; };
 template <int PREC> struct Choice<PREC, 512, 2> { using type = typename Choice<PREC, 512, 1>::type; };
