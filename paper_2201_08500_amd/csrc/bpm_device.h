@@ -1058,6 +1058,185 @@ struct Split4 {
   }
 };
 
+// Envelope-split march of a slice that fits one wavefront per envelope
+// (Nx = 256, 512): wavefront 0 carries psi~_+, wavefront 1 psi~_-, each with
+// the one-wavefront Stockham transform of In.  A thread's x samples l + 64 i
+// are exactly the transform's input and output slots, so there is no
+// forward exchange; after the inverse transform each wavefront writes its
+// envelope to a double-buffered LDS area and reads the partner's at the same
+// x for the coupling: one work-group barrier per A sub-step, and two
+// wavefronts per slice instead of one.
+template <int PREC, class In>
+struct Split1 {
+  using CT = typename Prec<PREC>::CT;
+  using ST = typename Prec<PREC>::ST;
+  using SV = typename vec2<ST>::type;
+  using IV = typename In::SV;
+  static_assert(In::T == 64, "one-wavefront transform");
+  static constexpr bool kSplit = true;
+  static constexpr int N = In::N;
+  static constexpr int R = In::R;
+  static constexpr int T = 128;
+  static constexpr size_t kScratchBytes = (size_t(In::kEnv) * sizeof(IV) + 15) / 16 * 16;
+  static constexpr size_t kXBytes = size_t(2) * N * sizeof(SV);   // both envelopes
+  static constexpr size_t kLdsBytes = 2 * kScratchBytes + 2 * kXBytes;
+  static_assert(kLdsBytes <= 160 * 1024, "split march does not fit in LDS");
+
+  BPM_INLINE static void st(SV* q, int i, cx<CT> v) {
+    SV s;
+    s.x = static_cast<ST>(v.x);
+    s.y = static_cast<ST>(v.y);
+    q[i] = s;
+  }
+  BPM_INLINE static cx<CT> ld(const SV* q, int i) {
+    const SV s = q[i];
+    return {static_cast<CT>(s.x), static_cast<CT>(s.y)};
+  }
+
+  template <bool DEFORMED, int ORDER, bool MASKED>
+  BPM_INLINE static void run(const MarchParams& p, int slice, int t, SV* lds) {
+    if (__builtin_amdgcn_readfirstlane(t >= 64 ? 1 : 0))
+      run_env<DEFORMED, 1, ORDER, MASKED>(p, slice, t - 64, lds);
+    else
+      run_env<DEFORMED, 0, ORDER, MASKED>(p, slice, t, lds);
+  }
+
+  // Coupling of one B sub-step for envelope F (as in Split4::couple).
+  template <bool DEFORMED, int F>
+  BPM_INLINE static cx<CT> couple(const cx<double> (&d)[3], SV er, cx<CT> self,
+                                  cx<CT> other) {
+    cx<double> c = d[1 + F];
+    if constexpr (DEFORMED) {
+      const cx<double> ee = {static_cast<double>(er.x), static_cast<double>(er.y)};
+      c = F ? cmulc(c, ee) : cmul(c, ee);
+    }
+    return conv<CT>(cmuladd(d[0], conv<double>(self), c, conv<double>(other)));
+  }
+
+  // Lane l of envelope E: x samples l + 64 i.
+  template <bool DEFORMED, int E, int ORDER, bool MASKED>
+  BPM_INLINE static void run_env(const MarchParams& p, int slice, int l, SV* lds) {
+    using S = Scheme<ORDER>;
+    const SliceConst& sc = p.sc[slice];
+    const SV* table = static_cast<const SV*>(p.table);
+    SV* out = static_cast<SV*>(E ? p.Eh_out : p.E0_out) + size_t(slice) * N;
+    IV* scratch = reinterpret_cast<IV*>(reinterpret_cast<char*>(lds) + E * kScratchBytes);
+    SV* X = reinterpret_cast<SV*>(reinterpret_cast<char*>(lds) + 2 * kScratchBytes);
+
+    typename In::Ctx ic;
+    In::init(ic, l);
+    cx<double> P[S::NP][R];
+    bool inside[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int k = l + 64 * i;                 // bin of slot i
+      const int ks = k < N / 2 ? k : k - N;
+#pragma unroll
+      for (int q = 0; q < S::NP; ++q)
+        P[q][i] = propagator(ks, N, p.dx, sc.k, p.h_half, E ? -1.0 : 1.0, p.dz,
+                             p.a_frac[S::pdef(q)]);
+      const double x = static_cast<double>(l + 64 * i - N / 2) * p.dx;
+      inside[i] = (x >= p.x_front) && (x < p.x_end);
+    }
+    cx<double> d[S::NS][3];
+#pragma unroll
+    for (int s = 0; s < S::NS; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[s][c] = {sc.d[s][2 * c], sc.d[s][2 * c + 1]};
+
+    const SV* in_a = static_cast<const SV*>(p.E0_in) + size_t(slice) * N;
+    const SV* in_b = p.Eh_in ? static_cast<const SV*>(p.Eh_in) + size_t(slice) * N
+                             : nullptr;
+    const SV* src = E == 0 ? in_a : in_b;
+    cx<CT> v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = src ? ld(src, l + 64 * i) : cx<CT>{CT(0), CT(0)};
+
+    SV er[R], er_next[R];
+    bool in_cur[R], in_next[R];
+    if constexpr (ORDER > 1 && DEFORMED) {
+      const SV* row = table + size_t(p.n0) * N;
+#pragma unroll
+      for (int i = 0; i < R; ++i) er[i] = er_next[i] = row[l + 64 * i];
+    }
+    if constexpr (ORDER > 1) {
+      crystal_row<R, N, MASKED>(p, p.n0, l, 64, inside, in_cur);
+      const SV* osrc = E == 0 ? in_b : in_a;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const cx<CT> other = osrc ? ld(osrc, l + 64 * i) : cx<CT>{CT(0), CT(0)};
+        if (in_cur[i]) v[i] = couple<DEFORMED, E>(d[0], er[i], v[i], other);
+      }
+    }
+
+    int buf = 0;
+    for (int n = 0; n < p.Nz; ++n) {
+      if constexpr (ORDER == 1) {
+        if constexpr (DEFORMED) {
+          const SV* row = table + size_t(p.n0 + n) * N;
+#pragma unroll
+          for (int i = 0; i < R; ++i) er[i] = row[l + 64 * i];
+        }
+        crystal_row<R, N, MASKED>(p, p.n0 + n, l, 64, inside, in_cur);
+      } else {
+        if (n + 1 < p.Nz) {
+          if constexpr (DEFORMED) {
+            const SV* row = table + size_t(p.n0 + n + 1) * N;
+#pragma unroll
+            for (int i = 0; i < R; ++i) er_next[i] = row[l + 64 * i];
+          }
+          crystal_row<R, N, MASKED>(p, p.n0 + n + 1, l, 64, inside, in_next);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < S::NS; ++s) {
+        if (S::has_a(s)) {
+          cx<CT> z[1][R];
+#pragma unroll
+          for (int i = 0; i < R; ++i) z[0][i] = v[i];
+          In::template fft_n<false, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+            z[0][i] = conv<CT>(cmul(conv<double>(z[0][i]), P[S::pset(s)][i]));
+          In::template fft_n<true, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
+          // exchange: this envelope out, the partner's in (double-buffered:
+          // the next write to this half comes after the next barrier)
+          SV* Xb = X + buf * 2 * N;
+          buf ^= 1;
+#pragma unroll
+          for (int i = 0; i < R; ++i) st(Xb + E * N, l + 64 * i, z[0][i]);
+          lds_barrier();
+          const bool chain = ORDER > 1 && s == S::NS - 1 && n + 1 < p.Nz;
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const cx<CT> self = z[0][i];
+            const cx<CT> other = ld(Xb + (1 - E) * N, l + 64 * i);
+            if (ORDER > 1 && chain) {
+              cx<CT> s1 = self, o1 = other;
+              if (in_cur[i]) {
+                s1 = couple<DEFORMED, E>(d[s], er[i], self, other);
+                o1 = couple<DEFORMED, 1 - E>(d[s], er[i], other, self);
+              }
+              v[i] = in_next[i] ? couple<DEFORMED, E>(d[0], er_next[i], s1, o1) : s1;
+            } else {
+              v[i] = in_cur[i] ? couple<DEFORMED, E>(d[s], er[i], self, other) : self;
+            }
+          }
+        }
+      }
+      if constexpr (ORDER > 1) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if constexpr (DEFORMED) er[i] = er_next[i];
+          in_cur[i] = in_next[i];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) st(out, l + 64 * i, v[i]);
+  }
+};
+
 // Whole march of one slice by threads t = 0..T-1 of the calling group, with
 // both envelopes in every thread (Stockham and four-step transforms).  Each
 // step runs the sub-steps of Scheme<ORDER> (Eq. fov10 per sub-step).
@@ -1327,8 +1506,8 @@ template <int PREC> struct Choice<PREC, 4096, 1> {
   using type = FourStep<PREC, 8, InWave512<PREC>, PREC != BPM_PREC_FP32>;
 };
 // 2 -- envelope-split four-step (2W wavefronts) where it fits, else four-step
-template <int PREC> struct Choice<PREC, 256, 2> { using type = typename Choice<PREC, 256, 1>::type; };
-template <int PREC> struct Choice<PREC, 512, 2> { using type = typename Choice<PREC, 512, 1>::type; };
+template <int PREC> struct Choice<PREC, 256, 2> { using type = Split1<PREC, InWave256<PREC>>; };
+template <int PREC> struct Choice<PREC, 512, 2> { using type = Split1<PREC, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 1024, 2> { using type = Split4<PREC, 2, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 2048, 2> { using type = Split4<PREC, 4, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 4096, 2> { using type = typename Choice<PREC, 4096, 1>::type; };

@@ -85,10 +85,11 @@ int launch_pulse(int prec, int N, int Nx, bool to_freq, double dt, const void* i
 // slices); 0 Stockham, 1 four-step, 2 envelope-split four-step.
 int default_schedule(int prec, int Nx) {
   const int col = Nx == 256 ? 0 : Nx == 512 ? 1 : Nx == 1024 ? 2 : Nx == 2048 ? 3 : 4;
+  // (2 at Nx 4096 is the four-step: the envelope split does not fit there)
   static const int kBest[3][5] = {
-      /* fp64  */ {0, 1, 2, 2, 1},
-      /* fp32  */ {0, 1, 2, 2, 1},
-      /* fp32s */ {1, 1, 2, 2, 1},
+      /* fp64  */ {2, 2, 2, 2, 1},
+      /* fp32  */ {2, 2, 2, 2, 1},
+      /* fp32s */ {2, 2, 2, 2, 1},
   };
   const int row = prec == BPM_PREC_FP64 ? 0 : prec == BPM_PREC_FP32 ? 1 : 2;
   return kBest[row][col];
