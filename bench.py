@@ -259,6 +259,112 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
+def bench_extensions(args):
+    """The extensions of the march on the bent-crystal workload, each timed
+    against the plain first-order march of the same precision: 2nd- and
+    4th-order splitting, a shaped crystal mask, a march in segments, and the
+    pulse pipeline (time -> frequency, march, frequency -> time).  Accuracy of
+    each against the fp64 GPU run of the same configuration (all slices)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2201_08500_amd import Plan
+    from workloads.metrics import rel_l2
+
+    torch.cuda.set_device(0)
+    w = W.c2_bent_crystal()
+    u = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
+    cells = w.cell_updates
+    prec = args.headline
+    x = (np.arange(w.Nx) - w.Nx // 2) * w.dx
+    z = np.arange(w.Nz) * w.dz
+    # tilted entrance surface (asymmetric cut) x >= -40 um + 0.05 z
+    mask = x[None, :] >= (-40e-6 + 0.05 * z)[:, None]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    def both(a, b):
+        return np.concatenate([a.cpu().numpy().ravel(), b.cpu().numpy().ravel()]).astype(np.complex128)
+
+    def march_case(precision, **kw):
+        p = Plan.from_workload(w, precision=precision, **kw)
+        E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
+        a, b = torch.empty_like(E0), torch.empty_like(E0)
+        ws = torch.empty(p.workspace_bytes(), dtype=torch.uint8, device="cuda")
+        p.deformation_table(u, ws)
+        ms = timed(lambda: p.march(E0, ws, a, b), args.steps)
+        return p, E0, ws, a, b, ms
+
+    out = {}
+    _, _, _, a, b, base_ms = march_case(prec)
+    out["first_order"] = {"march_ms": base_ms, "cell_updates_per_s": cells / (base_ms * 1e-3)}
+    for name, kw in [("order2", dict(split_order=2)), ("order4", dict(split_order=4)),
+                     ("mask", dict(mask=mask))]:
+        print(f"[bench] extensions: {name}", file=sys.stderr, flush=True)
+        _, _, _, a, b, ms = march_case(prec, **kw)
+        _, _, _, ra, rb, _ = march_case("fp64", **kw)
+        out[name] = {"march_ms": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+                     "relative_to_first_order": ms / base_ms,
+                     "rel_l2_vs_fp64_gpu": float(rel_l2(both(a, b), both(ra, rb)))}
+    # segments: 8 x 500 steps chained through their outputs
+    print("[bench] extensions: segments", file=sys.stderr, flush=True)
+    p, E0, ws, a, b, _ = march_case(prec)
+    sa, sb = torch.empty_like(E0), torch.empty_like(E0)
+    seg = w.Nz // 8
+
+    def segmented():
+        p.march_segment(E0, None, ws, 0, seg, sa, sb)
+        for k in range(1, 8):
+            p.march_segment(sa, sb, ws, k * seg, seg, sa, sb)
+    ms = timed(segmented, args.steps)
+    p.march(E0, ws, a, b)
+    torch.cuda.synchronize()
+    out["segments8"] = {"march_ms": ms, "relative_to_first_order": ms / base_ms,
+                        "rel_l2_vs_monolithic": float(rel_l2(both(sa, sb), both(a, b)))}
+    # pulse: the slices on a DFT grid spanning +-5 Darwin widths
+    print("[bench] extensions: pulse", file=sys.stderr, flush=True)
+    eps = W.darwin_relative_width(w.chih, w.chihbar, w.theta_B)
+    omega0 = 2 * math.pi * 299792458.0 / w.lam
+    dt = 2 * math.pi / (10 * eps * omega0)
+    pp = Plan(w.Nx, w.dx, w.dz, w.Nz, w.chi0, w.chih, w.chihbar, w.theta_B, w.lam,
+              w.Nomega, precision=prec, time_step=dt)
+    f = W.pulse_field(w.Nx, w.dx, w.Nomega, dt, w.lam, w.theta_B, w.theta_B, 40 * dt)
+    ft = torch.from_numpy(f).to(pp.field_dtype).cuda()
+    ew = torch.empty_like(ft)
+    t_ms = timed(lambda: pp.to_frequency(ft, out=ew), args.steps)
+    back = pp.to_time(pp.to_frequency(ft))
+    torch.cuda.synchronize()
+    pa, pb = pp.propagate_pulse(ft, u)
+    torch.cuda.synchronize()
+    tot = timed(lambda: pp.propagate_pulse(ft, u), max(2, args.steps // 2))
+    out["pulse"] = {"transform_ms": t_ms, "pipeline_ms": tot,
+                    "pipeline_cell_updates_per_s": cells / (tot * 1e-3),
+                    "round_trip_rel_l2": float(rel_l2(back.cpu().numpy().astype(np.complex128), f)),
+                    "dt_fs": dt * 1e15}
+    line = {
+        "metric": METRIC, "value": out["first_order"]["cell_updates_per_s"],
+        "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": base_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32s": "f64", "fp32": "f32", "fp64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": w.name + "-extensions", "precision": prec},
+        "extensions": out,
+    }
+    print(json.dumps(line))
+
+
 def bench_serve(args):
     """Served request stream: Poisson arrivals (seeded), sizes as the uneven
     batch, half fp64 and half fp32-storage requests, admission by an HBM
@@ -357,7 +463,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices-per-core", type=int, default=96)
     ap.add_argument("--workload", default="bent-crystal",
-                    choices=["bent-crystal", "batch", "serve"])
+                    choices=["bent-crystal", "batch", "serve", "extensions"])
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-duration", type=float, default=60.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -385,6 +491,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "extensions":
+        bench_extensions(args)
         return
 
     import numpy as np
