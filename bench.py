@@ -8,6 +8,10 @@ One benchmark step is one pass of the whole hot path: the deformation
 pre-pass (exp(i h u) table) plus the march of all slices, inputs resident in
 HBM.  Metric: cell-updates/s = Nx * Nz * Nomega / step time.
 
+--workload thermal-bump runs the same measurement on the 4096 x 8192 x 1024
+thermal-bump configuration; batch, serve and extensions time the batched
+launch, the served request stream and the march's extensions.
+
 Prints one JSON line.  The oracle (CPU, FP64 numpy) is timed on a bounded
 sample of slices on the host's cores as a reported baseline.
 """
@@ -458,12 +462,15 @@ def main():
     ap.add_argument("--headline", default="fp32s",
                     choices=["fp32s", "fp32", "fp64"])
     ap.add_argument("--variants", default="fp32s,fp32,fp64")
-    ap.add_argument("--oracle-slices", default="120,128,136",
-                    help="slices recomputed by the oracle for the error report")
+    ap.add_argument("--oracle-slices", default=None,
+                    help="slices recomputed by the oracle for the error report "
+                         "(default 120,128,136 for the bent crystal, 511,640 "
+                         "for the thermal bump)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices-per-core", type=int, default=96)
     ap.add_argument("--workload", default="bent-crystal",
-                    choices=["bent-crystal", "batch", "serve", "extensions"])
+                    choices=["bent-crystal", "thermal-bump", "batch", "serve",
+                             "extensions"])
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-duration", type=float, default=60.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -502,7 +509,15 @@ def main():
     from workloads.metrics import report
 
     torch.cuda.set_device(0)
-    w = W.c2_bent_crystal()
+    if args.workload == "thermal-bump":
+        # 4096 x 8192 x 1024: the largest configuration, a precision check
+        w = W.c3_thermal_bump()
+        default_slices = "511,640"
+    else:
+        w = W.c2_bent_crystal()
+        default_slices = "120,128,136"
+    if args.oracle_slices is None:
+        args.oracle_slices = default_slices
     u_t = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
     cells = w.cell_updates
     variants = [v for v in args.variants.split(",") if v]
