@@ -806,16 +806,17 @@ struct FourStep {
   }
 };
 
-// Envelope-split four-step march of one slice: 2 W wavefronts, wavefronts
-// 0..W-1 carry psi~_+ and W..2W-1 carry psi~_-, each with the radix-W
-// cross-wavefront step and an M-point in-wavefront transform of its own
-// envelope.  Twice the wavefronts of FourStep at half the registers each, so
-// two wavefronts share every SIMD and hide each other's LDS latency.  After
-// the inverse exchange every thread rebuilds BOTH envelopes at its x samples
-// (the cross-wavefront inverse DFT is done twice, a small cost) so that the
-// coupling needs no further exchange: two work-group barriers per z-step.
-// The envelope is a template parameter of the per-wavefront code (every
-// wavefront holds one envelope), so no per-sample selects remain.
+// Envelope-split four-step march of one slice: 2 W wavefronts.  In k space
+// wavefronts 0..W-1 carry psi~_+ and W..2W-1 carry psi~_-, each with an
+// M-point in-wavefront transform of its own envelope.  In x space the T = 2 W
+// 64 threads share the samples instead: thread t holds BOTH envelopes at
+// x = t + T s, s < R/2, so the cross-wavefront radix-W steps, the twiddles
+// and the coupling are each done once per sample, and the coupling needs no
+// exchange of its own: two work-group barriers per z-step.  Twice the
+// wavefronts of FourStep at half the registers each, so two wavefronts share
+// every SIMD and hide each other's LDS latency.  The envelope of the
+// in-wavefront part is a template parameter (every wavefront holds one
+// envelope there), so no per-sample selects remain.
 //
 // LDS: 2W regions, one per wavefront, each the forward exchange target
 // (M samples) and afterwards that wavefront's in-wave exchange buffer, then
@@ -879,39 +880,46 @@ struct Split4 {
     return conv<CT>(cmuladd(d[0], conv<double>(self), c, conv<double>(other)));
   }
 
-  // Thread t0 of envelope E (0: psi~_+, 1: psi~_-).  Each step runs the
-  // sub-steps of Scheme<ORDER>.  A-sub-steps are the transform phases;
-  // the B sub-steps run in x after the inverse exchange, where the thread
-  // holds both envelopes.  For ORDER > 1 the first B sub-step of a step
+  // Thread t = E T0 + t0: in k space lane l of wavefront wv = t0 / 64 of
+  // envelope E (0: psi~_+, 1: psi~_-); in x space both envelopes at the
+  // samples x = t + T s, s < H = R/2.  With J = R/W sub-rows m_j = t0 + T0 j
+  // per envelope, the thread's x samples are the rows j = E + 2 jj, jj < J/2:
+  // x = m_j + M q is slot s = jj + (J/2) q.  Each step runs the sub-steps of
+  // Scheme<ORDER>: A sub-steps are the transform phases, B sub-steps run in x
+  // after the inverse exchange.  For ORDER > 1 the first B sub-step of a step
   // (no A before it) runs right after the last B sub-step of the previous
-  // step (both envelopes updated by the first, this envelope by the
-  // second), and before the first step on the input fields.
+  // step, and before the first step on the input fields.
   template <bool DEFORMED, int E, int ORDER, bool MASKED>
   BPM_INLINE static void run_env(const MarchParams& p, int slice, int t0, SV* lds) {
     using S = Scheme<ORDER>;
+    static_assert(J % 2 == 0, "the x-space rows split evenly between the envelopes");
+    constexpr int JH = J / 2;      // x-space rows per thread
+    constexpr int H = R / 2;       // x samples per thread
     const int wv = t0 >> 6, l = t0 & 63;
+    const int t = E * T0 + t0;
     const SliceConst& sc = p.sc[slice];
     const SV* table = static_cast<const SV*>(p.table);
-    SV* out = static_cast<SV*>(E ? p.Eh_out : p.E0_out) + size_t(slice) * N;
+    SV* out_a = static_cast<SV*>(p.E0_out) + size_t(slice) * N;
+    SV* out_b = static_cast<SV*>(p.Eh_out) + size_t(slice) * N;
     SV* Gp = reinterpret_cast<SV*>(reinterpret_cast<char*>(lds) + kGBytes);
     SV* own = region(lds, E * W + wv);
     IV* scratch = reinterpret_cast<IV*>(own);
 
     typename In::Ctx ic;
     In::init(ic, l);
-    Tw<CT> twx[J * (W - 1)];
+    // W_N^{m_j k1} of this thread's rows
+    Tw<CT> twx[JH * (W - 1)];
 #pragma unroll
-    for (int j = 0; j < J; ++j)
+    for (int jj = 0; jj < JH; ++jj)
 #pragma unroll
       for (int k1 = 1; k1 < W; ++k1) {
         double sn, cs;
-        sincospi(-2.0 * double((t0 + T0 * j) * k1) / double(N), &sn, &cs);
-        twx[j * (W - 1) + k1 - 1] = Tw<CT>::from(cs, sn);
+        sincospi(-2.0 * double((t0 + T0 * (E + 2 * jj)) * k1) / double(N), &sn, &cs);
+        twx[jj * (W - 1) + k1 - 1] = Tw<CT>::from(cs, sn);
       }
     // own band's propagators at the bins of (wavefront wv, lane l, slot i);
-    // slab mask of the x samples t0 + T0 i
+    // slab mask of the x samples t + T s
     cx<double> P[S::NP][R];
-    bool inside[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int k = wv + W * (l + 64 * i);
@@ -920,43 +928,53 @@ struct Split4 {
       for (int q = 0; q < S::NP; ++q)
         P[q][i] = propagator(ks, N, p.dx, sc.k, p.h_half, E ? -1.0 : 1.0, p.dz,
                              p.a_frac[S::pdef(q)]);
-      const double x = static_cast<double>(t0 + T0 * i - N / 2) * p.dx;
-      inside[i] = (x >= p.x_front) && (x < p.x_end);
+    }
+    bool inside[H];
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+      const double x = static_cast<double>(t + T * s - N / 2) * p.dx;
+      inside[s] = (x >= p.x_front) && (x < p.x_end);
     }
 
     // coupling constants d0, d+1, d-1 of every B sub-step
     cx<double> d[S::NS][3];
 #pragma unroll
-    for (int s = 0; s < S::NS; ++s)
+    for (int q = 0; q < S::NS; ++q)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) d[s][c] = {sc.d[s][2 * c], sc.d[s][2 * c + 1]};
+      for (int c = 0; c < 3; ++c) d[q][c] = {sc.d[q][2 * c], sc.d[q][2 * c + 1]};
 
     const SV* in_a = static_cast<const SV*>(p.E0_in) + size_t(slice) * N;
     const SV* in_b = p.Eh_in ? static_cast<const SV*>(p.Eh_in) + size_t(slice) * N
                              : nullptr;
-    const SV* src = E == 0 ? in_a : in_b;
-    cx<CT> v[R];
+    cx<CT> a[H], b[H];
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = src ? ld(src, t0 + T0 * i) : cx<CT>{CT(0), CT(0)};
+    for (int s = 0; s < H; ++s) {
+      a[s] = ld(in_a, t + T * s);
+      b[s] = in_b ? ld(in_b, t + T * s) : cx<CT>{CT(0), CT(0)};
+    }
+
+    // B sub-step with constants dq and deformation er at slot s, both envelopes
+    auto couple2 = [&](const cx<double> (&dq)[3], SV er_s, cx<CT>& as, cx<CT>& bs) {
+      const cx<CT> a0 = as;
+      as = couple<DEFORMED, 0>(dq, er_s, a0, bs);
+      bs = couple<DEFORMED, 1>(dq, er_s, bs, a0);
+    };
 
     // deformation rows: er of the current step (ORDER > 1: prefetched one
     // step ahead into er_next); crystal flags of the current and next step
-    SV er[R], er_next[R];
-    bool in_cur[R], in_next[R];
+    SV er[H], er_next[H];
+    bool in_cur[H], in_next[H];
     if constexpr (ORDER > 1 && DEFORMED) {
       const SV* row = table + size_t(p.n0) * N;
 #pragma unroll
-      for (int i = 0; i < R; ++i) er[i] = er_next[i] = row[t0 + T0 * i];
+      for (int s = 0; s < H; ++s) er[s] = er_next[s] = row[t + T * s];
     }
     if constexpr (ORDER > 1) {
-      crystal_row<R, N, MASKED>(p, p.n0, t0, T0, inside, in_cur);
       // first B sub-step of the first step, on the input fields
-      const SV* osrc = E == 0 ? in_b : in_a;
+      crystal_row<H, N, MASKED>(p, p.n0, t, T, inside, in_cur);
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const cx<CT> other = osrc ? ld(osrc, t0 + T0 * i) : cx<CT>{CT(0), CT(0)};
-        if (in_cur[i]) v[i] = couple<DEFORMED, E>(d[0], er[i], v[i], other);
-      }
+      for (int s = 0; s < H; ++s)
+        if (in_cur[s]) couple2(d[0], er[s], a[s], b[s]);
     }
 
     for (int n = 0; n < p.Nz; ++n) {
@@ -965,33 +983,43 @@ struct Split4 {
         if constexpr (DEFORMED) {
           const SV* row = table + size_t(p.n0 + n) * N;
 #pragma unroll
-          for (int i = 0; i < R; ++i) er[i] = row[t0 + T0 * i];
+          for (int s = 0; s < H; ++s) er[s] = row[t + T * s];
         }
-        crystal_row<R, N, MASKED>(p, p.n0 + n, t0, T0, inside, in_cur);
+        crystal_row<H, N, MASKED>(p, p.n0 + n, t, T, inside, in_cur);
       } else {
         if (n + 1 < p.Nz) {
           if constexpr (DEFORMED) {
             const SV* row = table + size_t(p.n0 + n + 1) * N;
 #pragma unroll
-            for (int i = 0; i < R; ++i) er_next[i] = row[t0 + T0 * i];
+            for (int s = 0; s < H; ++s) er_next[s] = row[t + T * s];
           }
-          crystal_row<R, N, MASKED>(p, p.n0 + n + 1, t0, T0, inside, in_next);
+          crystal_row<H, N, MASKED>(p, p.n0 + n + 1, t, T, inside, in_next);
         }
       }
 #pragma unroll
-      for (int s = 0; s < S::NS; ++s) {
-        if (S::has_a(s)) {
-          // forward: radix-W across this envelope's wavefronts, exchange
+      for (int sub = 0; sub < S::NS; ++sub) {
+        if (S::has_a(sub)) {
+          // forward: radix-W over q for both envelopes at this thread's rows,
+          // into the regions of the envelope's wavefronts
 #pragma unroll
-          for (int j = 0; j < J; ++j) {
-            cx<CT> u[W];
+          for (int jj = 0; jj < JH; ++jj) {
+            const int m = t0 + T0 * (E + 2 * jj);
+            cx<CT> ua[W], ub[W];
 #pragma unroll
-            for (int q = 0; q < W; ++q) u[q] = v[j + J * q];
-            dft<W, false>(u);
+            for (int q = 0; q < W; ++q) {
+              ua[q] = a[jj + JH * q];
+              ub[q] = b[jj + JH * q];
+            }
+            dft<W, false>(ua);
+            dft<W, false>(ub);
 #pragma unroll
             for (int k1 = 0; k1 < W; ++k1) {
-              if (k1 > 0) u[k1] = twx[j * (W - 1) + k1 - 1].mul(u[k1]);
-              st(region(lds, E * W + k1), t0 + T0 * j, u[k1]);
+              if (k1 > 0) {
+                ua[k1] = twx[jj * (W - 1) + k1 - 1].mul(ua[k1]);
+                ub[k1] = twx[jj * (W - 1) + k1 - 1].mul(ub[k1]);
+              }
+              st(region(lds, k1), m, ua[k1]);
+              st(region(lds, W + k1), m, ub[k1]);
             }
           }
           lds_barrier();
@@ -1002,59 +1030,54 @@ struct Split4 {
           In::template fft_n<false, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
 #pragma unroll
           for (int i = 0; i < R; ++i)
-            z[0][i] = conv<CT>(cmul(conv<double>(z[0][i]), P[S::pset(s)][i]));
+            z[0][i] = conv<CT>(cmul(conv<double>(z[0][i]), P[S::pset(sub)][i]));
           In::template fft_n<true, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
 #pragma unroll
           for (int i = 0; i < R; ++i) st(Gp + (E * W + wv) * M, l + 64 * i, z[0][i]);
           lds_barrier();
-          // inverse radix-W for both envelopes at this thread's x samples, and
-          // the coupling of each group of W samples right away
-          const bool chain = ORDER > 1 && s == S::NS - 1 && n + 1 < p.Nz;
+          // inverse radix-W of both envelopes at this thread's rows, and the
+          // coupling of each group of W samples right away
+          const bool chain = ORDER > 1 && sub == S::NS - 1 && n + 1 < p.Nz;
 #pragma unroll
-          for (int j = 0; j < J; ++j) {
+          for (int jj = 0; jj < JH; ++jj) {
+            const int m = t0 + T0 * (E + 2 * jj);
             cx<CT> ua[W], ub[W];
 #pragma unroll
             for (int k1 = 0; k1 < W; ++k1) {
-              ua[k1] = ld(Gp + k1 * M, t0 + T0 * j);
-              ub[k1] = ld(Gp + (W + k1) * M, t0 + T0 * j);
+              ua[k1] = ld(Gp + k1 * M, m);
+              ub[k1] = ld(Gp + (W + k1) * M, m);
               if (k1 > 0) {
-                ua[k1] = twx[j * (W - 1) + k1 - 1].mulc(ua[k1]);
-                ub[k1] = twx[j * (W - 1) + k1 - 1].mulc(ub[k1]);
+                ua[k1] = twx[jj * (W - 1) + k1 - 1].mulc(ua[k1]);
+                ub[k1] = twx[jj * (W - 1) + k1 - 1].mulc(ub[k1]);
               }
             }
             dft<W, true>(ua);
             dft<W, true>(ub);
 #pragma unroll
             for (int q = 0; q < W; ++q) {
-              const int i = j + J * q;
-              const cx<CT> self = E ? ub[q] : ua[q];
-              const cx<CT> other = E ? ua[q] : ub[q];
-              if (ORDER > 1 && chain) {
-                // last B of step n (both envelopes, as each envelope's own
-                // thread computes it), then the first B of step n+1
-                cx<CT> s1 = self, o1 = other;
-                if (in_cur[i]) {
-                  s1 = couple<DEFORMED, E>(d[s], er[i], self, other);
-                  o1 = couple<DEFORMED, 1 - E>(d[s], er[i], other, self);
-                }
-                v[i] = in_next[i] ? couple<DEFORMED, E>(d[0], er_next[i], s1, o1) : s1;
-              } else {
-                v[i] = in_cur[i] ? couple<DEFORMED, E>(d[s], er[i], self, other) : self;
-              }
+              const int s = jj + JH * q;
+              a[s] = ua[q];
+              b[s] = ub[q];
+              if (in_cur[s]) couple2(d[sub], er[s], a[s], b[s]);
+              // the first B sub-step of step n+1 right after the last of step n
+              if (ORDER > 1 && chain && in_next[s]) couple2(d[0], er_next[s], a[s], b[s]);
             }
           }
         }
       }
       if constexpr (ORDER > 1) {
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          if constexpr (DEFORMED) er[i] = er_next[i];
-          in_cur[i] = in_next[i];
+        for (int s = 0; s < H; ++s) {
+          if constexpr (DEFORMED) er[s] = er_next[s];
+          in_cur[s] = in_next[s];
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < R; ++i) st(out, t0 + T0 * i, v[i]);
+    for (int s = 0; s < H; ++s) {
+      st(out_a, t + T * s, a[s]);
+      st(out_b, t + T * s, b[s]);
+    }
   }
 };
 
