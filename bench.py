@@ -46,10 +46,9 @@ def flops_per_cell_update(Nx: int) -> float:
 def lds_bytes_per_cell_update(Nx: int, storage_bytes: int) -> float:
     """LDS bytes per cell-update of the default (envelope-split four-step)
     schedule at Nx = 1024/2048: per envelope and z-step, two work-group
-    exchanges (each sample written and read once; the inverse exchange is
-    read by both envelopes' threads) and four wavefront-local Stockham
-    exchanges of the 512-point inner transform."""
-    accesses = 2 + 4 + 4 + 3   # fwd exchange, 2x2 local fwd, 2x2 local inv, inv exchange
+    exchanges and four wavefront-local Stockham exchanges of the 512-point
+    inner transform, each sample written and read once per exchange."""
+    accesses = 2 + 4 + 4 + 2   # fwd exchange, 2x2 local fwd, 2x2 local inv, inv exchange
     return 2 * accesses * storage_bytes
 
 
