@@ -68,10 +68,11 @@ enum {
  * STOCKHAM -- radix-R Stockham passes, one work-group barrier per pass;
  * FOURSTEP -- radix-W across the W wavefronts of a slice plus a Stockham
  * transform inside each wavefront, two barriers per z-step;
- * SPLIT -- the two envelopes on separate wavefronts: for Nx = 256 and 512
- * one wavefront per envelope (no forward exchange, one barrier per step),
- * for Nx = 1024 and 2048 FOURSTEP split by envelope (twice the wavefronts,
- * half the registers each), FOURSTEP at Nx = 4096;
+ * SPLIT -- the two envelopes on separate wavefronts: for Nx = 256 one
+ * wavefront per envelope (no forward exchange, one barrier per step), for
+ * Nx = 512, 1024 and 2048 FOURSTEP split by envelope in k space (twice the
+ * wavefronts, half the registers each) with the x samples shared by all
+ * threads, FOURSTEP at Nx = 4096;
  * AUTO -- the library's measured default for (precision, Nx) (currently
  * SPLIT at every size). */
 enum { BPM_SCHED_AUTO = -1, BPM_SCHED_STOCKHAM = 0, BPM_SCHED_FOURSTEP = 1,

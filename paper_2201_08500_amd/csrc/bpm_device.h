@@ -1530,7 +1530,7 @@ template <int PREC> struct Choice<PREC, 4096, 1> {
 };
 // 2 -- envelope-split four-step (2W wavefronts) where it fits, else four-step
 template <int PREC> struct Choice<PREC, 256, 2> { using type = Split1<PREC, InWave256<PREC>>; };
-template <int PREC> struct Choice<PREC, 512, 2> { using type = Split1<PREC, InWave512<PREC>>; };
+template <int PREC> struct Choice<PREC, 512, 2> { using type = Split4<PREC, 2, InWave256<PREC>>; };
 template <int PREC> struct Choice<PREC, 1024, 2> { using type = Split4<PREC, 2, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 2048, 2> { using type = Split4<PREC, 4, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 4096, 2> { using type = typename Choice<PREC, 4096, 1>::type; };
