@@ -114,9 +114,10 @@ def test_batch_with_mixed_orders_equals_alone():
 
 @pytest.mark.parametrize("Nx", [256, 512])
 @pytest.mark.parametrize("order", [1, 2, 4])
-def test_one_wave_per_envelope_split(Nx, order):
-    """The one-wavefront-per-envelope split march (Nx 256, 512): parity for
-    every precision and a general mask, and bitwise segment chaining."""
+def test_split_schedule_small_sizes(Nx, order):
+    """The split schedule at Nx 256 (one wavefront per envelope) and 512
+    (two wavefronts per envelope, 256-point in-wavefront transform): parity
+    for every precision and a general mask, and bitwise segment chaining."""
     from paper_2201_08500_amd import Plan
     w = W.small(Nx=Nx, Nz=19, Nomega=3, seed=120 + Nx // 256)
     for prec in ("fp64", "fp32s", "fp32"):
