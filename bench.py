@@ -446,6 +446,10 @@ def bench_serve(args):
                    "precisions": sorted(set(prec_map.values())),
                    "budget_GB": args.serve_budget_gb, "streams": args.serve_streams},
         "serve": dict(st, requests=len(trace), submit_lag_s=lag,
+                      materialize_parts_s=backend.timing,
+                      allocator={k: torch.cuda.memory_stats().get(k) for k in (
+                          "num_alloc_retries", "num_device_alloc", "num_device_free",
+                          "num_sync_all_streams")},
                       offered_cell_updates_per_s=sum(
                           s["Nx"] * s["Nz"] * s["Nomega"] for _, s, _ in trace)
                       / args.serve_duration),

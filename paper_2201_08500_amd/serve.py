@@ -91,6 +91,13 @@ class Server:
         self.retries = 0
         self.peak_used = 0.0
         self.broken = None                   # sticky device error, if any
+        # where the scheduler's time goes (host seconds) and what held back
+        # admission (scheduler passes with requests waiting)
+        self.host_materialize_s = 0.0
+        self.host_launch_s = 0.0
+        self.held_by_slots = 0
+        self.held_by_budget = 0
+        self.launch_log = []                 # (launched, finished, requests)
 
     # ---------------------------------------------------------------- API --
     def now(self) -> float:
@@ -163,13 +170,26 @@ class Server:
             return lat[k]
         span = (max(r.finished for r in done) - min(r.arrival for r in done)) if done else math.nan
         cells = sum(r.cell_updates for r in done)
+        # time with at least one launch in flight, and mean launches in flight
+        busy, area, end = 0.0, 0.0, -math.inf
+        for t0, t1, _ in sorted(self.launch_log):
+            area += t1 - t0
+            if t1 > end:
+                busy += t1 - max(t0, end)
+                end = t1
         return dict(completed=len(done), failed=len(self.failed),
                     launches=self.launches, retries=self.retries,
                     p50_s=pct(50), p99_s=pct(99),
                     max_s=lat[-1] if lat else math.nan,
                     cell_updates=cells, span_s=span,
                     cell_updates_per_s=(cells / span) if done and span > 0 else math.nan,
-                    peak_budget_used=self.peak_used)
+                    peak_budget_used=self.peak_used,
+                    in_flight_time_s=busy,
+                    mean_launches_in_flight=(area / busy) if busy > 0 else math.nan,
+                    host_materialize_s=self.host_materialize_s,
+                    host_launch_s=self.host_launch_s,
+                    held_by_slots=self.held_by_slots,
+                    held_by_budget=self.held_by_budget)
 
     # ---------------------------------------------------------- scheduler --
     def _run(self):
@@ -215,6 +235,8 @@ class Server:
                 continue
             done_any = True
             t = self.now()
+            if reqs:
+                self.launch_log.append((reqs[0].launched, t, len(reqs)))
             for r in reqs:
                 r.finished = t
                 self.backend.release(r)
@@ -239,7 +261,10 @@ class Server:
         with self._lock:
             while self._incoming:
                 self._pending.append(self._incoming.popleft())
-            if len(self._in_flight) >= self.max_in_flight or not self._pending:
+            if not self._pending:
+                return False
+            if len(self._in_flight) >= self.max_in_flight:
+                self.held_by_slots += 1
                 return False
             batch = []
             while (self._pending and len(batch) < self.max_batch
@@ -250,12 +275,18 @@ class Server:
                 self.peak_used = max(self.peak_used, self._used)
                 r.admitted = self.now()
                 batch.append(r)
+            if not batch:
+                self.held_by_budget += 1
         if not batch:
             return False
         ok = []
         for k, r in enumerate(batch):
             try:
-                self.backend.materialize(r)
+                t_m = time.perf_counter()
+                try:
+                    self.backend.materialize(r)
+                finally:
+                    self.host_materialize_s += time.perf_counter() - t_m
                 ok.append(r)
             except Retry as e:
                 if not self._in_flight and not ok:
@@ -276,12 +307,15 @@ class Server:
                 self._fail_now(r, e)
         if not ok:
             return True
+        t_l = time.perf_counter()
         try:
             handle = self.backend.launch(ok)
         except Exception as e:              # noqa: BLE001
             for r in ok:
                 self._fail_now(r, e)
             return True
+        finally:
+            self.host_launch_s += time.perf_counter() - t_l
         t = self.now()
         for r in ok:
             r.launched = t
@@ -326,6 +360,7 @@ class GpuBackend:
                 max(0.05, 1.0 - float(headroom_bytes) / total), self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self._k = 0
+        self.timing = {"plan_s": 0.0, "fields_s": 0.0, "u_s": 0.0, "job_s": 0.0}
 
     @staticmethod
     def _cell(prec):
@@ -352,13 +387,17 @@ class GpuBackend:
         torch = self.torch
         w = req.spec
         s = self.streams[self._k % len(self.streams)]
+        tm = self.timing
         try:
             with torch.cuda.stream(s):
+                t0 = time.perf_counter()
                 plan = Plan.from_workload(w, precision=req.precision)
+                t1 = time.perf_counter()
                 host_dtype = np.complex128 if plan.field_dtype == torch.complex128 \
                     else np.complex64
                 E0 = torch.from_numpy(np.ascontiguousarray(
                     w.E0_in, dtype=host_dtype)).to(self.device)
+                t2 = time.perf_counter()
                 u = None
                 if w.u is not None:
                     u = torch.from_numpy(w.u).to(self.device)
@@ -367,7 +406,13 @@ class GpuBackend:
                     gzs = torch.from_numpy(amp * gz).to(self.device)
                     u = torch.outer(gzs, torch.from_numpy(gx).to(self.device))
                     u.add_(torch.from_numpy(row).to(self.device))
+                t3 = time.perf_counter()
                 req.device = Job(plan, E0, u)
+                t4 = time.perf_counter()
+                tm["plan_s"] += t1 - t0
+                tm["fields_s"] += t2 - t1
+                tm["u_s"] += t3 - t2
+                tm["job_s"] += t4 - t3
         except torch.OutOfMemoryError as e:
             req.device = None
             raise Retry(str(e)) from e
