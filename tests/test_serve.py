@@ -248,3 +248,26 @@ def test_device_fault_fails_everything_and_drain_returns():
             srv.submit(req("c", 1)).result(timeout=5)
     finally:
         srv.stop()
+
+
+def test_scheduler_accounting():
+    """stats() reports the time with launches in flight, their mean count,
+    the host time per phase and why admission waited: two requests that
+    each fill the budget run one after the other, so one launch is in flight
+    at a time and the second request is held by the budget."""
+    be = FakeBackend()
+    srv = Server(be, budget_bytes=100, max_in_flight=4).start()
+    try:
+        r1 = srv.submit(req("a", 100, dur=0.05))
+        r2 = srv.submit(req("b", 100, dur=0.05))
+        assert srv.drain(timeout=5)
+        r1.result(timeout=1)
+        r2.result(timeout=1)
+    finally:
+        srv.stop()
+    st = srv.stats()
+    assert st["launches"] == 2
+    assert st["held_by_budget"] > 0 and st["held_by_slots"] == 0
+    assert 0.09 <= st["in_flight_time_s"] <= st["span_s"] + 1e-9
+    assert st["mean_launches_in_flight"] == pytest.approx(1.0, abs=0.05)
+    assert st["host_materialize_s"] >= 0.0 and st["host_launch_s"] >= 0.0
