@@ -13,6 +13,9 @@ ARCH = "gfx950"
 # Packed FP32 instructions are switched off for every device compile.
 DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Kernel units named *_ilp.hip hold the transform lengths for which the
+# instruction-level-parallelism machine scheduler measured faster.
+ILP_FLAGS = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
 
 
 def _hipcc() -> str:
@@ -44,7 +47,8 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     for src in sorted(os.listdir(CSRC)):
         if src.endswith(".hip"):
             obj = os.path.join(objdir, src[:-4] + ".o")
-            jobs.append([hipcc, *DEVICE_FLAGS, *extra_flags, "-c",
+            unit_flags = ILP_FLAGS if src.endswith("_ilp.hip") else []
+            jobs.append([hipcc, *DEVICE_FLAGS, *unit_flags, *extra_flags, "-c",
                          os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
     workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))

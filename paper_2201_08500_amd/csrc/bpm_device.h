@@ -1545,17 +1545,6 @@ int with_sched(int sched, F&& f) {
     default: return BPM_EUNSUPPORTED;
   }
 }
-template <int PREC, class F>
-int with_n(int Nx, int sched, F&& f) {
-  switch (Nx) {
-    case 256: return with_sched<PREC, 256>(sched, f);
-    case 512: return with_sched<PREC, 512>(sched, f);
-    case 1024: return with_sched<PREC, 1024>(sched, f);
-    case 2048: return with_sched<PREC, 2048>(sched, f);
-    case 4096: return with_sched<PREC, 4096>(sched, f);
-    default: return BPM_EUNSUPPORTED;
-  }
-}
 template <class F>
 int with_order(int order, F&& f) {
   switch (order) {
@@ -1568,10 +1557,13 @@ int with_order(int order, F&& f) {
 
 }  // namespace
 
-template <int PREC, bool MASKED>
-int launch_march_p(int Nx, int sched, int order, int Nomega, const MarchParams& p,
+// Entry points of one transform length N.  Each N is instantiated in one
+// kernel unit (see BPM_MARCH_N), so units can be compiled with different
+// scheduling options.
+template <int PREC, bool MASKED, int N>
+int launch_march_n(int sched, int order, int Nomega, const MarchParams& p,
                    hipStream_t stream) {
-  return with_n<PREC>(Nx, sched, [&](auto m) {
+  return with_sched<PREC, N>(sched, [&](auto m) {
     using M = decltype(m);
     return with_order(order, [&](auto o) {
       constexpr int ORDER = decltype(o)::value;
@@ -1586,10 +1578,10 @@ int launch_march_p(int Nx, int sched, int order, int Nomega, const MarchParams& 
   });
 }
 
-template <int PREC, bool MASKED>
-int launch_march_batch_p(int Nx, int sched, int order, const BatchItem* items,
+template <int PREC, bool MASKED, int N>
+int launch_march_batch_n(int sched, int order, const BatchItem* items,
                          const int* offsets, int n_groups, hipStream_t stream) {
-  return with_n<PREC>(Nx, sched, [&](auto m) {
+  return with_sched<PREC, N>(sched, [&](auto m) {
     using M = decltype(m);
     return with_order(order, [&](auto o) {
       constexpr int ORDER = decltype(o)::value;
@@ -1598,6 +1590,59 @@ int launch_march_batch_p(int Nx, int sched, int order, const BatchItem* items,
       return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
     });
   });
+}
+
+template <int PREC, bool MASKED, int N>
+int march_occupancy_n(int sched, int order, int* wg_per_cu, int* threads) {
+  return with_sched<PREC, N>(sched, [&](auto m) {
+    using M = decltype(m);
+    return with_order(order, [&](auto o) {
+      constexpr int ORDER = decltype(o)::value;
+      int n = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &n, reinterpret_cast<const void*>(&march_batch_kernel<M, ORDER, MASKED>), M::T,
+              0) != hipSuccess)
+        return BPM_EHIP;
+      *wg_per_cu = n;
+      *threads = M::T;
+      return BPM_OK;
+    });
+  });
+}
+
+// Declares (KW = extern) or instantiates (KW empty) the entry points of
+// transform length N for one precision and crystal kind.
+#define BPM_MARCH_N(KW, P, MASKED, N)                                              \
+  KW template int launch_march_n<P, MASKED, N>(int, int, int, const MarchParams&,  \
+                                               hipStream_t);                      \
+  KW template int launch_march_batch_n<P, MASKED, N>(int, int, const BatchItem*,   \
+                                                     const int*, int, hipStream_t); \
+  KW template int march_occupancy_n<P, MASKED, N>(int, int, int*, int*);
+
+template <int PREC, bool MASKED>
+int launch_march_p(int Nx, int sched, int order, int Nomega, const MarchParams& p,
+                   hipStream_t stream) {
+  switch (Nx) {
+    case 256: return launch_march_n<PREC, MASKED, 256>(sched, order, Nomega, p, stream);
+    case 512: return launch_march_n<PREC, MASKED, 512>(sched, order, Nomega, p, stream);
+    case 1024: return launch_march_n<PREC, MASKED, 1024>(sched, order, Nomega, p, stream);
+    case 2048: return launch_march_n<PREC, MASKED, 2048>(sched, order, Nomega, p, stream);
+    case 4096: return launch_march_n<PREC, MASKED, 4096>(sched, order, Nomega, p, stream);
+    default: return BPM_EUNSUPPORTED;
+  }
+}
+
+template <int PREC, bool MASKED>
+int launch_march_batch_p(int Nx, int sched, int order, const BatchItem* items,
+                         const int* offsets, int n_groups, hipStream_t stream) {
+  switch (Nx) {
+    case 256: return launch_march_batch_n<PREC, MASKED, 256>(sched, order, items, offsets, n_groups, stream);
+    case 512: return launch_march_batch_n<PREC, MASKED, 512>(sched, order, items, offsets, n_groups, stream);
+    case 1024: return launch_march_batch_n<PREC, MASKED, 1024>(sched, order, items, offsets, n_groups, stream);
+    case 2048: return launch_march_batch_n<PREC, MASKED, 2048>(sched, order, items, offsets, n_groups, stream);
+    case 4096: return launch_march_batch_n<PREC, MASKED, 4096>(sched, order, items, offsets, n_groups, stream);
+    default: return BPM_EUNSUPPORTED;
+  }
 }
 
 // Pulse transform of [N][Nx] fields: FP64 butterflies for every
@@ -1630,20 +1675,14 @@ int launch_pulse_p(int N, int Nx, bool to_freq, double dt, const void* in, void*
 
 template <int PREC, bool MASKED>
 int march_occupancy_p(int Nx, int sched, int order, int* wg_per_cu, int* threads) {
-  return with_n<PREC>(Nx, sched, [&](auto m) {
-    using M = decltype(m);
-    return with_order(order, [&](auto o) {
-      constexpr int ORDER = decltype(o)::value;
-      int n = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &n, reinterpret_cast<const void*>(&march_batch_kernel<M, ORDER, MASKED>), M::T,
-              0) != hipSuccess)
-        return BPM_EHIP;
-      *wg_per_cu = n;
-      *threads = M::T;
-      return BPM_OK;
-    });
-  });
+  switch (Nx) {
+    case 256: return march_occupancy_n<PREC, MASKED, 256>(sched, order, wg_per_cu, threads);
+    case 512: return march_occupancy_n<PREC, MASKED, 512>(sched, order, wg_per_cu, threads);
+    case 1024: return march_occupancy_n<PREC, MASKED, 1024>(sched, order, wg_per_cu, threads);
+    case 2048: return march_occupancy_n<PREC, MASKED, 2048>(sched, order, wg_per_cu, threads);
+    case 4096: return march_occupancy_n<PREC, MASKED, 4096>(sched, order, wg_per_cu, threads);
+    default: return BPM_EUNSUPPORTED;
+  }
 }
 
 }  // namespace bpm
