@@ -29,10 +29,14 @@
  * The caller owns all field buffers; the plan owns only its constants.
  *
  * Errors: functions return BPM_OK (0) or a negative code and never abort;
- * bpm_last_error() gives a message for the calling thread.  Calls are
+ * bpm_last_error() gives a message for the calling thread.  Launches are
  * asynchronous on the given stream (a hipStream_t passed as void*, NULL for
- * the default stream) and never synchronise; buffers must stay alive until
- * the stream has completed the work.
+ * the default stream); buffers must stay alive until the stream has
+ * completed the work.  Three calls block the host: the first call that uses
+ * a plan uploads its constants (hipMalloc and a blocking copy),
+ * bpm_batch_create uploads its work lists, and bpm_plan_destroy /
+ * bpm_batch_destroy free device memory with hipFree, which waits for the
+ * device to finish its outstanding work.
  */
 #ifndef BPM_H
 #define BPM_H
@@ -198,6 +202,7 @@ int bpm_batch_launch(const bpm_batch* batch, void* stream);
 int bpm_batch_info(const bpm_batch* batch, int* n_launches, int* n_slices,
                    int* n_workgroups);
 
+/* Free a prepared batch (hipFree: waits for the device).  NULL is ignored. */
 void bpm_batch_destroy(bpm_batch* batch);
 
 /* One-shot batch: create (work lists allocated stream-ordered), launch and
@@ -234,6 +239,8 @@ int bpm_march_segment(const bpm_plan* plan, const void* E0_in,
                       const void* Eh_in, const void* table, int n0, int nsteps,
                       void* E0_out, void* Eh_out, void* stream);
 
+/* Free a plan and its device constants (hipFree: waits for the device, so
+ * work launched with the plan has completed first).  NULL is ignored. */
 void bpm_plan_destroy(bpm_plan* plan);
 
 /* Message for the last error on the calling thread ("" if none). */
