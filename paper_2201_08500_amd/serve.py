@@ -158,6 +158,8 @@ class Server:
         self._stop.set()
         if self._thread is not None:
             self._thread.join()
+        if hasattr(self.backend, "idle"):
+            self.backend.idle()
 
     def stats(self) -> dict:
         done = [r for r in self.completed if r.state == "done"]
@@ -252,6 +254,8 @@ class Server:
                     self._used -= r.footprint
                     self._active -= 1
         self._in_flight = still
+        if done_any and not still and hasattr(self.backend, "idle"):
+            self.backend.idle()              # nothing runs: deferred cleanup
         return done_any
 
     def _admit_and_launch(self) -> bool:
@@ -360,6 +364,8 @@ class GpuBackend:
                 max(0.05, 1.0 - float(headroom_bytes) / total), self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self._k = 0
+        self._retired = []                   # plans of finished requests
+        self.max_retired = 100000            # ~20 KB of device constants each
         self.timing = {"plan_s": 0.0, "fields_s": 0.0, "u_s": 0.0, "job_s": 0.0}
 
     @staticmethod
@@ -433,8 +439,18 @@ class GpuBackend:
 
     def release(self, req):
         # inputs and workspace go back to the caching allocator; the outputs
-        # stay with the request (device-resident) unless keep_outputs is off
+        # stay with the request (device-resident) unless keep_outputs is off.
+        # The plan is retired, not destroyed: destroying it frees its device
+        # constants with hipFree, which waits for every launch on the device,
+        # so plans are destroyed together when nothing is in flight (idle()).
         j = req.device
         if j is not None:
             req.device = None
             req.outputs = (j.E0_out, j.Eh_out) if self.keep_outputs else None
+            self._retired.append(j.plan)
+            if len(self._retired) > self.max_retired:
+                self.idle()
+
+    def idle(self):
+        """Destroy the retired plans (called when no launch is in flight)."""
+        self._retired.clear()

@@ -271,3 +271,27 @@ def test_scheduler_accounting():
     assert 0.09 <= st["in_flight_time_s"] <= st["span_s"] + 1e-9
     assert st["mean_launches_in_flight"] == pytest.approx(1.0, abs=0.05)
     assert st["host_materialize_s"] >= 0.0 and st["host_launch_s"] >= 0.0
+
+
+def test_backend_idle_hook_runs_when_nothing_is_in_flight():
+    """A backend with idle() (deferred cleanup, e.g. destroying retired plans
+    without waiting for running launches) is called only when no launch is
+    in flight, and again at stop."""
+    class IdleBackend(FakeBackend):
+        def __init__(self):
+            super().__init__()
+            self.idle_live = []
+
+        def idle(self):
+            self.idle_live.append(self.live)
+
+    be = IdleBackend()
+    srv = Server(be, budget_bytes=100, max_in_flight=4).start()
+    try:
+        futs = [srv.submit(req(f"r{i}", 60, dur=0.02)) for i in range(3)]
+        assert srv.drain(timeout=5)
+        for f in futs:
+            f.result(timeout=1)
+    finally:
+        srv.stop()
+    assert len(be.idle_live) >= 2 and all(n == 0 for n in be.idle_live)
