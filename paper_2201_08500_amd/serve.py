@@ -349,7 +349,7 @@ class GpuBackend:
     host, `meta['u_factors'] = (row, gz, gx, amp)` describing
     u[n, j] = row[j] + (amp gz[n]) gx[j], or `u` as an array, or no u)."""
 
-    def __init__(self, streams: int = 4, device: int = 0, keep_outputs=True,
+    def __init__(self, streams: int = 2, device: int = 0, keep_outputs=True,
                  headroom_bytes: float = 0.0):
         """headroom_bytes > 0 caps torch's caching allocator at the device's
         memory minus that much, so the HIP runtime (queues, kernel scratch)
