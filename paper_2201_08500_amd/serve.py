@@ -365,7 +365,10 @@ class GpuBackend:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self._k = 0
         self._retired = []                   # plans of finished requests
-        self.max_retired = 100000            # ~20 KB of device constants each
+        # bound on retired plans (208 B of device constants per slice each,
+        # a few hundred MB at most) before they are destroyed even while
+        # launches run
+        self.max_retired = 20000
         self.timing = {"plan_s": 0.0, "fields_s": 0.0, "u_s": 0.0, "job_s": 0.0}
 
     @staticmethod
