@@ -351,7 +351,12 @@ class GpuBackend:
 
     def __init__(self, streams: int = 2, device: int = 0, keep_outputs=True,
                  headroom_bytes: float = 0.0):
-        """headroom_bytes > 0 caps torch's caching allocator at the device's
+        """streams: launch streams, one launch in flight on each.  Torch
+        caches freed blocks per stream, so each extra stream splits the
+        allocator's cache (with four, the split cache filled the memory cap
+        and each flush freed thousands of blocks); two measured best.
+
+        headroom_bytes > 0 caps torch's caching allocator at the device's
         memory minus that much, so the HIP runtime (queues, kernel scratch)
         can always allocate while the allocator holds cached blocks."""
         import torch
