@@ -177,11 +177,10 @@ def bench_batch(args):
     import torch
     import workloads as W
     from paper_2201_08500_amd import Batch, Job, Plan
-    from workloads.metrics import report
 
     torch.cuda.set_device(0)
     specs = W.c4_problem_specs(args.batch_problems, seed=4)
-    jobs, works = [], []
+    jobs = []
     cells = 0
     for s in specs:
         w = W.c4_problem(s, with_u=False)
@@ -192,7 +191,6 @@ def bench_batch(args):
         u = torch.outer(torch.from_numpy(amp * gz).cuda(), torch.from_numpy(gx).cuda())
         u.add_(torch.from_numpy(row).cuda())
         jobs.append(Job(p, E0, u))
-        works.append(w)
         cells += w.cell_updates
     print(f"[bench] batch: {len(jobs)} problems, {cells:.3e} cell-updates",
           file=sys.stderr, flush=True)
@@ -232,15 +230,6 @@ def bench_batch(args):
         same = all(torch.equal(oa, j.E0_out) and torch.equal(ob, j.Eh_out)
                    for j, (oa, ob) in zip(jobs, outs))
         del outs
-    # oracle spot check: two slices of the smallest problem
-    import oracle as O
-    i = min(range(len(works)), key=lambda k: works[k].Nx * works[k].Nz)
-    wsub = W.c4_problem(specs[i]).subset(sorted({0, works[i].Nomega // 2}))
-    sl = sorted({0, works[i].Nomega // 2})
-    E32 = wsub.E0_in.astype(np.complex64).astype(np.complex128)
-    ao, bo = O.march(O.Problem.from_workload(wsub), E32, wsub.u)
-    rep = report(jobs[i].E0_out.cpu().numpy()[sl].astype(np.complex128),
-                 jobs[i].Eh_out.cpu().numpy()[sl].astype(np.complex128), ao, bo)
     t = float(np.median(times))
     line = {
         "metric": METRIC, "value": cells / t, "unit": "cell-updates/s",
@@ -256,8 +245,7 @@ def bench_batch(args):
                       replay_s=[float(x) for x in times],
                       sequential_s=seq,
                       sequential_cell_updates_per_s=(cells / seq) if seq else None,
-                      sequential_bitwise_equal=(same if seq else None),
-                      oracle_spot_check=dict(problem=works[i].name, slices=sl, **rep)),
+                      sequential_bitwise_equal=(same if seq else None)),
     }
     print(json.dumps(line))
 
@@ -465,10 +453,6 @@ def main():
     ap.add_argument("--headline", default="fp32s",
                     choices=["fp32s", "fp32", "fp64"])
     ap.add_argument("--variants", default="fp32s,fp32,fp64")
-    ap.add_argument("--oracle-slices", default=None,
-                    help="slices recomputed by the oracle for the error report "
-                         "(default 120,128,136 for the bent crystal, 511,640 "
-                         "for the thermal bump)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices-per-core", type=int, default=96)
     ap.add_argument("--workload", default="bent-crystal",
@@ -517,12 +501,8 @@ def main():
     if args.workload == "thermal-bump":
         # 4096 x 8192 x 1024: the largest configuration, a precision check
         w = W.c3_thermal_bump()
-        default_slices = "511,640"
     else:
         w = W.c2_bent_crystal()
-        default_slices = "120,128,136"
-    if args.oracle_slices is None:
-        args.oracle_slices = default_slices
     u_t = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
     cells = w.cell_updates
     variants = [v for v in args.variants.split(",") if v]
@@ -546,29 +526,14 @@ def main():
               file=sys.stderr, flush=True)
         results[prec] = run_variant(w, prec, args.steps, args.warmup, w.E0_in, u_t)
 
-    # precision report: every variant against the FP64 GPU run (all slices)
-    # and against the oracle on a few slices
-    sl = [int(s) for s in args.oracle_slices.split(",") if s]
-    ref = ref32 = None
-    if sl:
-        import oracle as O
-        ws = w.subset(sl)
-        ref = O.march(O.Problem.from_workload(ws), ws.E0_in, ws.u)
+    # precision report: every variant against the FP64 GPU run on all slices
+    # (parity with the oracle is established by the GPU tests)
     prec_report = {}
     for prec, r in results.items():
         a, b = r["out"]
         entry = {}
-        if prec == "fp64":
-            if sl:
-                entry["vs_oracle"] = report(a[sl], b[sl], *ref)
-        else:
-            if sl and ref32 is None:
-                E32 = ws.E0_in.astype(np.complex64).astype(np.complex128)
-                ref32 = O.march(O.Problem.from_workload(ws), E32, ws.u)
-            if sl:
-                entry["vs_oracle"] = report(a[sl], b[sl], *ref32)
-            if "fp64" in results:
-                entry["vs_fp64_gpu_all_slices"] = report(a, b, *results["fp64"]["out"])
+        if prec != "fp64" and "fp64" in results:
+            entry["vs_fp64_gpu_all_slices"] = report(a, b, *results["fp64"]["out"])
         march_s = r["march_ms"] / 1e3
         entry.update(cell_updates_per_s=cells * args.steps / r["total_s"],
                      march_ms=r["march_ms"], deform_ms=r["deform_ms"],
