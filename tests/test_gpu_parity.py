@@ -144,6 +144,12 @@ def test_thermal_bump_full_size_sampled():
     r32 = report(a32[sl], b32[sl], ao, bo)
     print(f"{w.name} fp32s vs oracle slices {sl}: {r32}", flush=True)
     assert r32["rel_l2"] <= 1e-5, r32
+    # FP32 butterflies: reported, bounded (their error grows as sqrt(Nz) and
+    # exceeds 1e-5 at this Nz; fp32s is the mode that meets it)
+    af, bf = gpu_run(w, "fp32", sl)
+    rf = report(af, bf, ao, bo)
+    print(f"{w.name} fp32 vs oracle slices {sl}: {rf}", flush=True)
+    assert rf["rel_l2"] <= 1e-3, rf
 
 
 def test_determinism_and_slice_independence():
