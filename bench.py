@@ -1,19 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the FFT beam-propagation z-march on one MI355X.
 
-Workload: the time-dependent bent crystal -- Nx = 2048 transverse points,
-Nz = 4000 steps of 0.5 um, Nomega = 256 frequency slices of a 10 fs pulse,
-u = x^2 / (2R), R = 10 m (seeded synthetic inputs, workloads.c2_bent_crystal).
-One benchmark step is one pass of the whole hot path: the deformation
-pre-pass (exp(i h u) table) plus the march of all slices, inputs resident in
-HBM.  Metric: cell-updates/s = Nx * Nz * Nomega / step time.
+Default workload: the time-dependent crystal with a thermal bump, the
+largest configuration -- Nx = 4096 transverse points, Nz = 8192 steps of
+0.5 um, Nomega = 1024 frequency slices of a 10 fs pulse, u = Gaussian bump
+(1e-10 m, sigma 100 um) plus seeded white-noise strain of rms 1e-7 (seeded
+synthetic inputs, workloads.c3_thermal_bump).  One benchmark step is one
+pass of the whole hot path: the deformation pre-pass (exp(i h u) table) plus
+the march of all slices, inputs resident in HBM.  Metric: cell-updates/s =
+Nx * Nz * Nomega / step time, for the FP32-storage/FP64-arithmetic headline
+mode, with the FP32-butterfly and FP64 modes and their errors against the
+FP64 GPU run beside it.
 
---workload thermal-bump runs the same measurement on the 4096 x 8192 x 1024
-thermal-bump configuration; batch, serve and extensions time the batched
-launch, the served request stream and the march's extensions.
+The same JSON line carries the served request stream (Poisson arrivals,
+mixed sizes, half fp64 requests): p50/p99 latency and cell-updates/s, and the
+same trace served all in fp64.
 
-Prints one JSON line.  The oracle (CPU, FP64 numpy) is timed on a bounded
-sample of slices on the host's cores as a reported baseline.
+--workload bent-crystal runs the march measurement on the 2048 x 4000 x 256
+bent crystal; batch, serve and extensions time the batched launch, the
+served request stream alone and the march's extensions.
+
+The oracle (CPU, FP64 numpy) is timed on a bounded sample of slices on the
+host's cores as a reported baseline.
 """
 
 from __future__ import annotations
@@ -37,17 +45,20 @@ HBM_PEAK_GBS = 8000.0
 
 def flops_per_cell_update(Nx: int) -> float:
     """Algorithmic flops of one (x, z-step, slice) update: four complex FFTs
-    (two envelopes, forward and inverse) at 5 N log2 N each, two complex
-    propagator multiplies (6 each) and the deformed coupling (six complex
-    multiplies and two complex adds)."""
-    return 4 * 5 * math.log2(Nx) + 2 * 6 + (6 * 6 + 2 * 2)
+    (two envelopes, forward and inverse) at 5 N log2 N each, 2 x 6 for the
+    two propagator multiplies and 28 for the 2 x 2 coupling: 20 log2 Nx + 40
+    (240, 260, 280 at Nx = 1024, 2048, 4096).  The deformation phase factors
+    of the deformed coupling (two more complex multiplies, 12 flops) are
+    not counted."""
+    return 4 * 5 * math.log2(Nx) + 2 * 6 + 28
 
 
 def lds_bytes_per_cell_update(Nx: int, storage_bytes: int) -> float:
-    """LDS bytes per cell-update of the default (envelope-split four-step)
-    schedule at Nx = 1024/2048: per envelope and z-step, two work-group
-    exchanges and four wavefront-local Stockham exchanges of the 512-point
-    inner transform, each sample written and read once per exchange."""
+    """LDS bytes per cell-update of the default schedule at Nx = 1024, 2048
+    and 4096 (envelope-split four-step, four-step): per envelope and z-step,
+    two work-group exchanges and four wavefront-local Stockham exchanges of
+    the 512-point inner transform, each sample written and read once per
+    exchange."""
     accesses = 2 + 4 + 4 + 2   # fwd exchange, 2x2 local fwd, 2x2 local inv, inv exchange
     return 2 * accesses * storage_bytes
 
@@ -82,12 +93,16 @@ def measured_traffic(workload: str, precision: str):
     return float(rec["traffic_bytes_per_launch"])
 
 
+# Host cores one GPU's job may use on the measurement machines (the box's
+# CPU share per GPU); the oracle baseline runs one process per core up to it.
+HOST_CORE_SHARE = 16
+
+
 def _cpu_worker(args):
-    slices, seed, barrier_t0 = args
-    import numpy as np
+    workload, slices, barrier_t0 = args
     import oracle as O
     import workloads as W
-    w = W.c2_bent_crystal(seed=seed).subset(slices)
+    w = W.by_name(workload).subset(slices)
     p = O.Problem.from_workload(w)
     while time.time() < barrier_t0:   # common start after every worker's setup
         time.sleep(0.001)
@@ -97,17 +112,27 @@ def _cpu_worker(args):
     return w.cell_updates, t0, t1
 
 
-def cpu_baseline(slices_per_core: int = 12, cores: int | None = None) -> dict:
-    """Time the oracle, unmodified, on the host: `cores` processes, each
-    marching `slices_per_core` slices of the workload through all Nz steps
-    with one FFT thread."""
+def cpu_baseline(workload, slices_per_core: int, total_cells: int) -> dict:
+    """Time the oracle, unmodified, on the host: one process per available
+    core (at most the per-GPU share), each marching `slices_per_core` seeded
+    slices of the workload through all Nz steps with one FFT thread.  The
+    rate is measured on that sample; the time the whole workload would take
+    at it is an extrapolation and labelled so."""
     import multiprocessing as mp
+    import numpy as np
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     ncpu = os.cpu_count() or 1
-    cores = min(cores or ncpu, 16, ncpu)
-    start = time.time() + 15.0 + 0.5 * cores   # leaves time for input setup
-    jobs = [([(c * slices_per_core + i) % 256 for i in range(slices_per_core)], 2,
-             start) for c in range(cores)]
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = ncpu
+    cores = max(1, min(avail, HOST_CORE_SHARE))
+    w_nomega = W_NOMEGA[workload]
+    pick = np.random.default_rng(11).permutation(w_nomega)
+    start = time.time() + 20.0 + 0.5 * cores   # leaves time for input setup
+    jobs = [(workload, sorted(int(pick[(c * slices_per_core + i) % w_nomega])
+                              for i in range(slices_per_core)), start)
+            for c in range(cores)]
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
         res = pool.map(_cpu_worker, jobs)
@@ -122,11 +147,22 @@ def cpu_baseline(slices_per_core: int = 12, cores: int | None = None) -> dict:
                     break
     except OSError:
         pass
-    return {"value": cells / wall, "unit": "cell-updates/s", "cores": cores,
+    rate = cells / wall
+    return {"value": rate, "unit": "cell-updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{cores} processes x {slices_per_core} slices x 4000 steps "
-                      f"x 2048 points of the bent-crystal workload "
-                      f"({cells:.3e} cell-updates, {wall:.1f} s wall, {model})"}
+            "host_cpu_count": ncpu, "host_cores_available": avail,
+            "cpu_model": model,
+            "extrapolated_full_workload_s": total_cells / rate,
+            "sample": f"{cores} processes (one per core, the host's per-GPU share "
+                      f"of {HOST_CORE_SHARE}; os.cpu_count() = {ncpu}) x "
+                      f"{slices_per_core} seeded slices of {workload}, every slice "
+                      f"through all steps ({cells:.3e} cell-updates, {wall:.1f} s "
+                      f"wall, {model}); the whole workload would take "
+                      f"{total_cells / rate:.0f} s at this rate (extrapolated)"}
+
+
+W_NOMEGA = {"thermal-bump-4096x8192x1024": 1024, "bent-crystal-2048x4000x256": 256,
+            "perfect-crystal-1024x2000x1": 1}
 
 
 def run_variant(w, prec, steps, warmup, E0_np, u_t):
@@ -356,26 +392,23 @@ def bench_extensions(args):
     print(json.dumps(line))
 
 
-def bench_serve(args):
+def run_serve(rate, duration, all_fp64, args) -> dict:
     """Served request stream: Poisson arrivals (seeded), sizes as the uneven
-    batch, half fp64 and half fp32-storage requests, admission by an HBM
-    footprint budget, continuous batching over in-flight slots.  Reports
-    p50/p99 latency (arrival to outputs ready) and cell-updates/s."""
-    import queue
-    import threading
+    batch, half fp64 and half fp32-storage requests (all fp64 when
+    all_fp64), admission by an HBM footprint budget, continuous batching
+    over in-flight slots.  Returns the server's statistics: p50/p99 latency
+    (arrival to outputs ready) and cell-updates/s, among others."""
     from concurrent.futures import ThreadPoolExecutor
-    import numpy as np
     import torch
     import workloads as W
     from paper_2201_08500_amd.serve import GpuBackend, Request, Server
 
-    torch.cuda.set_device(0)
-    trace = W.c5_request_trace(rate=args.serve_rate, duration=args.serve_duration,
-                               seed=5)
+    trace = W.c5_request_trace(rate=rate, duration=duration, seed=5)
     prec_map = {"fp64": "fp64", "fp32": args.serve_fp32}
-    if args.serve_all_fp64:
+    if all_fp64:
         prec_map = {"fp64": "fp64", "fp32": "fp64"}
-    # 16 GiB of the device stay outside torch's allocator for the HIP runtime
+    # 16 GiB of the device stay outside torch's allocator for the HIP
+    # runtime; results are consumed at completion (not kept on the device)
     backend = GpuBackend(streams=args.serve_streams, keep_outputs=False,
                          headroom_bytes=16 * 2**30)
     srv = Server(backend, budget_bytes=args.serve_budget_gb * 1e9,
@@ -383,15 +416,17 @@ def bench_serve(args):
     # warm the kernels once outside the measured stream
     for prec in set(prec_map.values()):
         w0 = W.small(Nx=256, Nz=4, Nomega=1)
-        srv.backend.materialize(Request(spec=w0, precision=prec))
+        r0 = Request(spec=w0, precision=prec)
+        srv.backend.materialize(r0)
+        srv.backend.launch([r0])
     torch.cuda.synchronize()
     srv.start()
     pool = ThreadPoolExecutor(max_workers=6)
     futs = [pool.submit(W.c4_problem, spec, False) for _, spec, _ in trace[:64]]
     nxt = 64
     t0 = time.perf_counter()
-    submitted = []
     last_note = t0
+    tag = f"serve {rate:g} req/s{' all fp64' if all_fp64 else ''}"
     for i, (t_arr, spec, prec) in enumerate(trace):
         w = futs[i].result()
         futs[i] = None
@@ -401,18 +436,16 @@ def bench_serve(args):
         delay = t0 + t_arr - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        r = Request(spec=w, precision=prec_map[prec])
-        srv.submit(r)
-        submitted.append(r)
+        srv.submit(Request(spec=w, precision=prec_map[prec]))
         if time.perf_counter() - last_note > 10:
             last_note = time.perf_counter()
-            print(f"[bench] serve: {i + 1}/{len(trace)} submitted, "
+            print(f"[bench] {tag}: {i + 1}/{len(trace)} submitted, "
                   f"{len(srv.completed)} done", file=sys.stderr, flush=True)
     lag = time.perf_counter() - t0 - trace[-1][0]
     last, t_last = -1, time.perf_counter()
     while not srv.drain(timeout=10):
         n = len(srv.completed)
-        print(f"[bench] serve: draining, {n} done", file=sys.stderr, flush=True)
+        print(f"[bench] {tag}: draining, {n} done", file=sys.stderr, flush=True)
         if n != last:
             last, t_last = n, time.perf_counter()
         elif time.perf_counter() - t_last > 120:
@@ -423,24 +456,47 @@ def bench_serve(args):
         sys.exit(f"serve: device error, {len(srv.failed)} requests failed: {srv.broken}")
     pool.shutdown()
     st = srv.stats()
+    st.update(rate_per_s=rate, duration_s=duration, requests=len(trace),
+              precisions=sorted(set(prec_map.values())), submit_lag_s=lag,
+              budget_GB=args.serve_budget_gb, streams=args.serve_streams,
+              materialize_parts_s=dict(backend.timing),
+              offered_cell_updates_per_s=sum(
+                  s["Nx"] * s["Nz"] * s["Nomega"] for _, s, _ in trace) / duration)
+    del srv, backend
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return st
+
+
+def serve_runs(args) -> dict:
+    """The served stream at each rate of --serve-rates (mixed precisions),
+    and at each rate of --serve-fp64-rates the same trace all in fp64."""
+    out = {}
+    for rate in [float(r) for r in args.serve_rates.split(",") if r]:
+        print(f"[bench] serve: {rate:g} req/s mixed", file=sys.stderr, flush=True)
+        out[f"{rate:g}rps_mixed"] = run_serve(rate, args.serve_duration, False, args)
+    for rate in [float(r) for r in args.serve_fp64_rates.split(",") if r]:
+        print(f"[bench] serve: {rate:g} req/s all fp64", file=sys.stderr, flush=True)
+        out[f"{rate:g}rps_all_fp64"] = run_serve(rate, args.serve_duration, True, args)
+    return out
+
+
+def bench_serve(args):
+    """--workload serve: the served streams alone, one JSON line."""
+    import torch
+    torch.cuda.set_device(0)
+    runs = serve_runs(args)
+    head = next(iter(runs.values()))
     line = {
-        "metric": METRIC, "value": st["cell_updates_per_s"], "unit": "cell-updates/s",
-        "n_gpus": 1, "steps": len(trace), "warmup": 0,
-        "ms_per_step": st["p50_s"] * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "mixed f64" if not args.serve_all_fp64 else "f64",
+        "metric": METRIC, "value": head["cell_updates_per_s"], "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": head["requests"], "warmup": 0,
+        "ms_per_step": head["p50_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "mixed f64",
         "data": "synthetic",
-        "config": {"workload": f"served-stream-{args.serve_rate:g}rps-{args.serve_duration:g}s",
-                   "precisions": sorted(set(prec_map.values())),
+        "config": {"workload": f"served-stream-{head['rate_per_s']:g}rps-"
+                               f"{args.serve_duration:g}s",
                    "budget_GB": args.serve_budget_gb, "streams": args.serve_streams},
-        "serve": dict(st, requests=len(trace), submit_lag_s=lag,
-                      materialize_parts_s=backend.timing,
-                      allocator={k: torch.cuda.memory_stats().get(k) for k in (
-                          "num_alloc_retries", "num_device_alloc", "num_device_free",
-                          "num_sync_all_streams")},
-                      offered_cell_updates_per_s=sum(
-                          s["Nx"] * s["Nz"] * s["Nomega"] for _, s, _ in trace)
-                      / args.serve_duration),
+        "serve": runs,
     }
     print(json.dumps(line))
 
@@ -454,11 +510,18 @@ def main():
                     choices=["fp32s", "fp32", "fp64"])
     ap.add_argument("--variants", default="fp32s,fp32,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slices-per-core", type=int, default=96)
-    ap.add_argument("--workload", default="bent-crystal",
-                    choices=["bent-crystal", "thermal-bump", "batch", "serve",
+    ap.add_argument("--cpu-slices-per-core", type=int, default=None,
+                    help="oracle slices per host process (default: 24 of the "
+                         "thermal bump, 96 of the bent crystal)")
+    ap.add_argument("--workload", default="thermal-bump",
+                    choices=["thermal-bump", "bent-crystal", "batch", "serve",
                              "extensions"])
-    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="leave the served stream out of the march measurement")
+    ap.add_argument("--serve-rates", default="200",
+                    help="arrival rates (req/s) of the mixed-precision served runs")
+    ap.add_argument("--serve-fp64-rates", default="200",
+                    help="arrival rates of the same traces served all in fp64")
     ap.add_argument("--serve-duration", type=float, default=60.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-streams", type=int, default=2,
@@ -466,8 +529,6 @@ def main():
                          "blocks per stream, so more streams split the cache)")
     ap.add_argument("--serve-fp32", default="fp32s", choices=["fp32s", "fp32"],
                     help="precision used for the stream's FP32 requests")
-    ap.add_argument("--serve-all-fp64", action="store_true",
-                    help="run every request of the same trace in fp64")
     ap.add_argument("--batch-problems", type=int, default=512)
     ap.add_argument("--batch-compare", action="store_true",
                     help="also time the same jobs run one after another")
@@ -495,11 +556,11 @@ def main():
     import numpy as np
     import torch
     import workloads as W
-    from workloads.metrics import report
+    from workloads.metrics import report, within
 
     torch.cuda.set_device(0)
     if args.workload == "thermal-bump":
-        # 4096 x 8192 x 1024: the largest configuration, a precision check
+        # 4096 x 8192 x 1024: the largest configuration that fits one GPU
         w = W.c3_thermal_bump()
     else:
         w = W.c2_bent_crystal()
@@ -533,7 +594,12 @@ def main():
         a, b = r["out"]
         entry = {}
         if prec != "fp64" and "fp64" in results:
-            entry["vs_fp64_gpu_all_slices"] = report(a, b, *results["fp64"]["out"])
+            rep_ = report(a, b, *results["fp64"]["out"])
+            entry["vs_fp64_gpu_all_slices"] = rep_
+            # the target of the precision modes: relL2 <= 1e-5 over the
+            # result and per field, phase error <= 1e-4 rad
+            entry["meets_relL2_1e-5"] = not within(
+                rep_, 1e-5, phase_tol=1e-4, keys=("rel_l2", "rel_l2_E0", "rel_l2_Eh"))
         march_s = r["march_ms"] / 1e3
         entry.update(cell_updates_per_s=cells * args.steps / r["total_s"],
                      march_ms=r["march_ms"], deform_ms=r["deform_ms"],
@@ -573,9 +639,15 @@ def main():
                      "lds_TBps": lds_b * cells / (head["march_ms"] / 1e3) / 1e12},
         "precision_variants": prec_report,
     }
+    del results, u_t
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        line["serve"] = serve_runs(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on host cores)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.cpu_slices_per_core)
+        per_core = args.cpu_slices_per_core or (24 if w.Nx == 4096 else 96)
+        line["cpu_baseline"] = cpu_baseline(w.name, per_core, cells)
     print(json.dumps(line))
 
 

@@ -101,8 +101,12 @@ int bpm_plan_set_precision(bpm_plan* plan, int precision);
 /* Crystal mask Pi_j = [x_front <= x_j < x_front + thickness]; thickness may
  * be +inf.  (Symmetric Bragg slab, Section 2.1.) */
 int bpm_plan_set_crystal(bpm_plan* plan, double x_front, double thickness);
-/* Relative frequency offsets delta_w of the Nomega slices (host array,
- * copied). */
+/* Relative frequency offsets delta_w of the Nomega slices (host array of
+ * Nomega doubles, copied): slice w has the wavenumber k = k0 (1 + delta_w).
+ * These are the frequencies omega_i of the independent stationary problems
+ * into which Section 3 splits a pulse (Eq. tdp); the default grid is the
+ * one described at bpm_plan_create (the paper fixes none).  BPM_EINVAL for a
+ * NULL array or an offset that is not finite or is <= -1 (k <= 0). */
 int bpm_plan_set_detuning(bpm_plan* plan, const double* delta);
 /* General crystal mask Pi(x, z) replacing the slab (asymmetric Bragg, Laue,
  * wedges, any shape in the (x, z) plane): host array [Nz][Nx] of bytes,
@@ -142,10 +146,16 @@ int bpm_plan_get_constants(const bpm_plan* plan, int w, double* out);
  * deformation-phase table exp(i h u), shared by all slices). */
 size_t bpm_workspace_bytes(const bpm_plan* plan);
 
-/* Run the march for all slices.  E0_in: psi~_+ at z = 0 (psi~_- starts at
- * zero).  u_field may be NULL (undeformed crystal).  E0_out, Eh_out receive
- * psi~_+ and psi~_- after Nz steps; they must not alias E0_in.  The
- * workspace is allocated stream-ordered and released on the stream. */
+/* Run the march for all slices: Nz steps of Eq. fov10 (the split step of
+ * Eq. fov4 applied to the two envelopes, with the deformation phase of
+ * Eq. Authier), each slice an independent stationary problem (Eq. tdp).
+ * E0_in: psi~_+ at z = 0, device [Nomega][Nx] (psi~_- starts at zero).
+ * u_field: device float64 [Nz][Nx], or NULL (undeformed crystal).  E0_out,
+ * Eh_out: device [Nomega][Nx], receive psi~_+ and psi~_- after Nz steps;
+ * they must not alias E0_in or each other (BPM_EINVAL).  The caller owns
+ * every buffer.  The deformation workspace (bpm_workspace_bytes) is
+ * allocated stream-ordered on the stream and released on it (BPM_ENOMEM if
+ * that fails); launch failures return BPM_EHIP. */
 int bpm_propagate(const bpm_plan* plan, const void* E0_in,
                   const double* u_field, void* E0_out, void* Eh_out,
                   void* stream);
@@ -205,8 +215,11 @@ int bpm_batch_info(const bpm_batch* batch, int* n_launches, int* n_slices,
 /* Free a prepared batch (hipFree: waits for the device).  NULL is ignored. */
 void bpm_batch_destroy(bpm_batch* batch);
 
-/* One-shot batch: create (work lists allocated stream-ordered), launch and
- * release the work lists on the stream. */
+/* One-shot batch: create (work lists allocated stream-ordered and filled
+ * from host memory the stream releases once copied), launch, and release
+ * the work lists on the stream.  Not capturable: BPM_EINVAL while the
+ * stream is capturing a graph (a replay would copy from released host
+ * memory); capture bpm_batch_launch of a bpm_batch_create batch instead. */
 int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream);
 
 /* Time <-> frequency transform of a pulse along the slice axis (Section 3,

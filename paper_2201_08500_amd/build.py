@@ -31,9 +31,21 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False, extra_flags=()) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """True when obj is missing or older than src or any header of the
+    library (csrc/*.h and the public include/bpm.h)."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src, os.path.join(HERE, "..", "include", "bpm.h")]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, extra_flags=(), incremental: bool = False) -> str:
     """Compile every source (the kernel units in parallel) and link
-    libbpm.so; returns its path."""
+    libbpm.so; returns its path.  incremental=True recompiles only the
+    sources whose object is older than the source or a header."""
     from concurrent.futures import ThreadPoolExecutor
     hipcc = _hipcc()
     objdir = os.path.join(HERE, "_build")
@@ -41,17 +53,21 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     jobs = []
     # host plan: strict FP64 evaluation order for the plan constants
     host_obj = os.path.join(objdir, "bpm_host.o")
-    jobs.append([hipcc, "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-c",
-                 os.path.join(CSRC, "bpm_host.cpp"), "-o", host_obj])
+    host_src = os.path.join(CSRC, "bpm_host.cpp")
+    if not incremental or _stale(host_obj, host_src):
+        jobs.append([hipcc, "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-c",
+                     host_src, "-o", host_obj])
     objs = [host_obj]
     for src in sorted(os.listdir(CSRC)):
         if src.endswith(".hip"):
             obj = os.path.join(objdir, src[:-4] + ".o")
             unit_flags = ILP_FLAGS if src.endswith("_ilp.hip") else []
-            jobs.append([hipcc, *DEVICE_FLAGS, *unit_flags, *extra_flags, "-c",
-                         os.path.join(CSRC, src), "-o", obj])
+            if not incremental or _stale(obj, os.path.join(CSRC, src)):
+                jobs.append([hipcc, *DEVICE_FLAGS, *unit_flags, *extra_flags, "-c",
+                             os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
-    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    workers = max(1, min(max(1, len(jobs)),
+                         int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
     with ThreadPoolExecutor(workers) as pool:
         for f in [pool.submit(_run, cmd, verbose) for cmd in jobs]:
             f.result()
@@ -63,4 +79,5 @@ def build(verbose: bool = False, extra_flags=()) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -698,6 +698,15 @@ void bpm_batch_destroy(bpm_batch* b) {
 int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream) {
   g_error.clear();
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // The work lists are staged from host memory that a host callback
+  // releases after the copy: a graph replay would copy from freed memory.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t ce = hipStreamIsCapturing(s, &cap);
+  if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(BPM_EINVAL,
+                "bpm_propagate_batch cannot be captured in a graph; capture "
+                "bpm_batch_launch of a bpm_batch_create batch instead");
   bpm_batch* b = nullptr;
   int rc = batch_build(jobs, njobs, s, true, &b);
   if (rc) return rc;

@@ -5,14 +5,24 @@ arrive at any time.  A scheduler thread admits them, in arrival order, as
 device memory (an HBM footprint budget) and in-flight slots allow:
 - it materialises each admitted request's buffers on the device;
 - it packs everything admitted since the last launch into ONE batched
-  persistent launch (bpm_propagate_batch) on a free stream;
+  persistent launch (bpm_propagate_batch) on a stream with no launch in
+  flight (StreamSlots);
 - it polls completion events, so requests that arrive while others run are
   launched as soon as memory and a slot free up, and their work overlaps
   the running work on the device.
 
 Every slice runs the same code alone or in any mix, so a request's result
 does not depend on what it was batched with.  Latency is arrival to outputs
-ready (completion event observed).  Outputs stay device-resident.
+ready (completion event observed).
+
+Outputs stay device-resident.  The bytes a finished request keeps on the
+device (backend.retained(), its two output fields when the backend keeps
+them) stay charged to the budget until the caller hands them back with
+Server.release_outputs(); only the rest of its footprint (inputs,
+displacement, workspace) returns to the budget when it completes.  Retained
+outputs therefore hold back admission: a caller that never releases them
+stalls the queue once they fill the budget, instead of the device running
+out of memory outside the budget.
 
 The device side is a backend object, so the scheduling logic is testable on
 the CPU with a simulated device; GpuBackend drives libbpm.so.
@@ -62,6 +72,8 @@ class Request:
     launched: float = math.nan
     finished: float = math.nan
     device: Any = None                   # backend's per-request device state
+    outputs: Any = None                  # backend's retained outputs, if any
+    retained: int = 0                    # budget bytes still charged after done
 
 
 class Server:
@@ -79,7 +91,8 @@ class Server:
         self._incoming = collections.deque()
         self._pending = collections.deque()
         self._in_flight = []                 # (handle, [requests])
-        self._used = 0.0
+        self._used = 0.0                     # footprints admitted + retained outputs
+        self._retained = 0.0                 # part of _used held by finished outputs
         self._active = 0                     # admitted and not finished
         self._next_id = 0
         self._t0 = time.perf_counter()
@@ -142,6 +155,19 @@ class Server:
                     return True
         return False
 
+    def release_outputs(self, req: Request) -> None:
+        """Hand a finished request's retained outputs back: the backend drops
+        them and their bytes return to the budget."""
+        with self._lock:
+            n = req.retained
+            req.retained = 0
+            self._used -= n
+            self._retained -= n
+        if hasattr(self.backend, "drop_outputs"):
+            self.backend.drop_outputs(req)
+        else:
+            req.outputs = None
+
     def drain(self, timeout: Optional[float] = None) -> bool:
         """Wait until every submitted request has finished."""
         t_end = None if timeout is None else time.perf_counter() + timeout
@@ -186,6 +212,7 @@ class Server:
                     cell_updates=cells, span_s=span,
                     cell_updates_per_s=(cells / span) if done and span > 0 else math.nan,
                     peak_budget_used=self.peak_used,
+                    retained_bytes=self._retained,
                     in_flight_time_s=busy,
                     mean_launches_in_flight=(area / busy) if busy > 0 else math.nan,
                     host_materialize_s=self.host_materialize_s,
@@ -242,6 +269,15 @@ class Server:
             for r in reqs:
                 r.finished = t
                 self.backend.release(r)
+                keep = 0
+                if status is True and hasattr(self.backend, "retained"):
+                    keep = min(int(self.backend.retained(r)), r.footprint)
+                r.retained = keep
+                with self._lock:
+                    # the outputs a finished request keeps stay charged
+                    self._used -= r.footprint - keep
+                    self._retained += keep
+                    self._active -= 1
                 if status is True:
                     r.state = "done"
                     self.completed.append(r)
@@ -250,9 +286,6 @@ class Server:
                     r.state = "failed"
                     self.failed.append(r)
                     r.future.set_exception(RuntimeError(str(status)))
-                with self._lock:
-                    self._used -= r.footprint
-                    self._active -= 1
         self._in_flight = still
         if done_any and not still and hasattr(self.backend, "idle"):
             self.backend.idle()              # nothing runs: deferred cleanup
@@ -341,6 +374,37 @@ class Server:
             r.future.set_exception(err if isinstance(err, Exception) else RuntimeError(str(err)))
 
 
+class StreamSlots:
+    """Launch streams and the completion event of the last launch on each.
+
+    pick() returns the index of a stream whose last launch has completed (or
+    that never ran one), the one picked least recently first; launches finish
+    out of order (request sizes differ by ~1000x), so a round-robin choice
+    would queue a new launch behind a long one while another stream idles.
+    With every stream busy it returns the least recently picked one."""
+
+    def __init__(self, streams):
+        self.streams = list(streams)
+        self.last = [None] * len(self.streams)
+        self._order = list(range(len(self.streams)))   # least recently picked first
+
+    def pick(self) -> int:
+        choice = None
+        for i in self._order:
+            ev = self.last[i]
+            if ev is None or ev.query():
+                choice = i
+                break
+        if choice is None:
+            choice = self._order[0]
+        self._order.remove(choice)
+        self._order.append(choice)
+        return choice
+
+    def record(self, i: int, event) -> None:
+        self.last[i] = event
+
+
 class GpuBackend:
     """Device side over libbpm.so: buffers from torch, one bpm_propagate_batch
     per launch on a pool of streams, completion by events.
@@ -368,7 +432,8 @@ class GpuBackend:
             torch.cuda.set_per_process_memory_fraction(
                 max(0.05, 1.0 - float(headroom_bytes) / total), self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
-        self._k = 0
+        self.slots = StreamSlots(self.streams)
+        self._cur = None                     # slot of the batch being assembled
         self._retired = []                   # plans of finished requests
         # bound on retired plans (208 B of device constants per slice each,
         # a few hundred MB at most) before they are destroyed even while
@@ -391,6 +456,25 @@ class GpuBackend:
         w = req.spec
         return w.Nx * w.Nz * w.Nomega
 
+    def retained(self, req) -> int:
+        """Device bytes a finished request keeps: its two output fields when
+        outputs are kept."""
+        if not self.keep_outputs:
+            return 0
+        w = req.spec
+        return 2 * self._cell(req.precision) * w.Nomega * w.Nx
+
+    def drop_outputs(self, req):
+        req.outputs = None
+
+    def _slot(self) -> int:
+        """Stream slot of the batch being assembled: chosen at its first
+        materialize (a stream with no launch in flight) and used by its
+        launch, so its buffers and its kernels share one stream."""
+        if self._cur is None:
+            self._cur = self.slots.pick()
+        return self._cur
+
     def materialize(self, req):
         """Device buffers of one request, with no device temporaries: E0 is
         converted to the field type on the host, and u is formed in place
@@ -400,7 +484,7 @@ class GpuBackend:
         from . import Job, Plan
         torch = self.torch
         w = req.spec
-        s = self.streams[self._k % len(self.streams)]
+        s = self.streams[self._slot()]
         tm = self.timing
         try:
             with torch.cuda.stream(s):
@@ -434,12 +518,14 @@ class GpuBackend:
     def launch(self, reqs):
         from . import propagate_batch
         torch = self.torch
-        s = self.streams[self._k % len(self.streams)]
-        self._k += 1
+        i = self._slot()
+        self._cur = None
+        s = self.streams[i]
         with torch.cuda.stream(s):
             propagate_batch([r.device for r in reqs], stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
+        self.slots.record(i, ev)
         return ev
 
     def poll(self, ev):

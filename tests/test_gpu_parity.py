@@ -1,14 +1,22 @@
 """GPU parity: the HIP z-march through the C ABI against the FP64 oracle.
 
-Tolerances (relative L2 over both output fields of all compared slices):
+Every comparison asserts, against one tolerance: relative L2 over both
+output fields of all compared slices, relative L2 of the transmitted field
+E0 and of the reflected field Eh on their own, and the elementwise maximum
+error max|E_gpu - E_ref| / max|E_ref| over both fields and per field; the
+FP32 modes also assert the intensity-weighted phase error <= 1e-4 rad.
+Tolerances:
   * fp64 -- both sides are FP64; they differ by FFT rounding order
     (~1e-16 per step, random) and by the propagator phase, which the oracle
     forms in x87 extended precision (~4e-15 rad per step, repeated every
     step) and the kernel in double-double: tol = 1e-12 + 1e-14 * Nz.
   * fp32s -- FP32 storage between FFT passes, FP64 arithmetic: the target
-    relL2 <= 1e-5 and phase error <= 1e-4 rad.
-  * fp32 -- FP32 butterflies; its error grows with Nz (stated per result by
-    the benchmark); here checked at short marches against 1e-5.
+    1e-5 on every configuration.
+  * fp32 -- FP32 butterflies: 1e-5 on short marches.  Its rounding error is a
+    random walk that grows as sqrt(Nz) with about four times as many FP32
+    roundings per step as fp32s, so at full size it is bounded at its
+    measured level with a stated margin (see the full-size tests); fp32s is
+    the mode that meets the target there.
 Inputs of the FP32 paths are rounded to complex64 before both sides run, so
 the comparison measures the march and not the input rounding.
 """
@@ -20,7 +28,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from workloads.metrics import report
+from workloads.metrics import report, within
 
 pytestmark = pytest.mark.gpu
 
@@ -54,16 +62,21 @@ def oracle_run(w, prec, slices=None):
     return O.march(O.Problem.from_workload(ws), E0, ws.u)
 
 
+def assert_parity(r, prec, Nz, tol=None):
+    """Every metric of a report within the tolerance of its precision."""
+    if prec == "fp64":
+        bad = within(r, tol or tol64(Nz))
+    else:
+        bad = within(r, tol or 1e-5, phase_tol=1e-4)
+    assert not bad, (bad, r)
+
+
 def check(w, prec, slices=None, tol=None, schedule=None):
     a, b = gpu_run(w, prec, slices, schedule=schedule)
     ao, bo = oracle_run(w, prec, slices)
     r = report(a, b, ao, bo)
     print(f"\n{w.name} {prec}: {r}", flush=True)
-    if prec == "fp64":
-        assert r["rel_l2"] <= (tol or tol64(w.Nz)), r
-    else:
-        assert r["rel_l2"] <= (tol or 1e-5), r
-        assert r["phase_err_rad"] <= 1e-4, r
+    assert_parity(r, prec, w.Nz, tol)
     return r
 
 
@@ -103,9 +116,20 @@ def test_unequal_chih_chihbar():
 
 
 def test_perfect_crystal_full_size_fp64():
-    """1024 x 2000 steps, one slice, no deformation: the whole output."""
+    """1024 x 2000 steps, one slice, no deformation: the whole output.  The
+    reflected field is only 0.4% of the result here (the beam starts in
+    vacuum and the window is periodic), and rounding noise scales with the
+    whole state, so relative to its own norm Eh carries ~250x the state's
+    relative error: Eh is bounded at 1e-10 (measured 8.5e-11), everything
+    else at the FP64 tolerance."""
     w = W.c1_perfect_crystal()
-    check(w, "fp64")
+    a, b = gpu_run(w, "fp64")
+    ao, bo = oracle_run(w, "fp64")
+    r = report(a, b, ao, bo)
+    print(f"\n{w.name} fp64: {r}", flush=True)
+    assert not within(r, tol64(w.Nz), keys=("rel_l2", "rel_l2_E0", "max_err",
+                                            "max_err_E0")), r
+    assert not within(r, 1e-10, keys=("rel_l2_Eh", "max_err_Eh")), r
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32s", "fp32"])
@@ -118,12 +142,15 @@ def test_bent_crystal_full_size_sampled(prec):
     ao, bo = oracle_run(w, prec, slices)
     r = report(a, b, ao, bo)
     print(f"\n{w.name} {prec} slices {slices}: {r}", flush=True)
-    if prec == "fp64":
-        assert r["rel_l2"] <= tol64(w.Nz), r
-    elif prec == "fp32s":
-        assert r["rel_l2"] <= 1e-5 and r["phase_err_rad"] <= 1e-4, r
-    else:   # FP32 butterflies drift with Nz; bounded, reported by the bench
-        assert r["rel_l2"] <= 1e-3, r
+    if prec == "fp32":
+        # FP32 butterflies at Nz = 4000: the whole result meets 1e-5
+        # (measured 9.3e-6); the reflected field on its own measured
+        # 1.2e-5, bounded here at 1.5e-5 (a documented miss of that field)
+        assert not within(r, 1e-5, 1e-4, keys=("rel_l2", "rel_l2_E0", "max_err",
+                                               "max_err_E0")), r
+        assert not within(r, 1.5e-5, keys=("rel_l2_Eh", "max_err_Eh")), r
+    else:
+        assert_parity(r, prec, w.Nz)
 
 
 def test_thermal_bump_full_size_sampled():
@@ -135,21 +162,25 @@ def test_thermal_bump_full_size_sampled():
     a64, b64 = gpu_run(w, "fp64")
     r = report(a32, b32, a64, b64)
     print(f"\n{w.name} fp32s vs fp64 GPU (all slices): {r}", flush=True)
-    assert r["rel_l2"] <= 1e-5 and r["phase_err_rad"] <= 1e-4, r
+    assert_parity(r, "fp32s", w.Nz)
+    # every slice's result (both fields of it) within the target as well
+    assert r["worst_slice_rel_l2"] <= 1e-5, r
     ao, bo = oracle_run(w, "fp64", sl)
     r64 = report(a64[sl], b64[sl], ao, bo)
     print(f"{w.name} fp64 vs oracle slices {sl}: {r64}", flush=True)
-    assert r64["rel_l2"] <= tol64(w.Nz), r64
+    assert_parity(r64, "fp64", w.Nz)
     ao, bo = oracle_run(w, "fp32s", sl)
     r32 = report(a32[sl], b32[sl], ao, bo)
     print(f"{w.name} fp32s vs oracle slices {sl}: {r32}", flush=True)
-    assert r32["rel_l2"] <= 1e-5, r32
-    # FP32 butterflies: reported, bounded (their error grows as sqrt(Nz) and
-    # exceeds 1e-5 at this Nz; fp32s is the mode that meets it)
+    assert_parity(r32, "fp32s", w.Nz)
+    # FP32 butterflies at Nz = 8192: a random walk of about four times as
+    # many FP32 roundings per step as fp32s, measured 1.46e-5 against the
+    # oracle -- a documented miss of the 1e-5 target, bounded at 2e-5
+    # (fp32s is the mode that meets the target here)
     af, bf = gpu_run(w, "fp32", sl)
     rf = report(af, bf, ao, bo)
     print(f"{w.name} fp32 vs oracle slices {sl}: {rf}", flush=True)
-    assert rf["rel_l2"] <= 1e-3, rf
+    assert not within(rf, 2e-5, phase_tol=1e-4), rf
 
 
 def test_determinism_and_slice_independence():
@@ -209,16 +240,16 @@ def test_segmented_march_equals_monolithic(prec, schedule):
         # independently; they differ by the mode's rounding noise, and the
         # chained result meets the precision target against the oracle
         r = report(a2.cpu().numpy(), b2.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy())
-        assert r["rel_l2"] <= 2e-6, r
+        assert not within(r, 2e-6), r
         fa, fb = O.march(O.Problem.from_workload(w), Ein, w.u)
         r = report(a2.cpu().numpy().astype(np.complex128),
                    b2.cpu().numpy().astype(np.complex128), fa, fb)
-        assert r["rel_l2"] <= 1e-5, r
+        assert not within(r, 1e-5, phase_tol=1e-4), r
     else:
         assert torch.equal(a2, a) and torch.equal(b2, b)
     ra, rb = O.march(O.Problem.from_workload(w), Ein, w.u, n_steps=13)
     r = report(ck_a, ck_b, ra, rb)
-    assert r["rel_l2"] <= (tol64(13) if prec == "fp64" else 1e-5), r
+    assert_parity(r, prec, 13)
 
 
 def test_segment_rejects_bad_ranges():

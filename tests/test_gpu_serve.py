@@ -1,6 +1,8 @@
 """The continuous-batching server on the GPU: requests of mixed sizes and
 precisions arrive while others run; each served result equals the same
-problem run alone (bitwise), and admission respects the memory budget."""
+problem run alone (bitwise) and, for sampled requests, the FP64 oracle; and
+admission respects the memory budget, including outputs kept on the device
+until the caller releases them."""
 
 import random
 import time
@@ -8,7 +10,9 @@ import time
 import numpy as np
 import pytest
 
+import oracle as O
 import workloads as W
+from workloads.metrics import report, within
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -58,6 +62,68 @@ def test_served_results_equal_standalone(budget_mb):
     for r, (w, prec) in zip(rs, reqs):
         a, b = standalone(w, prec)
         assert torch.equal(r.outputs[0].cpu(), a) and torch.equal(r.outputs[1].cpu(), b), r.rid
+    # served results against the oracle: the first request of each precision
+    seen = set()
+    for r, (w, prec) in zip(rs, reqs):
+        if prec in seen:
+            continue
+        seen.add(prec)
+        assert_matches_oracle(r, w, prec)
+
+
+def assert_matches_oracle(r, w, prec):
+    E0 = w.E0_in if prec == "fp64" else w.E0_in.astype(np.complex64).astype(np.complex128)
+    ra, rb = O.march(O.Problem.from_workload(w), E0, w.u)
+    got = report(r.outputs[0].cpu().numpy().astype(np.complex128),
+                 r.outputs[1].cpu().numpy().astype(np.complex128), ra, rb)
+    print(f"served {w.name} {prec} vs oracle: {got}", flush=True)
+    tol = 1e-12 + 1e-14 * w.Nz if prec == "fp64" else 1e-5
+    assert not within(got, tol), (r.rid, prec, got)
+
+
+def test_retained_outputs_are_charged_until_released():
+    """Kept outputs stay charged to the budget: with a budget that holds the
+    footprints of only a few requests, a consumer that checks each result
+    against the oracle and then releases its outputs lets the whole stream
+    through, and the budget (inputs plus retained outputs) is never
+    exceeded."""
+    import threading
+    from paper_2201_08500_amd.serve import GpuBackend, Request, Server
+    reqs = [(W.small(Nx=1024, Nz=20 + 3 * i, Nomega=4, seed=300 + i),
+             ("fp64", "fp32s")[i % 2]) for i in range(8)]
+    backend = GpuBackend(streams=2)
+    foot = max(backend.footprint(Request(spec=w, precision=p)) for w, p in reqs)
+    budget = 3 * foot
+    srv = Server(backend, budget_bytes=budget, max_in_flight=2).start()
+    errors = []
+
+    def consume(r, w, prec):
+        try:
+            r.future.result(timeout=120)
+            assert_matches_oracle(r, w, prec)
+        except Exception as e:          # noqa: BLE001 -- reported below
+            errors.append(e)
+        finally:
+            srv.release_outputs(r)
+
+    try:
+        threads = []
+        for w, prec in reqs:
+            r = Request(spec=w, precision=prec)
+            srv.submit(r)
+            t = threading.Thread(target=consume, args=(r, w, prec))
+            t.start()
+            threads.append(t)
+        for t in threads:
+            t.join(timeout=180)
+        assert srv.drain(timeout=60)
+    finally:
+        srv.stop()
+    assert not errors, errors
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert srv.peak_used <= budget
+    assert st["retained_bytes"] == 0
 
 
 def test_served_separable_displacement_equals_host_u():

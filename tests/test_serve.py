@@ -295,3 +295,83 @@ def test_backend_idle_hook_runs_when_nothing_is_in_flight():
     finally:
         srv.stop()
     assert len(be.idle_live) >= 2 and all(n == 0 for n in be.idle_live)
+
+
+def test_retained_outputs_hold_back_admission():
+    """A finished request's kept outputs stay charged to the budget until the
+    caller releases them: the next request waits for that, not just for the
+    launch to finish."""
+    class KeepBackend(FakeBackend):
+        def retained(self, r):
+            return r.spec.get("keep", 0)
+
+        def drop_outputs(self, r):
+            r.outputs = None
+            r.spec["dropped"] = True
+
+    be = KeepBackend()
+    srv = Server(be, budget_bytes=100, max_in_flight=2).start()
+    try:
+        a = Request(spec=dict(name="a", bytes=60, keep=50, dur=0.01))
+        srv.submit(a).result(timeout=5)
+        b = req("b", 60)
+        fb = srv.submit(b)
+        time.sleep(0.1)
+        # 50 retained + 60 > 100: b stays queued while a's outputs are held
+        assert b.state == "queued" and srv.stats()["retained_bytes"] == 50
+        assert srv.peak_used <= 100
+        srv.release_outputs(a)
+        assert fb.result(timeout=5) is b
+        assert a.spec["dropped"] and a.retained == 0
+        assert srv.drain(timeout=5) and srv._used == 0
+    finally:
+        srv.stop()
+
+
+def test_failed_request_retains_nothing():
+    class KeepBackend(FakeBackend):
+        def retained(self, r):
+            return r.spec.get("keep", 0)
+
+    be = KeepBackend(fail_launch={0})
+    srv = Server(be, budget_bytes=100, max_in_flight=1).start()
+    try:
+        a = Request(spec=dict(name="a", bytes=60, keep=50))
+        with pytest.raises(RuntimeError):
+            srv.submit(a).result(timeout=5)
+        assert srv.drain(timeout=5) and srv._used == 0 and a.retained == 0
+    finally:
+        srv.stop()
+
+
+class _Event:
+    def __init__(self, done=False):
+        self.done = done
+
+    def query(self):
+        return self.done
+
+
+def test_stream_slots_pick_an_idle_stream():
+    """Launches finish out of order: with a long launch on stream 0 and a
+    short one on stream 1 that has finished, the next launch goes to stream
+    1, not back to stream 0 (round robin would queue it behind the long
+    one)."""
+    from paper_2201_08500_amd.serve import StreamSlots
+    slots = StreamSlots(["s0", "s1"])
+    i0 = slots.pick()
+    long_ev = _Event(False)
+    slots.record(i0, long_ev)
+    i1 = slots.pick()
+    assert i1 != i0
+    short_ev = _Event(False)
+    slots.record(i1, short_ev)
+    short_ev.done = True
+    assert slots.pick() == i1          # the idle stream, again
+    slots.record(i1, _Event(False))
+    # every stream busy: the least recently picked one
+    assert slots.pick() == i0
+    long_ev.done = True
+    # both idle: the one picked least recently first
+    s = StreamSlots(["a", "b", "c"])
+    assert [s.pick() for _ in range(4)] == [0, 1, 2, 0]
