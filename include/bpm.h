@@ -252,6 +252,30 @@ int bpm_march_segment(const bpm_plan* plan, const void* E0_in,
                       const void* Eh_in, const void* table, int n0, int nsteps,
                       void* E0_out, void* Eh_out, void* stream);
 
+/* Bytes of the static device workspace of bpm_propagate_noalloc: 128 MiB,
+ * held on every device the library runs on until the process ends. */
+#define BPM_NOALLOC_MAX_BYTES (128u << 20)
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * march as bpm_propagate, with the same arguments and bitwise the same
+ * results, that calls no hipMalloc / hipFree / allocating routine.  Its
+ * deformation table -- and the plan's per-slice constants and crystal mask
+ * while the plan has not uploaded them itself through an earlier call --
+ * live in one static device array of BPM_NOALLOC_MAX_BYTES per device
+ * instead: Nz * Nx * (16 for BPM_PREC_FP64, 8 otherwise) bytes of table
+ * when u_field is not NULL, plus 208 * Nomega bytes of constants and
+ * Nz * Nx bytes of mask when they are staged.  A problem that needs more
+ * returns BPM_EINVAL (use bpm_propagate_ws).  Constants and mask are
+ * copied from the plan's host memory on the stream, so the plan must stay
+ * alive until the stream has completed the call.  Every call on a device
+ * shares that device's array, which keeps the last call's contents: calls
+ * on one stream are ordered, but calls that overlap on one device (other
+ * streams, other threads) race and give wrong results. */
+int bpm_propagate_noalloc(const bpm_plan* plan, const void* E0_in,
+                          const double* u_field, void* E0_out, void* Eh_out,
+                          void* stream);
+
 /* Free a plan and its device constants (hipFree: waits for the device, so
  * work launched with the plan has completed first).  NULL is ignored. */
 void bpm_plan_destroy(bpm_plan* plan);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbpm.so")
 BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_EUNSUPPORTED = 0, -1, -2, -3, -4
 PRECISION = {"fp64": 0, "fp32": 1, "fp32s": 2}
 SCHEDULE = {"auto": -1, "stockham": 0, "fourstep": 1, "split": 2}
+NOALLOC_MAX_BYTES = 128 << 20        # BPM_NOALLOC_MAX_BYTES of include/bpm.h
 _CODES = {BPM_EINVAL: "EINVAL", BPM_ENOMEM: "ENOMEM", BPM_EHIP: "EHIP",
           BPM_EUNSUPPORTED: "EUNSUPPORTED"}
 
@@ -66,6 +67,9 @@ _SIGNATURES = [
      [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     ("bpm_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p]),
     ("bpm_propagate", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_void_p, ctypes.c_void_p]),
+    ("bpm_propagate_noalloc", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_void_p, ctypes.c_void_p]),
     ("bpm_propagate_ws", ctypes.c_int,
@@ -250,6 +254,23 @@ class Plan:
                                         _ptr(E0_out), _ptr(Eh_out),
                                         _ptr(workspace), s)
         _check(rc)
+        return E0_out, Eh_out
+
+    def propagate_noalloc(self, E0_in, u, E0_out, Eh_out, stream=None):
+        """bpm_propagate_noalloc: bpm_propagate with its workspace in the
+        library's static device array (no device allocation by the call;
+        the outputs are caller-provided)."""
+        import torch
+        self._check_field(E0_in, "E0_in")
+        self._check_field(E0_out, "E0_out")
+        self._check_field(Eh_out, "Eh_out")
+        if u is not None and not (u.is_cuda and u.is_contiguous()
+                                  and u.dtype == torch.float64
+                                  and tuple(u.shape) == (self.Nz, self.Nx)):
+            raise ValueError(f"u must be a contiguous CUDA float64 tensor "
+                             f"of shape ({self.Nz}, {self.Nx})")
+        _check(lib().bpm_propagate_noalloc(self._h, _ptr(E0_in), _ptr(u), _ptr(E0_out),
+                                           _ptr(Eh_out), _stream_handle(stream)))
         return E0_out, Eh_out
 
     def deformation_table(self, u, workspace, stream=None):

@@ -112,12 +112,22 @@ int compute_slice_constants(bpm_plan* p) {
   return BPM_OK;
 }
 
-// Freeze the plan on first use: constants computed and uploaded once.
-int freeze(bpm_plan* p) {
-  std::lock_guard<std::mutex> lock(p->mu);
+// Freeze the plan's host state on first use: constants computed once, no
+// device call.  Caller holds p->mu.
+int freeze_host_locked(bpm_plan* p) {
   if (p->frozen) return BPM_OK;
   int rc = compute_slice_constants(p);
   if (rc != BPM_OK) return rc;
+  p->frozen = true;
+  return BPM_OK;
+}
+
+// Freeze the plan and upload its constants (and general mask) once.
+int freeze(bpm_plan* p) {
+  std::lock_guard<std::mutex> lock(p->mu);
+  int rc = freeze_host_locked(p);
+  if (rc != BPM_OK) return rc;
+  if (p->dev_sc) return BPM_OK;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   e = hipMalloc(&p->dev_sc, sizeof(bpm::SliceConst) * p->Nomega);
@@ -138,7 +148,6 @@ int freeze(bpm_plan* p) {
     e = hipMemcpy(p->dev_mask, p->mask.data(), p->mask.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(crystal mask)");
   }
-  p->frozen = true;
   return BPM_OK;
 }
 
@@ -201,6 +210,20 @@ struct BatchGroup {
 };
 
 }  // namespace
+
+namespace bpm {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+void clear_error() { g_error.clear(); }
+int plan_freeze_host(bpm_plan* p) {
+  std::lock_guard<std::mutex> lock(p->mu);
+  return freeze_host_locked(p);
+}
+int plan_schedule_of(const bpm_plan* p) { return plan_schedule(p); }
+MarchParams plan_march_params(const bpm_plan* p, const void* E0_in, const void* table,
+                              void* E0_out, void* Eh_out) {
+  return march_params(p, E0_in, table, E0_out, Eh_out);
+}
+}  // namespace bpm
 
 struct bpm_batch {
   std::vector<DeformJob> deforms;

@@ -85,6 +85,21 @@ int default_schedule(int prec, int Nx);
 
 }  // namespace bpm
 
+struct bpm_plan;
+
+namespace bpm {
+// Host-side plan helpers (bpm_host.cpp) shared with the static-workspace
+// entry point (bpm_static.hip).
+int set_error(int code, const std::string& msg);   // records msg, returns code
+void clear_error();
+// Computes the plan's FP64 constants (host only, no device call) and freezes
+// its setters; idempotent.
+int plan_freeze_host(bpm_plan* p);
+int plan_schedule_of(const bpm_plan* p);
+MarchParams plan_march_params(const bpm_plan* p, const void* E0_in, const void* table,
+                              void* E0_out, void* Eh_out);
+}  // namespace bpm
+
 struct bpm_plan {
   int Nx = 0, Nz = 0, Nomega = 0;
   double dx = 0, dz = 0;
@@ -101,8 +116,8 @@ struct bpm_plan {
   // derived (FP64)
   double k0 = 0, h = 0;
   std::vector<bpm::SliceConst> sc;
-  bpm::SliceConst* dev_sc = nullptr;
+  bpm::SliceConst* dev_sc = nullptr;    // uploaded constants (nullptr until then)
   int device = -1;
-  bool frozen = false;
+  bool frozen = false;                   // constants computed, setters closed
   std::mutex mu;
 };
