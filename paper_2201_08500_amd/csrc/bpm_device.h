@@ -484,6 +484,17 @@ struct March {
   enum { kDouble = 0, kSingle = 1, kWave = 2 };
   static constexpr int kSync = NBUF == 2 ? kDouble : kSingle;
 
+  // Twiddle W_{Ns Rp}^{r (jb mod Ns)} of butterfly jb = t + s T of pass P,
+  // from a register array Tw<CT>[NTW] (one entry per (s, r) of this thread)
+  // or from a TwTable in LDS.
+  template <int P, class TWS>
+  BPM_INLINE static Tw<CT> twiddle(const TWS& tw, int t, int s, int r) {
+    if constexpr (std::is_array<TWS>::value)
+      return tw[tw_off(P) + s * (rad[P] - 1) + (r - 1)];
+    else
+      return tw.template get<P>(t, s, r);
+  }
+
   // Stockham pass P over NE envelopes v[e] (LDS region e at lds + e kEnv).
   // tw: the pass twiddles, a register array Tw<CT>[NTW] or a TwTable.
   template <int P, bool INV, int SYNC, int NE, class TWS>
@@ -505,7 +516,7 @@ struct March {
       if constexpr (P > 0) {
 #pragma unroll
         for (int r = 1; r < Rp; ++r) {
-          const Tw<CT> w = tw[tw_off(P) + s * (Rp - 1) + (r - 1)];
+          const Tw<CT> w = twiddle<P>(tw, t, s, r);
 #pragma unroll
           for (int e = 0; e < NE; ++e)
             u[e][r] = INV ? w.mulc(u[e][r]) : w.mul(u[e][r]);
@@ -611,20 +622,69 @@ struct March {
   }
 
   // Twiddles of a one-wavefront transform (T = 64) kept in LDS instead of
-  // registers: a table [NTW][64] of FP64 values (they depend on the lane
-  // only), shared by every wavefront of the work group.
-  static constexpr size_t kTableBytes = size_t(NTW) * 64 * sizeof(cx<double>);
+  // registers, as a table [NTW][64] of FP64 values indexed by the lane
+  // (each lane reads its own entries, so the reads never conflict); shared
+  // by every wavefront of the work group.
+  static constexpr size_t kLaneTableBytes = size_t(NTW) * 64 * sizeof(cx<double>);
   struct TwTable {
     const cx<double>* base;
-    int lane;
-    BPM_INLINE Tw<CT> operator[](int k) const { return Tw<CT>{base[k * 64 + lane]}; }
+    template <int P>
+    BPM_INLINE Tw<CT> get(int t, int s, int r) const {
+      return Tw<CT>{base[(tw_off(P) + s * (rad[P] - 1) + (r - 1)) * 64 + t]};
+    }
   };
-  __device__ static void fill_table(cx<double>* table, int lane) {
+  __device__ static void fill_lane_table(cx<double>* table, int lane) {
     static_assert(T == 64, "a twiddle table serves one-wavefront transforms");
     Tw<CT> tw[NTW];
     twiddles_impl(tw, lane, std::make_integer_sequence<int, NP>{});
 #pragma unroll
     for (int k = 0; k < NTW; ++k) table[k * 64 + lane] = tw[k].w;
+  }
+
+  // The same twiddles with one FP64 entry per distinct value, for where LDS
+  // is too tight for the lane table: pass p holds W_{Ns Rp}^{r j} for
+  // r = 1..Rp-1, j = 0..Ns-1 (butterfly jb reads entry j = jb mod Ns).
+  // Lanes with the same j read the same address and consecutive j are
+  // consecutive entries.  The values are the ones the register twiddles
+  // hold, bit for bit.
+  static constexpr int tab_off(int p) {
+    int o = 0;
+    for (int q = 1; q < p; ++q) o += (rad[q] - 1) * ns(q);
+    return o;
+  }
+  static constexpr int kTabEntries = tab_off(NP) > 0 ? tab_off(NP) : 1;
+  static constexpr size_t kTableBytes = size_t(kTabEntries) * sizeof(cx<double>);
+  struct TwTableJ {
+    const cx<double>* base;
+    template <int P>
+    BPM_INLINE Tw<CT> get(int t, int s, int r) const {
+      constexpr int Ns = ns(P);
+      const int j = (t + s * T) & (Ns - 1);   // Ns is a power of two
+      return Tw<CT>{base[tab_off(P) + (r - 1) * Ns + j]};
+    }
+  };
+  template <int P>
+  __device__ static void fill_pass(cx<double>* table, int t, int nthreads) {
+    if constexpr (P > 0) {
+      constexpr int Rp = rad[P];
+      constexpr int Ns = ns(P);
+      for (int e = t; e < (Rp - 1) * Ns; e += nthreads) {
+        const int r = 1 + e / Ns, j = e % Ns;
+        double sn, cs;
+        sincospi(-2.0 * double(r * j) / double(Ns * Rp), &sn, &cs);
+        table[tab_off(P) + e] = {cs, sn};
+      }
+    }
+  }
+  template <int... P>
+  __device__ static void fill_impl(cx<double>* table, int t, int nthreads,
+                                   std::integer_sequence<int, P...>) {
+    (fill_pass<P>(table, t, nthreads), ...);
+  }
+  // Filled by threads t = 0..nthreads-1 of the work group; a barrier must
+  // follow before any wavefront reads it.
+  __device__ static void fill_table_j(cx<double>* table, int t, int nthreads) {
+    fill_impl(table, t, nthreads, std::make_integer_sequence<int, NP>{});
   }
 
   // Transform interface used by march_slice: per-thread context (twiddles),
@@ -681,12 +741,12 @@ struct FourStep {
   static constexpr size_t kGp = W > 1 ? size_t(W) * 2 * M : 0;
   // Separate forward and inverse exchange buffers when they fit; otherwise
   // one buffer and two extra barriers per step.
-  static constexpr bool kAlias = (kG + kGp) * sizeof(SV) + (TWL ? In::kTableBytes : 0) >
+  static constexpr bool kAlias = (kG + kGp) * sizeof(SV) + (TWL ? In::kLaneTableBytes : 0) >
                                  160 * 1024;
   // TWL: the in-wavefront twiddles live in an LDS table after the exchange
   // buffers (frees their registers where the state fills the register file)
   static constexpr size_t kTabOff = ((kAlias ? kG : kG + kGp) * sizeof(SV) + 15) / 16 * 16;
-  static constexpr size_t kLdsBytes = kTabOff + (TWL ? In::kTableBytes : 0);
+  static constexpr size_t kLdsBytes = kTabOff + (TWL ? In::kLaneTableBytes : 0);
   static_assert(kLdsBytes <= 160 * 1024, "four-step march does not fit in LDS");
   static constexpr int NTWX = W > 1 ? J * (W - 1) : 1;
   using Reg = cx<CT>[R];
@@ -700,7 +760,7 @@ struct FourStep {
   }
   __device__ static void init(Ctx& c, int t, SV* lds) {
     if constexpr (TWL) {
-      if (t < 64) In::fill_table(table(lds), t);
+      if (t < 64) In::fill_lane_table(table(lds), t);
       c.in.xbuf = 0;
       lds_barrier();
     } else {
@@ -755,7 +815,7 @@ struct FourStep {
       wave_sync();
     }
     if constexpr (TWL)
-      In::template fft<false, In::kWave>(a, b, typename In::TwTable{table(lds), l}, own, l,
+      In::template fft<false, In::kWave>(a, b, typename In::TwTable{table(lds)}, own, l,
                                          c.in.xbuf);
     else
       In::template fft<false, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
@@ -765,7 +825,7 @@ struct FourStep {
     const int wv = t >> 6, l = t & 63;
     SV* own = lds + wv * kRegion;
     if constexpr (TWL)
-      In::template fft<true, In::kWave>(a, b, typename In::TwTable{table(lds), l}, own, l,
+      In::template fft<true, In::kWave>(a, b, typename In::TwTable{table(lds)}, own, l,
                                         c.in.xbuf);
     else
       In::template fft<true, In::kWave>(a, b, c.in.tw, own, l, c.in.xbuf);
@@ -820,8 +880,10 @@ struct FourStep {
 //
 // LDS: 2W regions, one per wavefront, each the forward exchange target
 // (M samples) and afterwards that wavefront's in-wave exchange buffer, then
-// the inverse exchange (2W M samples).
-template <int PREC, int W, class In>
+// the inverse exchange (2W M samples), then (TWL) the in-wavefront twiddle
+// table, which frees their registers where the state fills the register
+// file (Nx = 4096: W = 4 with a 1024-point in-wavefront transform).
+template <int PREC, int W, class In, bool TWL = false>
 struct Split4 {
   using CT = typename Prec<PREC>::CT;
   using ST = typename Prec<PREC>::ST;
@@ -840,8 +902,24 @@ struct Split4 {
   static constexpr size_t kRegionBytes =
       (cmax(size_t(M) * sizeof(SV), size_t(In::kEnv) * sizeof(IV)) + 15) / 16 * 16;
   static constexpr size_t kGBytes = size_t(2) * W * kRegionBytes;
-  static constexpr size_t kLdsBytes = kGBytes + size_t(2) * W * M * sizeof(SV);
+  static constexpr size_t kTabOff = kGBytes + size_t(2) * W * M * sizeof(SV);
+  static constexpr size_t kLdsBytes = kTabOff + (TWL ? In::kTableBytes : 0);
   static_assert(kLdsBytes <= 160 * 1024, "split march does not fit in LDS");
+  static_assert(kTabOff % 16 == 0, "twiddle table alignment");
+
+  BPM_INLINE static cx<double>* table(SV* lds) {
+    return reinterpret_cast<cx<double>*>(reinterpret_cast<char*>(lds) + kTabOff);
+  }
+  // The in-wavefront transform of one envelope (z: this lane's M/64 bins).
+  template <bool INV>
+  BPM_INLINE static void wave_fft(cx<CT> (&z)[1][R], typename In::Ctx& ic, SV* lds,
+                                  IV* scratch, int l) {
+    if constexpr (TWL)
+      In::template fft_n<INV, In::kWave, 1>(z, typename In::TwTableJ{table(lds)}, scratch, l,
+                                            ic.xbuf);
+    else
+      In::template fft_n<INV, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
+  }
 
   BPM_INLINE static void st(SV* q, int i, cx<CT> v) {
     SV s;
@@ -859,6 +937,10 @@ struct Split4 {
 
   template <bool DEFORMED, int ORDER, bool MASKED>
   BPM_INLINE static void run(const MarchParams& p, int slice, int t, SV* lds) {
+    if constexpr (TWL) {
+      In::fill_table_j(table(lds), t, T);
+      lds_barrier();
+    }
     // wave-uniform: T0 is a multiple of the wavefront size
     if (__builtin_amdgcn_readfirstlane(t >= T0 ? 1 : 0))
       run_env<DEFORMED, 1, ORDER, MASKED>(p, slice, t - T0, lds);
@@ -906,7 +988,10 @@ struct Split4 {
     IV* scratch = reinterpret_cast<IV*>(own);
 
     typename In::Ctx ic;
-    In::init(ic, l);
+    if constexpr (TWL)
+      ic.xbuf = 0;
+    else
+      In::init(ic, l);
     // W_N^{m_j k1} of this thread's rows
     Tw<CT> twx[JH * (W - 1)];
 #pragma unroll
@@ -1027,11 +1112,11 @@ struct Split4 {
 #pragma unroll
           for (int i = 0; i < R; ++i) z[0][i] = ld(own, l + 64 * i);
           wave_sync();
-          In::template fft_n<false, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
+          wave_fft<false>(z, ic, lds, scratch, l);
 #pragma unroll
           for (int i = 0; i < R; ++i)
             z[0][i] = conv<CT>(cmul(conv<double>(z[0][i]), P[S::pset(sub)][i]));
-          In::template fft_n<true, In::kWave, 1>(z, ic.tw, scratch, l, ic.xbuf);
+          wave_fft<true>(z, ic, lds, scratch, l);
 #pragma unroll
           for (int i = 0; i < R; ++i) st(Gp + (E * W + wv) * M, l + 64 * i, z[0][i]);
           lds_barrier();
@@ -1517,6 +1602,7 @@ template <int PREC> struct Choice<PREC, 512, 0> { using type = March<PREC, 512, 
 template <int PREC> struct Choice<PREC, 1024, 0> { using type = March<PREC, 1024, 8, 8, 8, 4, 4>; };
 template <int PREC> struct Choice<PREC, 2048, 0> { using type = March<PREC, 2048, 8, 8, 8, 8, 4>; };
 template <int PREC> struct Choice<PREC, 4096, 0> { using type = March<PREC, 4096, 8, 8, 8, 8, 8>; };
+template <int PREC> using InWave1024 = March<PREC, 1024, 16, 16, 8, 8>;
 template <int PREC> using InWave512 = March<PREC, 512, 8, 8, 8, 8>;
 template <int PREC> using InWave256 = March<PREC, 256, 4, 4, 4, 4, 4>;
 template <int PREC> struct Choice<PREC, 256, 1> { using type = FourStep<PREC, 1, InWave256<PREC>>; };
@@ -1533,7 +1619,14 @@ template <int PREC> struct Choice<PREC, 256, 2> { using type = Split1<PREC, InWa
 template <int PREC> struct Choice<PREC, 512, 2> { using type = Split4<PREC, 2, InWave256<PREC>>; };
 template <int PREC> struct Choice<PREC, 1024, 2> { using type = Split4<PREC, 2, InWave512<PREC>>; };
 template <int PREC> struct Choice<PREC, 2048, 2> { using type = Split4<PREC, 4, InWave512<PREC>>; };
-template <int PREC> struct Choice<PREC, 4096, 2> { using type = typename Choice<PREC, 4096, 1>::type; };
+// 4096: the FP32-storage modes split the envelopes over W = 4 wavefronts each
+// with a 1024-point in-wavefront transform (twiddles from the LDS table);
+// FP64 storage does not fit that in LDS (its inverse exchange alone is
+// 128 KiB) and keeps the four-step
+template <int PREC> struct Choice<PREC, 4096, 2> {
+  using type = std::conditional_t<PREC == BPM_PREC_FP64, typename Choice<PREC, 4096, 1>::type,
+                                  Split4<PREC, 4, InWave1024<PREC>, true>>;
+};
 
 // Calls f(M{}) with the transform of (precision, Nx, schedule).
 template <int PREC, int N, class F>

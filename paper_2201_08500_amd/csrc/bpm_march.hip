@@ -85,7 +85,9 @@ int launch_pulse(int prec, int N, int Nx, bool to_freq, double dt, const void* i
 // slices); 0 Stockham, 1 four-step, 2 envelope-split four-step.
 int default_schedule(int prec, int Nx) {
   const int col = Nx == 256 ? 0 : Nx == 512 ? 1 : Nx == 1024 ? 2 : Nx == 2048 ? 3 : 4;
-  // (2 at Nx 4096 is the four-step: the envelope split does not fit there)
+  // (at Nx 4096 the four-step: 8% faster than the envelope split with a
+  // 1024-point in-wavefront transform in fp32s, 5% in fp32; for fp64 the
+  // split does not fit in LDS and its schedule 2 is the four-step)
   static const int kBest[3][5] = {
       /* fp64  */ {2, 2, 2, 2, 1},
       /* fp32  */ {2, 2, 2, 2, 1},
