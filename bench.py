@@ -165,11 +165,11 @@ W_NOMEGA = {"thermal-bump-4096x8192x1024": 1024, "bent-crystal-2048x4000x256": 2
             "perfect-crystal-1024x2000x1": 1}
 
 
-def run_variant(w, prec, steps, warmup, E0_np, u_t):
+def run_variant(w, prec, steps, warmup, E0_np, u_t, schedule=None):
     import numpy as np
     import torch
     from paper_2201_08500_amd import Plan
-    plan = Plan.from_workload(w, precision=prec)
+    plan = Plan.from_workload(w, precision=prec, schedule=schedule)
     E0 = torch.from_numpy(E0_np).to(plan.field_dtype).cuda()
     a = torch.empty_like(E0)
     b = torch.empty_like(E0)
@@ -509,6 +509,10 @@ def main():
     ap.add_argument("--headline", default="fp32s",
                     choices=["fp32s", "fp32", "fp64"])
     ap.add_argument("--variants", default="fp32s,fp32,fp64")
+    ap.add_argument("--schedule", default=None,
+                    choices=["auto", "stockham", "fourstep", "split"],
+                    help="transform schedule of every variant (default: the "
+                         "library's per-size default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices-per-core", type=int, default=None,
                     help="oracle slices per host process (default: 24 of the "
@@ -585,7 +589,8 @@ def main():
     for prec in variants:
         print(f"[bench] {prec}: warmup {args.warmup}, timing {args.steps} steps",
               file=sys.stderr, flush=True)
-        results[prec] = run_variant(w, prec, args.steps, args.warmup, w.E0_in, u_t)
+        results[prec] = run_variant(w, prec, args.steps, args.warmup, w.E0_in, u_t,
+                                    args.schedule)
 
     # precision report: every variant against the FP64 GPU run on all slices
     # (parity with the oracle is established by the GPU tests)
@@ -628,6 +633,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "Nx": w.Nx, "Nz": w.Nz,
                    "Nomega": w.Nomega, "precision": args.headline,
+                   "schedule": args.schedule or "auto",
                    "storage": "complex64" if storage == 8 else "complex128"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
