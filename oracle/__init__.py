@@ -24,3 +24,10 @@ from .bpm import (  # noqa: F401
     split_coefficients,
     march,
 )
+from .bpm3d import (  # noqa: F401
+    Problem3D,
+    wavenumbers_y,
+    propagator3d,
+    crystal_mask3d,
+    march3d,
+)
