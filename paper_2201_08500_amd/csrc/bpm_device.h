@@ -406,6 +406,36 @@ struct Scheme {
   static constexpr int pdef(int q) { return ORDER == 1 ? 0 : (q == 0 ? 1 : 2); }
 };
 
+// The thread index as the compiler sees it inside a transform pass: an
+// opaque copy when the twiddle source sets kOpaqueIndex (then the pass's LDS
+// addresses are formed in the pass instead of being kept live across
+// passes), the index itself otherwise.
+template <class TWS, class = void>
+struct wants_opaque : std::false_type {};
+template <class TWS>
+struct wants_opaque<TWS, std::void_t<decltype(TWS::kOpaqueIndex)>>
+    : std::integral_constant<bool, TWS::kOpaqueIndex> {};
+template <class TWS>
+BPM_INLINE int opaque_index(int t) {
+  if constexpr (wants_opaque<TWS>::value) asm volatile("" : "+v"(t));
+  return t;
+}
+
+// The thread index of one z-step of a march, opaque to the compiler when the
+// transform sets kOpaqueStep: the transform's LDS addresses are then formed
+// in every step instead of being hoisted out of the step loop and kept live
+// for the whole march.
+template <class Tr, class = void>
+struct opaque_steps : std::false_type {};
+template <class Tr>
+struct opaque_steps<Tr, std::void_t<decltype(Tr::kOpaqueStep)>>
+    : std::integral_constant<bool, Tr::kOpaqueStep> {};
+template <class Tr>
+BPM_INLINE int opaque_step(int t) {
+  if constexpr (opaque_steps<Tr>::value) asm volatile("" : "+v"(t));
+  return t;
+}
+
 // ------------------------------------------------------------- the march --
 
 template <int PREC, int N_, int R_, int... RADS>
@@ -472,6 +502,11 @@ struct March {
     const SV s = lds[idx];
     return {static_cast<CT>(s.x), static_cast<CT>(s.y)};
   }
+  template <class VT>
+  BPM_INLINE static cx<VT> load_as(const SV* lds, int idx) {
+    const SV s = lds[idx];
+    return {static_cast<VT>(s.x), static_cast<VT>(s.y)};
+  }
 
   // Stockham pass P (radix rad[P], sub-length Ns): butterfly jb reads
   // x[jb + r N/Rp], applies twiddles W_{Ns Rp}^{r (jb mod Ns)}, transforms,
@@ -496,10 +531,16 @@ struct March {
   }
 
   // Stockham pass P over NE envelopes v[e] (LDS region e at lds + e kEnv).
-  // tw: the pass twiddles, a register array Tw<CT>[NTW] or a TwTable.
-  template <int P, bool INV, int SYNC, int NE, class TWS>
-  BPM_INLINE static void pass_n(cx<CT> (&v)[NE][R], const TWS& tw,
-                                SV* lds, int t, int& xbuf) {
+  // tw: the pass twiddles, a register array Tw<CT>[NTW] or a TwTable.  The
+  // registers v hold the arithmetic type CT, or (VT = ST) the storage type,
+  // widened to CT per butterfly: the same rounding (every value between
+  // passes has been through an LDS store), half the registers.
+  template <int P, bool INV, int SYNC, int NE, class TWS, class VT>
+  BPM_INLINE static void pass_n(cx<VT> (&v)[NE][R], const TWS& tw,
+                                SV* lds, int t_in, int& xbuf) {
+    // a twiddle source may ask for the thread index to be opaque per pass,
+    // so that the pass's LDS addresses are formed where they are used
+    const int t = opaque_index<TWS>(t_in);
     constexpr int Rp = rad[P];
     constexpr int Ns = ns(P);
     constexpr int G = R / Rp;
@@ -512,7 +553,7 @@ struct March {
 #pragma unroll
       for (int e = 0; e < NE; ++e)
 #pragma unroll
-        for (int r = 0; r < Rp; ++r) u[e][r] = v[e][s + r * G];
+        for (int r = 0; r < Rp; ++r) u[e][r] = conv<CT>(v[e][s + r * G]);
       if constexpr (P > 0) {
 #pragma unroll
         for (int r = 1; r < Rp; ++r) {
@@ -528,7 +569,7 @@ struct March {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
 #pragma unroll
-          for (int r = 0; r < Rp; ++r) v[e][s + r * G] = u[e][r];
+          for (int r = 0; r < Rp; ++r) v[e][s + r * G] = conv<VT>(u[e][r]);
       } else {
         const int jb = t + s * T;
         const int base = (jb / Ns) * Ns * Rp + (jb % Ns);
@@ -551,7 +592,7 @@ struct March {
         const int idx = t + T * i;
         const int slot = idx + Ns * (idx / D);
 #pragma unroll
-        for (int e = 0; e < NE; ++e) v[e][i] = load(base_lds + e * kEnv, slot);
+        for (int e = 0; e < NE; ++e) v[e][i] = load_as<VT>(base_lds + e * kEnv, slot);
       }
       if constexpr (SYNC == kSingle) {
         lds_barrier();
@@ -563,15 +604,15 @@ struct March {
     }
   }
 
-  template <bool INV, int SYNC, int NE, class TWS, int... P>
-  BPM_INLINE static void fft_impl(cx<CT> (&v)[NE][R], const TWS& tw,
+  template <bool INV, int SYNC, int NE, class TWS, class VT, int... P>
+  BPM_INLINE static void fft_impl(cx<VT> (&v)[NE][R], const TWS& tw,
                                   SV* lds, int t, int& xbuf,
                                   std::integer_sequence<int, P...>) {
     (pass_n<P, INV, SYNC, NE>(v, tw, lds, t, xbuf), ...);
   }
-  // In-place transform of NE envelopes.
-  template <bool INV, int SYNC, int NE, class TWS>
-  BPM_INLINE static void fft_n(cx<CT> (&v)[NE][R], const TWS& tw,
+  // In-place transform of NE envelopes (registers of type CT or ST).
+  template <bool INV, int SYNC, int NE, class TWS, class VT>
+  BPM_INLINE static void fft_n(cx<VT> (&v)[NE][R], const TWS& tw,
                                SV* lds, int t, int& xbuf) {
     fft_impl<INV, SYNC, NE>(v, tw, lds, t, xbuf,
                             std::make_integer_sequence<int, NP>{});
@@ -726,6 +767,7 @@ struct FourStep {
   // fetch the deformation row after the forward transform (fewer live
   // registers across it) where the register file is the limit
   static constexpr bool kLateRow = TWL;
+  static constexpr bool kOpaqueStep = PREC != BPM_PREC_FP64;
   using CT = typename Prec<PREC>::CT;
   using ST = typename Prec<PREC>::ST;
   using SV = typename vec2<ST>::type;
@@ -1407,6 +1449,8 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
   }
 
   for (int n = 0; n < p.Nz; ++n) {
+    // the transforms' LDS addresses formed per step (see opaque_index)
+    const int ts = opaque_step<Tr>(t);
     // Row n0 + n of exp(i h u), fetched at the start of the step and used by
     // the couplings, so its latency hides behind the transforms.
     // late: fetch the row after the forward transform (first order only:
@@ -1423,7 +1467,7 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
 #pragma unroll
     for (int s = 0; s < S::NS; ++s) {
       if (S::has_a(s)) {
-        Tr::forward(a, b, ctx, lds, t);
+        Tr::forward(a, b, ctx, lds, ts);
         if constexpr (DEFORMED && late) {
           const SV* row = table + size_t(p.n0 + n) * N;
 #pragma unroll
@@ -1434,7 +1478,7 @@ BPM_INLINE void march_slice_joint(const MarchParams& p, int slice, int t,
           a[i] = conv<CT>(cmul(conv<double>(a[i]), Pp[S::pset(s)][i]));
           b[i] = conv<CT>(cmul(conv<double>(b[i]), Pm[S::pset(s)][i]));
         }
-        Tr::inverse(a, b, ctx, lds, t);
+        Tr::inverse(a, b, ctx, lds, ts);
       }
       // Coupling in FP64 where the slab is; samples outside keep the field
       // (whole-wave vacuum groups branch past).
@@ -1502,10 +1546,15 @@ __global__ void __launch_bounds__(M::T)
   for (int k = k0; k < k1; ++k) {
     const MarchParams p = items[k].p;
     const int slice = items[k].slice;
+    // the thread index opaque per item: what is formed from it (twiddles,
+    // addresses, crystal flags) is formed per item instead of being hoisted
+    // out of the item loop and kept live through every march
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
     if (p.table)
-      march_slice<M, true, ORDER, MASKED>(p, slice, threadIdx.x, lds);
+      march_slice<M, true, ORDER, MASKED>(p, slice, t, lds);
     else
-      march_slice<M, false, ORDER, MASKED>(p, slice, threadIdx.x, lds);
+      march_slice<M, false, ORDER, MASKED>(p, slice, t, lds);
     lds_barrier();   // LDS of this item fully consumed before the next one
   }
 }
