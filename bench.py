@@ -286,6 +286,73 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
+def bench_3d(args):
+    """The march on the 3D grid of the paper's finite-element example,
+    22 x 4267 x 1842 (Bluestein transforms of length 16384 along x, direct
+    22-point DFTs along y), --slices-3d frequency slices: one step is the
+    whole march (deformation table, propagator table, 2 Nz + 1 launches),
+    timed with HIP events on the stream.  FP64 rows of length 16384 do not
+    fit in LDS, so fp32s (the headline) and fp32 run and are compared with
+    each other; their parity with the oracle on a sampled slice is the GPU
+    tests' job."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2201_08500_amd import Plan3D
+    from workloads.metrics import report
+
+    torch.cuda.set_device(0)
+    w = W.heat_bump_3d(Nomega=args.slices_3d)
+    u = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
+    cells = w.cell_updates
+    out = {}
+    fields = {}
+    for prec in ("fp32s", "fp32"):
+        p = Plan3D.from_workload(w, precision=prec)
+        E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
+        a, b = torch.empty_like(E0), torch.empty_like(E0)
+        ws = torch.empty(p.workspace_bytes(), dtype=torch.uint8, device="cuda")
+        stream = torch.cuda.current_stream()
+        for _ in range(args.warmup):
+            p.propagate(E0, u, a, b, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        ts = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            p.propagate(E0, u, a, b, workspace=ws, stream=stream)
+            e1.record(stream)
+            ts.append((e0, e1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ts]))
+        fields[prec] = (a.cpu().numpy().astype(np.complex128),
+                        b.cpu().numpy().astype(np.complex128))
+        out[prec] = {"march_ms": ms, "cell_updates_per_s": cells * args.steps / wall}
+        print(f"[bench] 3d {prec}: {ms:.1f} ms per march", file=sys.stderr, flush=True)
+    out["fp32_vs_fp32s"] = report(*fields["fp32"], *fields["fp32s"])
+    head = out["fp32s"]
+    F = flops_per_cell_update(w.Nx * w.Ny)
+    achieved = F * cells / (head["march_ms"] / 1e3) / 1e12
+    line = {
+        "metric": METRIC, "value": head["cell_updates_per_s"], "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["march_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "Nx": w.Nx, "Ny": w.Ny, "Nz": w.Nz,
+                   "Nomega": w.Nomega, "precision": "fp32s", "storage": "complex64",
+                   "x_transform": "Bluestein, L = 16384"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f64"],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f64"],
+                     "flops_per_cell_update": F, "traffic": None,
+                     "kernel": "3D march (row and column kernels)"},
+        "variants": out,
+    }
+    print(json.dumps(line))
+
+
 def bench_extensions(args):
     """The extensions of the march on the bent-crystal workload, each timed
     against the plain first-order march of the same precision: 2nd- and
@@ -519,7 +586,9 @@ def main():
                          "thermal bump, 96 of the bent crystal)")
     ap.add_argument("--workload", default="thermal-bump",
                     choices=["thermal-bump", "bent-crystal", "batch", "serve",
-                             "extensions"])
+                             "extensions", "3d"])
+    ap.add_argument("--slices-3d", type=int, default=16,
+                    help="frequency slices of the 3D workload")
     ap.add_argument("--no-serve", action="store_true",
                     help="leave the served stream out of the march measurement")
     ap.add_argument("--serve-rates", default="200",
@@ -555,6 +624,9 @@ def main():
         return
     if args.workload == "extensions":
         bench_extensions(args)
+        return
+    if args.workload == "3d":
+        bench_3d(args)
         return
 
     import numpy as np

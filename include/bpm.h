@@ -96,6 +96,30 @@ bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
                           bpm_complex chihbar, double theta_B, double lambda,
                           int Nomega);
 
+/* Create a plan on a 3D grid: Ny rows (spacing dy) along y, any Nx along x
+ * (the axis of h), marching along z (Section 2.1: the step of Eq. fov4 with
+ * both transverse wavenumbers, P+-(Kx, Ky) = exp(i dz sqrt(k^2 -
+ * (Kx +- h/2)^2 - Ky^2)); the coupling of Eq. fov10 at every (x, y); the grid
+ * of the finite-element example of Section 3.4, 22 x 4267 x 1842, is one).
+ * Sample (i, j) sits at y_i = (i - Ny/2) dy, x_j = (j - Nx/2) dx (integer
+ * division); the crystal is the slab of bpm_plan_set_crystal for every y.
+ * Fields are device [Nomega][Ny][Nx] and u_field device float64
+ * [Nz][Ny][Nx].  Nx in [2, 8192] (a power of two >= 64 is transformed
+ * directly, any other length by Bluestein's algorithm on a power of two
+ * L >= 2 Nx - 1), Ny in [1, 32]; BPM_PREC_FP64 needs L <= 8192 (otherwise
+ * the propagate returns BPM_EUNSUPPORTED).  Other arguments and defaults as
+ * bpm_plan_create.  A 3D plan supports bpm_propagate, bpm_propagate_ws (with
+ * a workspace of bpm_workspace_bytes, required even for u_field NULL: it
+ * holds the propagator table), the precision, crystal, detuning and
+ * time-grid setters (the pulse transforms treat every (y, x) sample as a
+ * column; Ny Nx must be even), and first-order splitting with or without
+ * the Zassenhaus factor; the segment, batch, mask, schedule, deformation-
+ * table and no-allocation calls return BPM_EUNSUPPORTED for it.  Returns
+ * NULL on invalid input. */
+bpm_plan* bpm_plan_create_3d(int Nx, int Ny, double dx, double dy, double dz, int Nz,
+                             bpm_complex chi0, bpm_complex chih, bpm_complex chihbar,
+                             double theta_B, double lambda, int Nomega);
+
 /* Setters: allowed until the plan's first propagate, BPM_EINVAL after. */
 int bpm_plan_set_precision(bpm_plan* plan, int precision);
 /* Crystal mask Pi_j = [x_front <= x_j < x_front + thickness]; thickness may
@@ -143,7 +167,8 @@ int bpm_plan_get_schedule(const bpm_plan* plan);
 int bpm_plan_get_constants(const bpm_plan* plan, int w, double* out);
 
 /* Bytes of device workspace a deformed propagate needs (the per-cell
- * deformation-phase table exp(i h u), shared by all slices). */
+ * deformation-phase table exp(i h u), shared by all slices; for a 3D plan
+ * also the FP64 propagator table, 32 Nomega Ny Nx bytes). */
 size_t bpm_workspace_bytes(const bpm_plan* plan);
 
 /* Run the march for all slices: Nz steps of Eq. fov10 (the split step of

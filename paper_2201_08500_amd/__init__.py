@@ -10,6 +10,7 @@ from ._native import (  # noqa: F401
     BpmError,
     Job,
     Plan,
+    Plan3D,
     propagate_batch,
     PRECISION,
     LIB_PATH,

@@ -48,6 +48,10 @@ _SIGNATURES = [
      [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
       bpm_complex, bpm_complex, bpm_complex, ctypes.c_double, ctypes.c_double,
       ctypes.c_int]),
+    ("bpm_plan_create_3d", ctypes.c_void_p,
+     [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+      ctypes.c_int, bpm_complex, bpm_complex, bpm_complex, ctypes.c_double,
+      ctypes.c_double, ctypes.c_int]),
     ("bpm_plan_set_precision", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bpm_plan_set_crystal", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]),
@@ -144,15 +148,20 @@ def _stream_handle(stream):
 class Plan:
     """Owns a bpm_plan (see include/bpm.h for the meaning of every argument)."""
 
+    Ny = 1   # rows along y (Plan3D)
+
     def __init__(self, Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam,
                  Nomega, precision="fp64", x_front=None, thickness=None,
                  delta=None, split_order=1, zassenhaus=True, schedule=None,
-                 time_step=None, mask=None):
+                 time_step=None, mask=None, _handle=None):
         L = lib()
         self._h = None
-        h = L.bpm_plan_create(int(Nx), float(dx), float(dz), int(Nz),
-                              _cx(chi0), _cx(chih), _cx(chihbar),
-                              float(theta_B), float(lam), int(Nomega))
+        if _handle is None:
+            h = L.bpm_plan_create(int(Nx), float(dx), float(dz), int(Nz),
+                                  _cx(chi0), _cx(chih), _cx(chihbar),
+                                  float(theta_B), float(lam), int(Nomega))
+        else:
+            h = _handle
         if not h:
             raise BpmError(BPM_EINVAL, last_error())
         self._h = ctypes.c_void_p(h)
@@ -184,7 +193,7 @@ class Plan:
         if split_order != 1 or not zassenhaus:
             _check(L.bpm_plan_set_options(self._h, int(split_order),
                                           int(bool(zassenhaus))))
-        if schedule is None:
+        if schedule is None and _handle is None:
             from .autotune import cached_choice
             schedule = cached_choice(precision, Nx)
         if schedule is not None:
@@ -218,13 +227,28 @@ class Plan:
     def workspace_bytes(self) -> int:
         return int(lib().bpm_workspace_bytes(self._h))
 
+    @property
+    def field_shape(self):
+        return (self.Nomega, self.Nx)
+
+    @property
+    def u_shape(self):
+        return (self.Nz, self.Nx)
+
     def _check_field(self, t, name):
         import torch
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()
                 and t.dtype == self.field_dtype
-                and tuple(t.shape) == (self.Nomega, self.Nx)):
+                and tuple(t.shape) == self.field_shape):
             raise ValueError(f"{name} must be a contiguous CUDA {self.field_dtype} "
-                             f"tensor of shape ({self.Nomega}, {self.Nx})")
+                             f"tensor of shape {self.field_shape}")
+
+    def _check_u(self, u):
+        import torch
+        if not (isinstance(u, torch.Tensor) and u.is_cuda and u.is_contiguous()
+                and u.dtype == torch.float64 and tuple(u.shape) == self.u_shape):
+            raise ValueError(f"u must be a contiguous CUDA float64 tensor of shape "
+                             f"{self.u_shape}")
 
     def propagate(self, E0_in, u=None, E0_out=None, Eh_out=None,
                   workspace=None, stream=None):
@@ -233,10 +257,7 @@ class Plan:
         import torch
         self._check_field(E0_in, "E0_in")
         if u is not None:
-            if not (u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
-                    and tuple(u.shape) == (self.Nz, self.Nx)):
-                raise ValueError(f"u must be a contiguous CUDA float64 tensor "
-                                 f"of shape ({self.Nz}, {self.Nx})")
+            self._check_u(u)
         if E0_out is None:
             E0_out = torch.empty_like(E0_in)
         if Eh_out is None:
@@ -264,21 +285,15 @@ class Plan:
         self._check_field(E0_in, "E0_in")
         self._check_field(E0_out, "E0_out")
         self._check_field(Eh_out, "Eh_out")
-        if u is not None and not (u.is_cuda and u.is_contiguous()
-                                  and u.dtype == torch.float64
-                                  and tuple(u.shape) == (self.Nz, self.Nx)):
-            raise ValueError(f"u must be a contiguous CUDA float64 tensor "
-                             f"of shape ({self.Nz}, {self.Nx})")
+        if u is not None:
+            self._check_u(u)
         _check(lib().bpm_propagate_noalloc(self._h, _ptr(E0_in), _ptr(u), _ptr(E0_out),
                                            _ptr(Eh_out), _stream_handle(stream)))
         return E0_out, Eh_out
 
     def deformation_table(self, u, workspace, stream=None):
         """bpm_deformation_table: exp(i h u) for every cell into workspace."""
-        import torch
-        if not (u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
-                and tuple(u.shape) == (self.Nz, self.Nx)):
-            raise ValueError("u must be a contiguous CUDA float64 (Nz, Nx) tensor")
+        self._check_u(u)
         if workspace.numel() * workspace.element_size() < self.workspace_bytes():
             raise ValueError("workspace too small")
         _check(lib().bpm_deformation_table(self._h, _ptr(u), _ptr(workspace),
@@ -350,6 +365,41 @@ class Plan:
             pass
 
 
+class Plan3D(Plan):
+    """A plan on a 3D grid (bpm_plan_create_3d): Ny rows of dy along y, any Nx
+    along x; fields (Nomega, Ny, Nx), displacement (Nz, Ny, Nx).  Supports
+    propagate (with or without a caller workspace), the pulse transforms and
+    the precision, crystal, detuning and time-grid settings of Plan."""
+
+    def __init__(self, Nx, Ny, dx, dy, dz, Nz, chi0, chih, chihbar, theta_B, lam,
+                 Nomega, precision="fp64", x_front=None, thickness=None,
+                 delta=None, zassenhaus=True, time_step=None):
+        h = lib().bpm_plan_create_3d(int(Nx), int(Ny), float(dx), float(dy), float(dz),
+                                     int(Nz), _cx(chi0), _cx(chih), _cx(chihbar),
+                                     float(theta_B), float(lam), int(Nomega))
+        if not h:
+            raise BpmError(BPM_EINVAL, last_error())
+        self.Ny = int(Ny)
+        super().__init__(Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam, Nomega,
+                         precision=precision, x_front=x_front, thickness=thickness,
+                         delta=delta, zassenhaus=zassenhaus, time_step=time_step,
+                         _handle=h)
+
+    @classmethod
+    def from_workload(cls, w, precision="fp64", **kw):
+        return cls(w.Nx, w.Ny, w.dx, w.dy, w.dz, w.Nz, w.chi0, w.chih, w.chihbar,
+                   w.theta_B, w.lam, w.Nomega, precision=precision,
+                   x_front=w.x_front, thickness=w.thickness, delta=w.delta, **kw)
+
+    @property
+    def field_shape(self):
+        return (self.Nomega, self.Ny, self.Nx)
+
+    @property
+    def u_shape(self):
+        return (self.Nz, self.Ny, self.Nx)
+
+
 class Job:
     """One batch entry: a Plan and its device buffers (outputs allocated if
     not given; a workspace is allocated for a deformed job if not given)."""
@@ -364,9 +414,7 @@ class Job:
         plan._check_field(self.E0_out, "E0_out")
         plan._check_field(self.Eh_out, "Eh_out")
         if u is not None:
-            if not (u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
-                    and tuple(u.shape) == (plan.Nz, plan.Nx)):
-                raise ValueError("u must be a contiguous CUDA float64 (Nz, Nx) tensor")
+            plan._check_u(u)
             if workspace is None:
                 workspace = torch.empty(plan.workspace_bytes(), dtype=torch.uint8,
                                         device=E0_in.device)

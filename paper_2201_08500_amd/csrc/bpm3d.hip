@@ -1,0 +1,422 @@
+// gfx950 kernels of the z-march on a 3D grid: two transverse axes, x (along
+// h, the axis of the two angular bands) and y, marching along z (Section 2.1:
+// Eq. fov4 with k_x and k_y; the two-band coupling of Eq. fov10 at every
+// (x, y); the finite-element example of Section 3.4 runs on such a grid).
+//
+// A slice's state (both envelopes, Ny x Nx) does not fit on chip at the
+// sizes of Section 3.4 (22 x 4267), so it lives in HBM, in the caller's two
+// output buffers, and each step is two launches over all slices:
+//   row kernel    -- one work group per (slice, envelope, K_y) row: FFT along
+//                    x, the band propagator exp(i dz sqrt(k^2 - (K_x +- h/2)^2
+//                    - K_y^2)) / (Nx Ny), inverse FFT along x, in place;
+//   column kernel -- 32 x-columns x Ny threads per work group: inverse DFT
+//                    along y (back to x space), the coupling of the step with
+//                    the deformation row and the slab, forward DFT along y
+//                    for the next step (the last step stores x space).
+// The first launch transforms the incident field along y.
+//
+// Transforms along x of any length: a power of two Nx >= 64 is transformed
+// directly; any other Nx by Bluestein's algorithm on the power of two
+// L >= 2 Nx - 1 (at least 64).  With w_n = exp(-i pi n^2 / Nx), the DFT is
+// X_k = w_k (a * conj(w))_k with a_n = x_n w_n, a circular convolution of
+// length L computed with two length-L FFTs and G = FFT_L(conj(w))/L.  The
+// propagator step then needs Y_k conj(w_k) = P_k X_k conj(w_k) = P_k c_k
+// (|w_k| = 1), so the chirps between the forward and inverse transforms
+// cancel: four length-L FFTs, and a chirp at each end.  The inverse
+// transform's kernel FFT_L(w)/L equals conj(G) because the chirp sequence
+// is symmetric.  Twiddles of the length-L transform come from an FP64 table
+// W_L^m in global memory (shared by every row, resident in L2): registers
+// and LDS hold the row.  The y transform is a direct DFT (Ny <= 32).
+
+#include "bpm_device.h"
+
+namespace bpm {
+namespace {
+
+// Keeps the compiler from moving global table loads across the transforms
+// or merging the same twiddle loads of successive transforms (hoisted early
+// or shared, they stay live in registers through whole FFTs and spill).
+BPM_INLINE void phase_fence() { asm volatile("" ::: "memory"); }
+
+// The thread index as an opaque value: the LDS slot addresses of a
+// transform depend only on it, and without this the compiler computes them
+// once and keeps them live across all four transforms of a row (tens of
+// registers per pass), spilling.
+BPM_INLINE int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Twiddle W_{Ns Rp}^{r j} of pass P of transform M as W_L^{r j L/(Ns Rp)}
+// from the table tab[m] = exp(-2 pi i m / L), loaded where it is used.
+template <class M>
+struct TwGlobal {
+  static constexpr bool kOpaqueIndex = true;
+  const cx<double>* tab;
+  template <int P>
+  BPM_INLINE Tw<typename M::CT> get(int t, int s, int r) const {
+    constexpr int Ns = M::ns(P);
+    constexpr int Rp = M::rad[P];
+    const int j = (t + s * M::T) & (Ns - 1);
+    phase_fence();
+    return Tw<typename M::CT>{tab[(r * j) * (M::N / (Ns * Rp))]};
+  }
+};
+
+template <class T>
+BPM_INLINE cx<double> to_d(cx<T> a) {
+  return {static_cast<double>(a.x), static_cast<double>(a.y)};
+}
+BPM_INLINE cx<double> conjd(cx<double> a) { return {a.x, -a.y}; }
+
+// exp(i dz sqrt(k^2 - (K_x + band h/2)^2 - K_y^2)) / (Nx Ny) for signed bins
+// (mx, my), K = 2 pi m / (N d), evaluated and reduced modulo 2 pi in
+// double-double; principal root (decay) where evanescent.
+__device__ cx<double> propagator3(int mx, int my, int Nx, int Ny, double dx, double dy,
+                                  double k, double h_half, double band, double dz) {
+  const dd two_pi = {kTwoPiHi, kTwoPiLo};
+  const dd Kx = dd_div_d(dd_mul_d(two_pi, static_cast<double>(mx)),
+                         static_cast<double>(Nx) * dx);
+  const dd Ky = dd_div_d(dd_mul_d(two_pi, static_cast<double>(my)),
+                         static_cast<double>(Ny) * dy);
+  const dd kp = dd_add(Kx, dd{band * h_half, 0.0});
+  const dd kz2 = dd_add(dd_add(two_prod(k, k), dd_neg(dd_mul(kp, kp))), dd_neg(dd_mul(Ky, Ky)));
+  const double inv_n = 1.0 / (static_cast<double>(Nx) * static_cast<double>(Ny));
+  if (kz2.hi < 0.0) return {exp(-dz * sqrt(-kz2.hi)) * inv_n, 0.0};
+  dd phi = dd_mul_d(dd_sqrt(kz2), dz);
+  const double n = floor(phi.hi / kTwoPiHi);
+  phi = dd_add(phi, dd_neg(dd_mul_d(two_pi, n)));
+  if (phi.hi < 0.0) phi = dd_add(phi, two_pi);
+  if (phi.hi >= kTwoPiHi) phi = dd_add(phi, dd_neg(two_pi));
+  double s, c;
+  sincos(phi.hi + phi.lo, &s, &c);
+  return {c * inv_n, s * inv_n};
+}
+
+// Propagator table P[((w * 2 + env) * Ny + ky) * Nx + kx], one thread per
+// entry (grid-stride).
+__global__ void prop3_kernel(cx<double>* __restrict__ P, const SliceConst* __restrict__ sc,
+                             int Nx, int Ny, int Nomega, double dx, double dy, double dz,
+                             double h_half) {
+  const size_t n = size_t(Nomega) * 2 * Ny * Nx;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    const int kx = static_cast<int>(i % Nx);
+    const size_t r = i / Nx;
+    const int ky = static_cast<int>(r % Ny);
+    const int env = static_cast<int>((r / Ny) & 1);
+    const int w = static_cast<int>(r / (2 * size_t(Ny)));
+    const int mx = kx < (Nx + 1) / 2 ? kx : kx - Nx;
+    const int my = ky < (Ny + 1) / 2 ? ky : ky - Ny;
+    P[i] = propagator3(mx, my, Nx, Ny, dx, dy, sc[w].k, h_half, env ? -1.0 : 1.0, dz);
+  }
+}
+
+struct Row3Params {
+  void* a;                    // psi~_+ state [Nomega][Ny][Nx] (storage type)
+  void* b;                    // psi~_- state
+  const cx<double>* P;        // [Nomega][2][Ny][Nx]
+  const cx<double>* chirp;    // [Nx] w_n (Bluestein only)
+  const cx<double>* G;        // [L] FFT_L(conj(w)) / L (Bluestein only)
+  const cx<double>* tw;       // [L] exp(-2 pi i m / L)
+  int Nx, Ny;
+};
+
+// One (slice, envelope, K_y) row per work group: FFT_x, propagator, inverse
+// FFT_x, in place.  Thread t holds samples t + T i of the length-L sequence,
+// in registers of the storage type (widened to the arithmetic type inside
+// each butterfly and pointwise product).
+template <class M, bool BLUE>
+__global__ void __launch_bounds__(M::T) row3_kernel(Row3Params p) {
+  using CT = typename M::ST;
+  using SV = typename M::SV;
+  constexpr int R = M::R, T = M::T;
+  constexpr bool kTwo = 2 * M::kEnvBytes <= 160 * 1024;
+  constexpr int SYNC = kTwo ? M::kDouble : M::kSingle;
+  __shared__ __align__(16) SV lds[(kTwo ? 2 : 1) * M::kEnv];
+  const int t = threadIdx.x;
+  const int row = blockIdx.x;
+  const int ky = row % p.Ny;
+  const int env = (row / p.Ny) & 1;
+  const int w = row / (2 * p.Ny);
+  SV* line = static_cast<SV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
+  const cx<double>* Prow = p.P + size_t(row) * p.Nx;
+  const TwGlobal<M> tws{p.tw};
+  int xbuf = 0;
+  cx<CT> v[1][R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int n = t + T * i;
+    cx<double> x = {0.0, 0.0};
+    if (n < p.Nx) {
+      const SV s = line[n];
+      x = {static_cast<double>(s.x), static_cast<double>(s.y)};
+      if constexpr (BLUE) x = cmul(x, p.chirp[n]);
+    }
+    v[0][i] = conv<CT>(x);
+  }
+  if constexpr (BLUE) {
+    M::template fft_n<false, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
+    phase_fence();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (i % 4 == 0) phase_fence();     // table loads in groups of four
+      v[0][i] = conv<CT>(cmul(to_d(v[0][i]), p.G[t + T * i]));
+    }
+    phase_fence();
+    M::template fft_n<true, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
+    phase_fence();
+    // c_k P_k for k < Nx (the chirps cancel), zero beyond
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (i % 4 == 0) phase_fence();
+      const int k = t + T * i;
+      v[0][i] = k < p.Nx ? conv<CT>(cmul(to_d(v[0][i]), Prow[k])) : cx<CT>{CT(0), CT(0)};
+    }
+    phase_fence();
+    M::template fft_n<false, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
+    phase_fence();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (i % 4 == 0) phase_fence();
+      v[0][i] = conv<CT>(cmul(to_d(v[0][i]), conjd(p.G[t + T * i])));
+    }
+    phase_fence();
+    M::template fft_n<true, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
+    phase_fence();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int n = t + T * i;
+      if (n < p.Nx) {
+        const cx<double> y = cmul(to_d(v[0][i]), conjd(p.chirp[n]));
+        SV s;
+        s.x = static_cast<typename M::ST>(y.x);
+        s.y = static_cast<typename M::ST>(y.y);
+        line[n] = s;
+      }
+    }
+  } else {
+    M::template fft_n<false, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
+    phase_fence();
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[0][i] = conv<CT>(cmul(to_d(v[0][i]), Prow[t + T * i]));
+    phase_fence();
+    M::template fft_n<true, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      SV s;
+      s.x = static_cast<typename M::ST>(v[0][i].x);
+      s.y = static_cast<typename M::ST>(v[0][i].y);
+      line[t + T * i] = s;
+    }
+  }
+}
+
+struct Col3Params {
+  const void* E0_in;          // x-space input (first launch)
+  void* a;                    // psi~_+ state / output
+  void* b;                    // psi~_- state / output
+  const void* table;          // [Nz][Ny][Nx] exp(i h u), or nullptr
+  const SliceConst* sc;
+  const cx<double>* wy;       // [Ny] exp(-2 pi i j / Ny)
+  int Nx, Ny, n;              // n: the step whose coupling this launch applies
+  int mode;                   // 0 first, 1 step, 2 last
+  double dx, x_front, x_end;
+};
+
+constexpr int kCol = 32;      // x-columns per work group
+constexpr int kMaxNy = 32;
+
+// blockDim = (32, Ny), grid = (ceil(Nx / 32), Nomega).  Thread (xl, i)
+// holds sample y_i (x space) or bin K_y = i of column x of both envelopes.
+template <class ST>
+__global__ void __launch_bounds__(kCol * kMaxNy) col3_kernel(Col3Params p) {
+  using SV = typename vec2<ST>::type;
+  __shared__ cx<double> sa[kMaxNy * kCol];
+  __shared__ cx<double> sb[kMaxNy * kCol];
+  __shared__ cx<double> sw[kMaxNy];
+  const int xl = threadIdx.x, i = threadIdx.y;
+  const int x = blockIdx.x * kCol + xl;
+  const int w = blockIdx.y;
+  const int Ny = p.Ny;
+  const bool valid = x < p.Nx;
+  const size_t at = (size_t(w) * Ny + i) * p.Nx + x;
+  if (i == 0 && xl < Ny) sw[xl] = p.wy[xl];
+  cx<double> ax = {0.0, 0.0}, bx = {0.0, 0.0};
+  if (p.mode == 0) {
+    if (valid) {
+      const SV s = static_cast<const SV*>(p.E0_in)[at];
+      ax = {static_cast<double>(s.x), static_cast<double>(s.y)};
+    }
+    lds_barrier();
+  } else {
+    if (valid) {
+      const SV s = static_cast<const SV*>(p.a)[at];
+      const SV q = static_cast<const SV*>(p.b)[at];
+      sa[i * kCol + xl] = {static_cast<double>(s.x), static_cast<double>(s.y)};
+      sb[i * kCol + xl] = {static_cast<double>(q.x), static_cast<double>(q.y)};
+    }
+    lds_barrier();
+    // inverse DFT along y (unnormalised; 1/Ny is in the propagator)
+    for (int k = 0; k < Ny; ++k) {
+      const cx<double> tw = conjd(sw[(i * k) % Ny]);
+      ax = ax + cmul(sa[k * kCol + xl], tw);
+      bx = bx + cmul(sb[k * kCol + xl], tw);
+    }
+    // coupling of step n inside the slab (Eq. fov10, Eq. Authier)
+    const double xp = static_cast<double>(x - p.Nx / 2) * p.dx;
+    if (valid && xp >= p.x_front && xp < p.x_end) {
+      const SliceConst& c = p.sc[w];
+      const cx<double> d0 = {c.d[0][0], c.d[0][1]};
+      cx<double> cp = {c.d[0][2], c.d[0][3]}, cm = {c.d[0][4], c.d[0][5]};
+      if (p.table) {
+        const SV e = static_cast<const SV*>(p.table)[(size_t(p.n) * Ny + i) * p.Nx + x];
+        const cx<double> ee = {static_cast<double>(e.x), static_cast<double>(e.y)};
+        cp = cmul(cp, ee);
+        cm = cmulc(cm, ee);
+      }
+      const cx<double> a0 = ax;
+      ax = cmuladd(d0, a0, cp, bx);
+      bx = cmuladd(d0, bx, cm, a0);
+    }
+    lds_barrier();        // every column read before it is overwritten
+  }
+  if (p.mode == 2) {
+    if (valid) {
+      SV s, q;
+      s.x = static_cast<ST>(ax.x);
+      s.y = static_cast<ST>(ax.y);
+      q.x = static_cast<ST>(bx.x);
+      q.y = static_cast<ST>(bx.y);
+      static_cast<SV*>(p.a)[at] = s;
+      static_cast<SV*>(p.b)[at] = q;
+    }
+    return;
+  }
+  sa[i * kCol + xl] = ax;
+  sb[i * kCol + xl] = bx;
+  lds_barrier();
+  cx<double> A = {0.0, 0.0}, B = {0.0, 0.0};
+  for (int j = 0; j < Ny; ++j) {
+    const cx<double> tw = sw[(i * j) % Ny];
+    A = A + cmul(sa[j * kCol + xl], tw);
+    B = B + cmul(sb[j * kCol + xl], tw);
+  }
+  if (valid) {
+    SV s, q;
+    s.x = static_cast<ST>(A.x);
+    s.y = static_cast<ST>(A.y);
+    q.x = static_cast<ST>(B.x);
+    q.y = static_cast<ST>(B.y);
+    static_cast<SV*>(p.a)[at] = s;
+    static_cast<SV*>(p.b)[at] = q;
+  }
+}
+
+// Row transforms by length L (thread count L / R).
+template <int PREC, int L> struct Row3T;
+template <int PREC> struct Row3T<PREC, 64> { using type = March<PREC, 64, 4, 4, 4, 4>; };
+template <int PREC> struct Row3T<PREC, 128> { using type = March<PREC, 128, 8, 8, 4, 4>; };
+template <int PREC> struct Row3T<PREC, 256> { using type = March<PREC, 256, 4, 4, 4, 4, 4>; };
+template <int PREC> struct Row3T<PREC, 512> { using type = March<PREC, 512, 8, 8, 8, 8>; };
+template <int PREC> struct Row3T<PREC, 1024> { using type = March<PREC, 1024, 8, 8, 8, 4, 4>; };
+template <int PREC> struct Row3T<PREC, 2048> { using type = March<PREC, 2048, 8, 8, 8, 8, 4>; };
+template <int PREC> struct Row3T<PREC, 4096> { using type = March<PREC, 4096, 8, 8, 8, 8, 8>; };
+template <int PREC> struct Row3T<PREC, 8192> { using type = March<PREC, 8192, 16, 8, 8, 8, 4, 4>; };
+template <int PREC> struct Row3T<PREC, 16384> { using type = March<PREC, 16384, 16, 8, 8, 8, 8, 4>; };
+
+template <int PREC, int L>
+int launch_row3_l(bool blue, int rows, const Row3Params& p, hipStream_t s) {
+  using M = typename Row3T<PREC, L>::type;
+  if constexpr ((PREC == BPM_PREC_FP64 ? 2 : 1) * L > 16384) {
+    return BPM_EUNSUPPORTED;   // an FP64 row of this length does not fit in LDS
+  } else {
+    if (blue)
+      hipLaunchKernelGGL((row3_kernel<M, true>), dim3(rows), dim3(M::T), 0, s, p);
+    else
+      hipLaunchKernelGGL((row3_kernel<M, false>), dim3(rows), dim3(M::T), 0, s, p);
+    return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
+  }
+}
+
+template <int PREC>
+int launch_row3_p(int L, bool blue, int rows, const Row3Params& p, hipStream_t s) {
+  switch (L) {
+    case 64: return launch_row3_l<PREC, 64>(blue, rows, p, s);
+    case 128: return launch_row3_l<PREC, 128>(blue, rows, p, s);
+    case 256: return launch_row3_l<PREC, 256>(blue, rows, p, s);
+    case 512: return launch_row3_l<PREC, 512>(blue, rows, p, s);
+    case 1024: return launch_row3_l<PREC, 1024>(blue, rows, p, s);
+    case 2048: return launch_row3_l<PREC, 2048>(blue, rows, p, s);
+    case 4096: return launch_row3_l<PREC, 4096>(blue, rows, p, s);
+    case 8192: return launch_row3_l<PREC, 8192>(blue, rows, p, s);
+    case 16384: return launch_row3_l<PREC, 16384>(blue, rows, p, s);
+    default: return BPM_EUNSUPPORTED;
+  }
+}
+
+}  // namespace
+
+int launch_march3(const March3Params& q, hipStream_t s) {
+  if (q.Ny < 1 || q.Ny > kMaxNy) return BPM_EUNSUPPORTED;
+  // propagator table
+  {
+    const size_t n = size_t(q.Nomega) * 2 * q.Ny * q.Nx;
+    const int block = 256;
+    const size_t want = (n + block - 1) / block;
+    const int grid = static_cast<int>(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(prop3_kernel, dim3(grid), dim3(block), 0, s,
+                       static_cast<cx<double>*>(q.P), q.sc, q.Nx, q.Ny, q.Nomega, q.dx, q.dy,
+                       q.dz, q.h_half);
+    if (hipGetLastError() != hipSuccess) return BPM_EHIP;
+  }
+  Col3Params c{};
+  c.E0_in = q.E0_in;
+  c.a = q.E0_out;
+  c.b = q.Eh_out;
+  c.table = q.table;
+  c.sc = q.sc;
+  c.wy = static_cast<const cx<double>*>(q.wy);
+  c.Nx = q.Nx;
+  c.Ny = q.Ny;
+  c.dx = q.dx;
+  c.x_front = q.x_front;
+  c.x_end = q.x_end;
+  Row3Params r{};
+  r.a = q.E0_out;
+  r.b = q.Eh_out;
+  r.P = static_cast<const cx<double>*>(q.P);
+  r.chirp = static_cast<const cx<double>*>(q.chirp);
+  r.G = static_cast<const cx<double>*>(q.G);
+  r.tw = static_cast<const cx<double>*>(q.tw);
+  r.Nx = q.Nx;
+  r.Ny = q.Ny;
+  const dim3 cgrid((q.Nx + kCol - 1) / kCol, q.Nomega);
+  const dim3 cblock(kCol, q.Ny);
+  const int rows = q.Nomega * 2 * q.Ny;
+  auto col = [&](int mode, int n) -> int {
+    c.mode = mode;
+    c.n = n;
+    if (q.prec == BPM_PREC_FP64)
+      hipLaunchKernelGGL(col3_kernel<double>, cgrid, cblock, 0, s, c);
+    else
+      hipLaunchKernelGGL(col3_kernel<float>, cgrid, cblock, 0, s, c);
+    return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
+  };
+  auto row = [&]() -> int {
+    switch (q.prec) {
+      case BPM_PREC_FP64: return launch_row3_p<BPM_PREC_FP64>(q.L, q.bluestein, rows, r, s);
+      case BPM_PREC_FP32: return launch_row3_p<BPM_PREC_FP32>(q.L, q.bluestein, rows, r, s);
+      case BPM_PREC_FP32S: return launch_row3_p<BPM_PREC_FP32S>(q.L, q.bluestein, rows, r, s);
+      default: return BPM_EUNSUPPORTED;
+    }
+  };
+  int rc = col(0, 0);
+  for (int n = 0; rc == BPM_OK && n < q.Nz; ++n) {
+    rc = row();
+    if (rc == BPM_OK) rc = col(n + 1 < q.Nz ? 1 : 2, n);
+  }
+  return rc;
+}
+
+}  // namespace bpm

@@ -112,6 +112,64 @@ int compute_slice_constants(bpm_plan* p) {
   return BPM_OK;
 }
 
+// Forward FFT (kernel exp(-2 pi i jk / n), no scaling) of a power-of-two
+// length in FP64, in place: iterative radix 2, every twiddle evaluated
+// directly (no recurrence).
+void fft_host(std::vector<cplx>& a) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    for (size_t k = 0; k < len / 2; ++k) {
+      const double ang = -2.0 * M_PI * double(k) / double(len);
+      const cplx w(std::cos(ang), std::sin(ang));
+      for (size_t i = 0; i < n; i += len) {
+        const cplx u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+// FP64 tables of a 3D plan, concatenated: the chirp w_n = exp(-i pi n^2/Nx)
+// (n^2 reduced modulo 2 Nx in integers), G = FFT_L(conj(w) wrapped
+// circularly) / L, the length-L twiddles exp(-2 pi i m / L) and the y-DFT
+// twiddles exp(-2 pi i j / Ny).
+std::vector<cplx> tables3(const bpm_plan* p) {
+  const int N = p->Nx, L = p->L3, Ny = p->Ny;
+  std::vector<cplx> out;
+  out.reserve(size_t(N) + 2 * size_t(L) + Ny);
+  std::vector<cplx> w(N);
+  for (int n = 0; n < N; ++n) {
+    const long long m = (static_cast<long long>(n) * n) % (2LL * N);
+    const double ang = -M_PI * double(m) / double(N);
+    w[n] = cplx(std::cos(ang), std::sin(ang));
+  }
+  std::vector<cplx> h(L, cplx(0.0, 0.0));
+  if (p->bluestein) {
+    for (int m = 0; m < N; ++m) h[m] = std::conj(w[m]);
+    for (int m = 1; m < N; ++m) h[L - m] = std::conj(w[m]);
+    fft_host(h);
+    for (auto& v : h) v /= double(L);
+  }
+  out.insert(out.end(), w.begin(), w.end());
+  out.insert(out.end(), h.begin(), h.end());
+  for (int m = 0; m < L; ++m) {
+    const double ang = -2.0 * M_PI * double(m) / double(L);
+    out.emplace_back(std::cos(ang), std::sin(ang));
+  }
+  for (int j = 0; j < Ny; ++j) {
+    const double ang = -2.0 * M_PI * double(j) / double(Ny);
+    out.emplace_back(std::cos(ang), std::sin(ang));
+  }
+  return out;
+}
+
 // Freeze the plan's host state on first use: constants computed once, no
 // device call.  Caller holds p->mu.
 int freeze_host_locked(bpm_plan* p) {
@@ -148,6 +206,75 @@ int freeze(bpm_plan* p) {
     e = hipMemcpy(p->dev_mask, p->mask.data(), p->mask.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(crystal mask)");
   }
+  if (p->three_d && !p->dev_tables3) {
+    const std::vector<cplx> t = tables3(p);
+    e = hipMalloc(&p->dev_tables3, t.size() * sizeof(cplx));
+    if (e != hipSuccess) {
+      p->dev_tables3 = nullptr;
+      return fail(BPM_ENOMEM, std::string("hipMalloc(3D tables): ") + hipGetErrorString(e));
+    }
+    e = hipMemcpy(p->dev_tables3, t.data(), t.size() * sizeof(cplx), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D tables)");
+  }
+  return BPM_OK;
+}
+
+// A 3D plan can only propagate whole marches (bpm_propagate, _ws).
+int reject_3d(const bpm_plan* p, const char* what) {
+  if (p && p->three_d)
+    return fail(BPM_EUNSUPPORTED, std::string(what) + " is not available for 3D plans");
+  return BPM_OK;
+}
+
+// Propagator-table bytes of a 3D plan's workspace (256-byte aligned).
+size_t prop3_bytes(const bpm_plan* p) {
+  return (size_t(p->Nomega) * 2 * p->Ny * p->Nx * 16 + 255) & ~size_t(255);
+}
+
+// The whole 3D march: deformation table, propagator table, then the row
+// and column launches of every step (bpm3d.hip).
+int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_out,
+               void* Eh_out, void* workspace, hipStream_t s) {
+  if (p->precision == BPM_PREC_FP64 && p->L3 > 8192)
+    return fail(BPM_EUNSUPPORTED, "FP64 3D rows need a transform length <= 8192 "
+                                  "(Nx <= 4096, or a power of two <= 8192)");
+  int rc = freeze(p);
+  if (rc) return rc;
+  char* ws = static_cast<char*>(workspace);
+  void* table = nullptr;
+  if (u_field) {
+    table = ws + prop3_bytes(p);
+    rc = bpm::launch_deform(p->precision, p->Nx * p->Ny, p->Nz, p->h, u_field, table, s);
+    if (rc) return fail(rc, "deformation pre-pass launch failed");
+  }
+  const cplx* t3 = static_cast<const cplx*>(p->dev_tables3);
+  bpm::March3Params q{};
+  q.prec = p->precision;
+  q.Nx = p->Nx;
+  q.Ny = p->Ny;
+  q.Nz = p->Nz;
+  q.Nomega = p->Nomega;
+  q.L = p->L3;
+  q.bluestein = p->bluestein;
+  q.dx = p->dx;
+  q.dy = p->dy;
+  q.dz = p->dz;
+  q.h_half = 0.5 * p->h;
+  q.x_front = p->x_front;
+  q.x_end = p->x_front + p->thickness;
+  q.E0_in = E0_in;
+  q.E0_out = E0_out;
+  q.Eh_out = Eh_out;
+  q.table = table;
+  q.sc = p->dev_sc;
+  q.P = ws;
+  q.chirp = t3;
+  q.G = t3 + p->Nx;
+  q.tw = t3 + p->Nx + p->L3;
+  q.wy = t3 + p->Nx + 2 * size_t(p->L3);
+  rc = bpm::launch_march3(q, s);
+  if (rc == BPM_EUNSUPPORTED) return fail(rc, "unsupported 3D size/precision");
+  if (rc) return fail(rc, "3D march launch failed");
   return BPM_OK;
 }
 
@@ -237,6 +364,7 @@ namespace {
 int validate_job(const bpm_job& j, int idx) {
   const std::string at = "job " + std::to_string(idx) + ": ";
   if (!j.plan) return fail(BPM_EINVAL, at + "plan is NULL");
+  if (j.plan->three_d) return fail(BPM_EUNSUPPORTED, at + "3D plans are not batched");
   if (!j.E0_in || !j.E0_out || !j.Eh_out)
     return fail(BPM_EINVAL, at + "E0_in, E0_out and Eh_out must be non-NULL");
   if (j.E0_in == j.E0_out || j.E0_in == j.Eh_out || j.E0_out == j.Eh_out)
@@ -443,6 +571,40 @@ bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
   return p;
 }
 
+bpm_plan* bpm_plan_create_3d(int Nx, int Ny, double dx, double dy, double dz, int Nz,
+                             bpm_complex chi0, bpm_complex chih, bpm_complex chihbar,
+                             double theta_B, double lambda, int Nomega) {
+  g_error.clear();
+  if (Nx < 2 || Nx > 8192) {
+    fail(BPM_EINVAL, "Nx must lie in [2, 8192]");
+    return nullptr;
+  }
+  if (Ny < 1 || Ny > 32) {
+    fail(BPM_EINVAL, "Ny must lie in [1, 32]");
+    return nullptr;
+  }
+  if (!(dy > 0) || !std::isfinite(dy)) {
+    fail(BPM_EINVAL, "dy must be finite and > 0");
+    return nullptr;
+  }
+  // the 2D validation of everything else, on a power-of-two stand-in for Nx
+  bpm_plan* p = bpm_plan_create(256, dx, dz, Nz, chi0, chih, chihbar, theta_B, lambda,
+                                Nomega);
+  if (!p) return nullptr;
+  p->Nx = Nx;
+  p->Ny = Ny;
+  p->dy = dy;
+  p->three_d = true;
+  p->bluestein = !(is_pow2(Nx) && Nx >= 64);
+  int L = 64;
+  if (p->bluestein)
+    while (L < 2 * Nx - 1) L <<= 1;
+  else
+    L = Nx;
+  p->L3 = L;
+  return p;
+}
+
 int bpm_plan_set_precision(bpm_plan* p, int precision) {
   int rc = check_mutable(p);
   if (rc) return rc;
@@ -477,6 +639,7 @@ int bpm_plan_set_detuning(bpm_plan* p, const double* delta) {
 int bpm_plan_set_mask(bpm_plan* p, const unsigned char* mask) {
   int rc = check_mutable(p);
   if (rc) return rc;
+  if (mask && p->three_d) return reject_3d(p, "a general crystal mask");
   if (!mask) {
     p->mask.clear();
     return BPM_OK;
@@ -517,6 +680,7 @@ int bpm_plan_set_options(bpm_plan* p, int split_order, int zassenhaus) {
     return fail(BPM_EINVAL, "split_order must be 1, 2 or 4");
   if (zassenhaus != 0 && zassenhaus != 1)
     return fail(BPM_EINVAL, "zassenhaus must be 0 or 1");
+  if (split_order != 1 && p->three_d) return reject_3d(p, "higher-order splitting");
   p->split_order = split_order;
   p->zassenhaus = zassenhaus;
   return BPM_OK;
@@ -528,6 +692,7 @@ int bpm_plan_set_schedule(bpm_plan* p, int schedule) {
   if (schedule != BPM_SCHED_AUTO && schedule != BPM_SCHED_STOCKHAM &&
       schedule != BPM_SCHED_FOURSTEP && schedule != BPM_SCHED_SPLIT)
     return fail(BPM_EINVAL, "unknown schedule");
+  if (schedule != BPM_SCHED_AUTO && p->three_d) return reject_3d(p, "a transform schedule");
   p->schedule = schedule;
   return BPM_OK;
 }
@@ -561,6 +726,8 @@ int bpm_plan_get_constants(const bpm_plan* cp, int w, double* out) {
 size_t bpm_workspace_bytes(const bpm_plan* p) {
   if (!p) return 0;
   const size_t cell = p->precision == BPM_PREC_FP64 ? 16 : 8;
+  if (p->three_d)
+    return prop3_bytes(p) + size_t(p->Nx) * size_t(p->Ny) * size_t(p->Nz) * cell;
   return size_t(p->Nx) * size_t(p->Nz) * cell;
 }
 
@@ -570,7 +737,10 @@ static int pulse_transform(const bpm_plan* p, const void* in, void* out, void* s
   if (!p) return fail(BPM_EINVAL, "plan is NULL");
   if (!in || !out) return fail(BPM_EINVAL, "input and output must be non-NULL");
   if (!(p->dt > 0.0)) return fail(BPM_EINVAL, "the plan has no time grid (bpm_plan_set_time_grid)");
-  int rc = bpm::launch_pulse(p->precision, p->Nomega, p->Nx, to_freq, p->dt, in, out,
+  // every (y, x) sample is a column of the slice axis
+  const int cols = p->Nx * p->Ny;
+  if (cols % 2) return fail(BPM_EINVAL, "the pulse transform needs an even Ny * Nx");
+  int rc = bpm::launch_pulse(p->precision, p->Nomega, cols, to_freq, p->dt, in, out,
                              static_cast<hipStream_t>(stream));
   if (rc) return fail(rc, "pulse transform launch failed");
   return BPM_OK;
@@ -590,6 +760,7 @@ int bpm_deformation_table(const bpm_plan* cp, const double* u_field,
                           void* workspace, void* stream) {
   g_error.clear();
   if (!cp) return fail(BPM_EINVAL, "plan is NULL");
+  if (int rc = reject_3d(cp, "bpm_deformation_table")) return rc;
   if (!u_field || !workspace)
     return fail(BPM_EINVAL, "u_field and workspace must be non-NULL");
   bpm_plan* p = const_cast<bpm_plan*>(cp);
@@ -605,6 +776,7 @@ int bpm_march(const bpm_plan* cp, const void* E0_in, const void* table,
               void* E0_out, void* Eh_out, void* stream) {
   g_error.clear();
   if (!cp) return fail(BPM_EINVAL, "plan is NULL");
+  if (int rc = reject_3d(cp, "bpm_march")) return rc;
   if (!E0_in || !E0_out || !Eh_out)
     return fail(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
   if (E0_in == E0_out || E0_in == Eh_out || E0_out == Eh_out)
@@ -625,6 +797,7 @@ int bpm_march_segment(const bpm_plan* cp, const void* E0_in, const void* Eh_in,
                       void* Eh_out, void* stream) {
   g_error.clear();
   if (!cp) return fail(BPM_EINVAL, "plan is NULL");
+  if (int rc = reject_3d(cp, "bpm_march_segment")) return rc;
   if (!E0_in || !E0_out || !Eh_out)
     return fail(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
   if (E0_out == Eh_out || (Eh_in && (E0_out == Eh_in || Eh_out == E0_in)))
@@ -654,6 +827,11 @@ int bpm_propagate_ws(const bpm_plan* cp, const void* E0_in,
     return fail(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
   if (E0_in == E0_out || E0_in == Eh_out || E0_out == Eh_out)
     return fail(BPM_EINVAL, "output buffers must not alias each other or E0_in");
+  if (cp->three_d) {
+    if (!workspace) return fail(BPM_EINVAL, "a 3D propagate needs a workspace");
+    return propagate3(const_cast<bpm_plan*>(cp), E0_in, u_field, E0_out, Eh_out, workspace,
+                      static_cast<hipStream_t>(stream));
+  }
   if (u_field && !workspace)
     return fail(BPM_EINVAL, "a deformed propagate needs a workspace");
   if (u_field) {
@@ -670,8 +848,9 @@ int bpm_propagate(const bpm_plan* p, const void* E0_in, const double* u_field,
   if (!p) return fail(BPM_EINVAL, "plan is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* ws = nullptr;
-  if (u_field) {
-    hipError_t e = hipMallocAsync(&ws, bpm_workspace_bytes(p), s);
+  if (u_field || p->three_d) {
+    const size_t bytes = p->three_d && !u_field ? prop3_bytes(p) : bpm_workspace_bytes(p);
+    hipError_t e = hipMallocAsync(&ws, bytes, s);
     if (e != hipSuccess)
       return fail(BPM_ENOMEM, std::string("hipMallocAsync(workspace): ") +
                                   hipGetErrorString(e));
@@ -743,6 +922,7 @@ int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream) {
 
 void bpm_plan_destroy(bpm_plan* p) {
   if (!p) return;
+  if (p->dev_tables3) (void)hipFree(p->dev_tables3);
   if (p->dev_sc) (void)hipFree(p->dev_sc);
   if (p->dev_mask) (void)hipFree(p->dev_mask);
   delete p;

@@ -83,6 +83,27 @@ int launch_pulse(int prec, int N, int Nx, bool to_freq, double dt, const void* i
 // Library default schedule of (precision, Nx).
 int default_schedule(int prec, int Nx);
 
+// One march on a 3D grid (bpm3d.hip): the state lives in E0_out / Eh_out
+// ([Nomega][Ny][Nx]); P is the propagator table workspace
+// ([Nomega][2][Ny][Nx] complex FP64); chirp [Nx], G [L], tw [L] and
+// wy [Ny] are the plan's FP64 tables (complex, interleaved).
+struct March3Params {
+  int prec, Nx, Ny, Nz, Nomega, L;
+  bool bluestein;
+  double dx, dy, dz, h_half, x_front, x_end;
+  const void* E0_in;
+  void* E0_out;
+  void* Eh_out;
+  const void* table;        // [Nz][Ny][Nx] exp(i h u), or nullptr
+  const SliceConst* sc;
+  void* P;
+  const void* chirp;
+  const void* G;
+  const void* tw;
+  const void* wy;
+};
+int launch_march3(const March3Params& q, hipStream_t stream);
+
 }  // namespace bpm
 
 struct bpm_plan;
@@ -117,6 +138,14 @@ struct bpm_plan {
   double k0 = 0, h = 0;
   std::vector<bpm::SliceConst> sc;
   bpm::SliceConst* dev_sc = nullptr;    // uploaded constants (nullptr until then)
+  // 3D grid (bpm_plan_create_3d): Ny rows of dy along y, any Nx; the x
+  // transform has length L (Bluestein when Nx is not a power of two >= 64)
+  bool three_d = false;
+  int Ny = 1;
+  double dy = 0.0;
+  int L3 = 0;
+  bool bluestein = false;
+  void* dev_tables3 = nullptr;          // chirp [Nx], G [L], tw [L], wy [Ny]
   int device = -1;
   bool frozen = false;                   // constants computed, setters closed
   std::mutex mu;

@@ -59,6 +59,8 @@ extern "C" int bpm_propagate_noalloc(const bpm_plan* cp, const void* E0_in,
     return bpm::set_error(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
   if (E0_in == E0_out || E0_in == Eh_out || E0_out == Eh_out)
     return bpm::set_error(BPM_EINVAL, "output buffers must not alias each other or E0_in");
+  if (cp->three_d)
+    return bpm::set_error(BPM_EUNSUPPORTED, "bpm_propagate_noalloc is not available for 3D plans");
   bpm_plan* p = const_cast<bpm_plan*>(cp);
   int rc = bpm::plan_freeze_host(p);
   if (rc) return rc;

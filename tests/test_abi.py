@@ -172,3 +172,30 @@ def test_too_long_step_is_rejected_at_use():
     with pytest.raises(N.BpmError) as e:
         p.constants(0)
     assert "too long" in str(e.value)
+
+
+@pytest.mark.parametrize("bad", [dict(Nx=1), dict(Nx=8193), dict(Ny=0), dict(Ny=33),
+                                 dict(dy=0.0), dict(dz=0.0), dict(Nz=0)])
+def test_plan_create_3d_rejects_invalid_arguments(bad):
+    N = _lib()
+    kw = dict(Nx=60, Ny=4, dx=0.5e-6, dy=2e-6, dz=0.5e-6, Nz=10, theta_B=math.pi / 4,
+              lam=1.24e-10, Nomega=2, **C)
+    kw.update(bad)
+    with pytest.raises(N.BpmError):
+        N.Plan3D(**kw)
+
+
+def test_plan_3d_workspace_and_setters():
+    N = _lib()
+    L = N.lib()
+    p = N.Plan3D(60, 4, 0.5e-6, 2e-6, 0.5e-6, 10, C["chi0"], C["chih"], C["chihbar"],
+                 math.pi / 4, 1.24e-10, 3, precision="fp32s")
+    # propagator table (FP64, both envelopes, 256-byte aligned) + table
+    prop = (3 * 2 * 4 * 60 * 16 + 255) // 256 * 256
+    assert p.workspace_bytes() == prop + 60 * 4 * 10 * 8
+    assert p.field_shape == (3, 4, 60) and p.u_shape == (10, 4, 60)
+    assert L.bpm_plan_set_options(p.handle, 2, 1) == -4          # order 2: unsupported
+    assert L.bpm_plan_set_options(p.handle, 1, 0) == 0
+    assert L.bpm_plan_set_mask(p.handle, ctypes.c_void_p(1)) == -4
+    assert L.bpm_plan_set_schedule(p.handle, 1) == -4
+    p.close()

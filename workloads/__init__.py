@@ -18,4 +18,7 @@ from .configs import (  # noqa: F401
     detuning_grid,
     pulse_field,
     by_name,
+    Workload3D,
+    small3d,
+    heat_bump_3d,
 )

@@ -325,6 +325,112 @@ def c5_request_trace(rate: float = 200.0, duration: float = 60.0, seed: int = 5)
     return out
 
 
+@dataclass
+class Workload3D:
+    """A problem on a 3D grid: rows y_i = (i - Ny/2) dy, columns
+    x_j = (j - Nx/2) dx; E0_in (Nomega, Ny, Nx), u (Nz, Ny, Nx) or None."""
+    name: str
+    Nx: int
+    Ny: int
+    dx: float
+    dy: float
+    dz: float
+    Nz: int
+    chi0: complex
+    chih: complex
+    chihbar: complex
+    theta_B: float
+    lam: float
+    Nomega: int
+    delta: np.ndarray
+    E0_in: np.ndarray
+    u: Optional[np.ndarray] = None
+    x_front: float = 0.0
+    thickness: float = math.inf
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def cell_updates(self) -> int:
+        return self.Nx * self.Ny * self.Nz * self.Nomega
+
+    def subset(self, slices) -> "Workload3D":
+        idx = np.asarray(slices, dtype=np.int64)
+        return Workload3D(self.name + f"[{len(idx)} slices]", self.Nx, self.Ny, self.dx,
+                          self.dy, self.dz, self.Nz, self.chi0, self.chih, self.chihbar,
+                          self.theta_B, self.lam, len(idx), self.delta[idx].copy(),
+                          self.E0_in[idx].copy(), self.u, self.x_front, self.thickness,
+                          dict(self.meta))
+
+
+def beam_3d(Nx, Ny, dx, dy, lam, theta_B, delta, theta_i, amp, x0, y0, w0x, w0y):
+    """The Gaussian beam exp(-(x-x0)^2/w0x^2 - (y-y0)^2/w0y^2) at glancing
+    angle theta_i in the (x, z) plane, carrier exp(i h x / 2) removed, one
+    (Ny, Nx) plane per slice."""
+    rows = incident_envelope(Nx, dx, lam, theta_B, delta, theta_i, amp, x0, w0x)
+    y = x_grid(Ny, dy)
+    gy = np.exp(-((y - y0) / w0y) ** 2)
+    return rows[:, None, :] * gy[None, :, None]
+
+
+def small3d(Nx=60, Ny=6, Nz=20, Nomega=2, seed=0, deformed=True, dx=DX, dy=None,
+            dz=DZ, x_front=0.0, thickness=math.inf) -> Workload3D:
+    """Small seeded 3D problem for parity tests: a pulse of Nomega slices, a
+    beam centred on the crystal face in x and on the window in y, a bent
+    crystal with a bump that varies along y and seeded noise strain."""
+    rng = np.random.default_rng(seed)
+    dy = 4 * dx if dy is None else dy
+    eps = darwin_relative_width(CHIH, CHIH, THETA_B)
+    delta = detuning_grid(Nomega, eps)
+    amp = pulse_amplitudes(delta, LAMBDA, 10e-15, rng)
+    Lx, Ly = Nx * dx, Ny * dy
+    xg = x_grid(Nx, dx)
+    x0 = min(max(x_front, xg[0]), xg[-1])
+    E0 = beam_3d(Nx, Ny, dx, dy, LAMBDA, THETA_B, delta, THETA_B, amp, x0, 0.0,
+                 0.08 * Lx + 2 * dx, 0.3 * Ly + dy)
+    u = None
+    if deformed:
+        y = x_grid(Ny, dy)
+        R = rng.uniform(1.0, 100.0)
+        row = (xg - x0) ** 2 / (2.0 * R)
+        z = np.arange(Nz) * dz
+        bump = rng.uniform(0.2e-10, 1e-10) * np.exp(
+            -((xg[None, None, :] - x0) ** 2 + y[None, :, None] ** 2
+              + (z[:, None, None] - Nz * dz / 2) ** 2) / (2 * (0.2 * max(Lx, Ly)) ** 2))
+        strain = rng.normal(0.0, 1e-7, size=(Nz, Ny, Nx))
+        u = row[None, None, :] + bump + dx * np.cumsum(strain, axis=2)
+    return Workload3D(f"small3d-{Nx}x{Ny}x{Nz}x{Nomega}-s{seed}", Nx, Ny, dx, dy, dz, Nz,
+                      CHI0, CHIH, CHIH, THETA_B, LAMBDA, Nomega, delta, E0, u,
+                      x_front, thickness, {"seed": seed})
+
+
+def heat_bump_3d(Nomega: int = 16, seed: int = 6, Nz: int = 1842) -> Workload3D:
+    """The grid of the paper's finite-element example (Section 3.4): 22 rows
+    along y by 4267 samples along x, 1842 steps; dx = dz = 0.5 um, dy = 5 um.
+    A pulse of Nomega slices over +-5 Darwin widths, a 30 um rms beam centred
+    on the crystal face, and a Gaussian thermal bump (1e-10 m, sigma 100 um
+    in x and z, 30 um in y) plus seeded noise strain standing in for the
+    finite-element displacement."""
+    Nx, Ny, dy = 4267, 22, 5e-6
+    rng = np.random.default_rng(seed)
+    eps = darwin_relative_width(CHIH, CHIH, THETA_B)
+    delta = detuning_grid(Nomega, eps)
+    amp = pulse_amplitudes(delta, LAMBDA, 10e-15, rng)
+    w0 = 30e-6 * math.sqrt(2.0)                 # 30 um rms intensity width
+    E0 = beam_3d(Nx, Ny, DX, dy, LAMBDA, THETA_B, delta, THETA_B, amp, 0.0, 0.0,
+                 w0, w0)
+    xg, y = x_grid(Nx, DX), x_grid(Ny, dy)
+    z = np.arange(Nz) * DZ
+    gz = np.exp(-(z - Nz * DZ / 2) ** 2 / (2 * (100e-6) ** 2))
+    gxy = np.exp(-xg[None, :] ** 2 / (2 * (100e-6) ** 2)) * np.exp(-y[:, None] ** 2 / (2 * (30e-6) ** 2))
+    u = (1e-10 * gz)[:, None, None] * gxy[None, :, :]
+    strain = rng.normal(0.0, 1e-7, size=(Nz, Ny, Nx))
+    cs = np.cumsum(strain, axis=2)
+    u += DX * (cs - cs[:, :, Nx // 2][:, :, None])
+    return Workload3D(f"heat-bump-3d-{Nx}x{Ny}x{Nz}x{Nomega}", Nx, Ny, DX, dy, DZ, Nz,
+                      CHI0, CHIH, CHIH, THETA_B, LAMBDA, Nomega, delta, E0, u,
+                      0.0, math.inf, {"seed": seed, "sigma_t": 10e-15})
+
+
 def by_name(name: str) -> Workload:
     table = {
         "perfect-crystal-1024x2000x1": c1_perfect_crystal,
