@@ -104,18 +104,20 @@ bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
  * Sample (i, j) sits at y_i = (i - Ny/2) dy, x_j = (j - Nx/2) dx (integer
  * division); the crystal is the slab of bpm_plan_set_crystal for every y.
  * Fields are device [Nomega][Ny][Nx] and u_field device float64
- * [Nz][Ny][Nx].  Nx in [2, 8192] (a power of two >= 64 is transformed
- * directly, any other length by Bluestein's algorithm on a power of two
- * L >= 2 Nx - 1), Ny in [1, 32]; BPM_PREC_FP64 needs L <= 8192 (otherwise
- * the propagate returns BPM_EUNSUPPORTED).  Other arguments and defaults as
- * bpm_plan_create.  A 3D plan supports bpm_propagate, bpm_propagate_ws (with
- * a workspace of bpm_workspace_bytes, required even for u_field NULL: it
- * holds the propagator table), the precision, crystal, detuning and
- * time-grid setters (the pulse transforms treat every (y, x) sample as a
- * column; Ny Nx must be even), and first-order splitting with or without
- * the Zassenhaus factor; the segment, batch, mask, schedule, deformation-
- * table and no-allocation calls return BPM_EUNSUPPORTED for it.  Returns
- * NULL on invalid input. */
+ * [Nz][Ny][Nx].  Nx in [2, 8192]: the propagator step of a row, a cyclic
+ * convolution of length Nx, runs on the power of two L = Nx (Nx >= 64) or
+ * else the smallest L >= max(2 Nx - 1, 64), Ny in [1, 32]; BPM_PREC_FP64
+ * needs L <= 8192 (otherwise the propagate returns BPM_EUNSUPPORTED).  On
+ * its first propagate the plan builds and keeps on the device FP64 row
+ * tables of 32 Nomega Ny L bytes (for L != Nx with host FFTs of the
+ * device-evaluated propagator, once).  Other arguments and defaults as
+ * bpm_plan_create.  A 3D plan supports bpm_propagate, bpm_propagate_ws (the
+ * workspace holds the deformation table, as for a 2D plan), the precision,
+ * crystal, detuning and time-grid setters (the pulse transforms treat every
+ * (y, x) sample as a column; Ny Nx must be even), and first-order splitting
+ * with or without the Zassenhaus factor; the segment, batch, mask, schedule,
+ * deformation-table and no-allocation calls return BPM_EUNSUPPORTED for it.
+ * Returns NULL on invalid input. */
 bpm_plan* bpm_plan_create_3d(int Nx, int Ny, double dx, double dy, double dz, int Nz,
                              bpm_complex chi0, bpm_complex chih, bpm_complex chihbar,
                              double theta_B, double lambda, int Nomega);
@@ -166,9 +168,9 @@ int bpm_plan_get_schedule(const bpm_plan* plan);
  * Zassenhaus factor).  Touches no device. */
 int bpm_plan_get_constants(const bpm_plan* plan, int w, double* out);
 
-/* Bytes of device workspace a deformed propagate needs (the per-cell
- * deformation-phase table exp(i h u), shared by all slices; for a 3D plan
- * also the FP64 propagator table, 32 Nomega Ny Nx bytes). */
+/* Bytes of device workspace a deformed propagate needs: the per-cell
+ * deformation-phase table exp(i h u), shared by all slices (Nz Nx cells,
+ * Nz Ny Nx for a 3D plan; 16 bytes a cell in FP64, 8 otherwise). */
 size_t bpm_workspace_bytes(const bpm_plan* plan);
 
 /* Run the march for all slices: Nz steps of Eq. fov10 (the split step of

@@ -15,18 +15,18 @@
 //                    for the next step (the last step stores x space).
 // The first launch transforms the incident field along y.
 //
-// Transforms along x of any length: a power of two Nx >= 64 is transformed
-// directly; any other Nx by Bluestein's algorithm on the power of two
-// L >= 2 Nx - 1 (at least 64).  With w_n = exp(-i pi n^2 / Nx), the DFT is
-// X_k = w_k (a * conj(w))_k with a_n = x_n w_n, a circular convolution of
-// length L computed with two length-L FFTs and G = FFT_L(conj(w))/L.  The
-// propagator step then needs Y_k conj(w_k) = P_k X_k conj(w_k) = P_k c_k
-// (|w_k| = 1), so the chirps between the forward and inverse transforms
-// cancel: four length-L FFTs, and a chirp at each end.  The inverse
-// transform's kernel FFT_L(w)/L equals conj(G) because the chirp sequence
-// is symmetric.  Twiddles of the length-L transform come from an FP64 table
-// W_L^m in global memory (shared by every row, resident in L2): registers
-// and LDS hold the row.  The y transform is a direct DFT (Ny <= 32).
+// Transforms along x of any length: the propagator step of a row is the
+// cyclic convolution of the row with p = IDFT_Nx(P), so for any Nx it is
+// computed on a power of two L: L = Nx for powers of two >= 64, otherwise
+// the smallest power of two >= max(2 Nx - 1, 64).  The row, zero-padded to
+// L, is transformed, multiplied by the row's table Q = FFT_L(q) / L, where q
+// holds p at offsets -(Nx-1)..Nx-1 wrapped to length L (no two offsets meet
+// for L >= 2 Nx - 1), and transformed back; its first Nx samples are the
+// step.  For L = Nx, Q = P.  The plan builds Q once (FP64), the host
+// evaluating IDFT_Nx by Bluestein's algorithm for other lengths.  Twiddles
+// of the length-L transform come from an FP64 table W_L^m in global memory
+// (shared by every row, resident in L2): registers and LDS hold the row.
+// The y transform is a direct DFT (Ny <= 32).
 
 #include "bpm_device.h"
 
@@ -115,18 +115,17 @@ __global__ void prop3_kernel(cx<double>* __restrict__ P, const SliceConst* __res
 struct Row3Params {
   void* a;                    // psi~_+ state [Nomega][Ny][Nx] (storage type)
   void* b;                    // psi~_- state
-  const cx<double>* P;        // [Nomega][2][Ny][Nx]
-  const cx<double>* chirp;    // [Nx] w_n (Bluestein only)
-  const cx<double>* G;        // [L] FFT_L(conj(w)) / L (Bluestein only)
+  const cx<double>* Q;        // [Nomega][2][Ny][L] row propagator
   const cx<double>* tw;       // [L] exp(-2 pi i m / L)
   int Nx, Ny;
 };
 
-// One (slice, envelope, K_y) row per work group: FFT_x, propagator, inverse
-// FFT_x, in place.  Thread t holds samples t + T i of the length-L sequence,
-// in registers of the storage type (widened to the arithmetic type inside
-// each butterfly and pointwise product).
-template <class M, bool BLUE>
+// One (slice, envelope, K_y) row per work group: the row zero-padded to L,
+// FFT_L, times the row's propagator table, inverse FFT_L, the first Nx
+// samples stored back in place.  Thread t holds samples t + T i, in
+// registers of the storage type (widened to the arithmetic type inside each
+// butterfly and pointwise product).
+template <class M>
 __global__ void __launch_bounds__(M::T) row3_kernel(Row3Params p) {
   using CT = typename M::ST;
   using SV = typename M::SV;
@@ -140,74 +139,36 @@ __global__ void __launch_bounds__(M::T) row3_kernel(Row3Params p) {
   const int env = (row / p.Ny) & 1;
   const int w = row / (2 * p.Ny);
   SV* line = static_cast<SV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
-  const cx<double>* Prow = p.P + size_t(row) * p.Nx;
+  const cx<double>* Qrow = p.Q + size_t(row) * M::N;
   const TwGlobal<M> tws{p.tw};
   int xbuf = 0;
   cx<CT> v[1][R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int n = t + T * i;
-    cx<double> x = {0.0, 0.0};
-    if (n < p.Nx) {
-      const SV s = line[n];
-      x = {static_cast<double>(s.x), static_cast<double>(s.y)};
-      if constexpr (BLUE) x = cmul(x, p.chirp[n]);
-    }
-    v[0][i] = conv<CT>(x);
+    SV s;
+    s.x = 0;
+    s.y = 0;
+    if (n < p.Nx) s = line[n];
+    v[0][i] = {static_cast<CT>(s.x), static_cast<CT>(s.y)};
   }
-  if constexpr (BLUE) {
-    M::template fft_n<false, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
-    phase_fence();
+  M::template fft_n<false, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
+  phase_fence();
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      if (i % 4 == 0) phase_fence();     // table loads in groups of four
-      v[0][i] = conv<CT>(cmul(to_d(v[0][i]), p.G[t + T * i]));
-    }
-    phase_fence();
-    M::template fft_n<true, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
-    phase_fence();
-    // c_k P_k for k < Nx (the chirps cancel), zero beyond
+  for (int i = 0; i < R; ++i) {
+    if (i % 4 == 0) phase_fence();     // table loads in groups of four
+    v[0][i] = conv<CT>(cmul(to_d(v[0][i]), Qrow[t + T * i]));
+  }
+  phase_fence();
+  M::template fft_n<true, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      if (i % 4 == 0) phase_fence();
-      const int k = t + T * i;
-      v[0][i] = k < p.Nx ? conv<CT>(cmul(to_d(v[0][i]), Prow[k])) : cx<CT>{CT(0), CT(0)};
-    }
-    phase_fence();
-    M::template fft_n<false, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
-    phase_fence();
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      if (i % 4 == 0) phase_fence();
-      v[0][i] = conv<CT>(cmul(to_d(v[0][i]), conjd(p.G[t + T * i])));
-    }
-    phase_fence();
-    M::template fft_n<true, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
-    phase_fence();
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int n = t + T * i;
-      if (n < p.Nx) {
-        const cx<double> y = cmul(to_d(v[0][i]), conjd(p.chirp[n]));
-        SV s;
-        s.x = static_cast<typename M::ST>(y.x);
-        s.y = static_cast<typename M::ST>(y.y);
-        line[n] = s;
-      }
-    }
-  } else {
-    M::template fft_n<false, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
-    phase_fence();
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[0][i] = conv<CT>(cmul(to_d(v[0][i]), Prow[t + T * i]));
-    phase_fence();
-    M::template fft_n<true, SYNC, 1>(v, tws, lds, opaque(t), xbuf);
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
+  for (int i = 0; i < R; ++i) {
+    const int n = t + T * i;
+    if (n < p.Nx) {
       SV s;
       s.x = static_cast<typename M::ST>(v[0][i].x);
       s.y = static_cast<typename M::ST>(v[0][i].y);
-      line[t + T * i] = s;
+      line[n] = s;
     }
   }
 }
@@ -258,10 +219,12 @@ __global__ void __launch_bounds__(kCol * kMaxNy) col3_kernel(Col3Params p) {
     }
     lds_barrier();
     // inverse DFT along y (unnormalised; 1/Ny is in the propagator)
-    for (int k = 0; k < Ny; ++k) {
-      const cx<double> tw = conjd(sw[(i * k) % Ny]);
+    for (int k = 0, ik = 0; k < Ny; ++k) {      // ik = i k mod Ny
+      const cx<double> tw = conjd(sw[ik]);
       ax = ax + cmul(sa[k * kCol + xl], tw);
       bx = bx + cmul(sb[k * kCol + xl], tw);
+      ik += i;
+      if (ik >= Ny) ik -= Ny;
     }
     // coupling of step n inside the slab (Eq. fov10, Eq. Authier)
     const double xp = static_cast<double>(x - p.Nx / 2) * p.dx;
@@ -297,8 +260,10 @@ __global__ void __launch_bounds__(kCol * kMaxNy) col3_kernel(Col3Params p) {
   sb[i * kCol + xl] = bx;
   lds_barrier();
   cx<double> A = {0.0, 0.0}, B = {0.0, 0.0};
-  for (int j = 0; j < Ny; ++j) {
-    const cx<double> tw = sw[(i * j) % Ny];
+  for (int j = 0, ij = 0; j < Ny; ++j) {      // ij = i j mod Ny
+    const cx<double> tw = sw[ij];
+    ij += i;
+    if (ij >= Ny) ij -= Ny;
     A = A + cmul(sa[j * kCol + xl], tw);
     B = B + cmul(sb[j * kCol + xl], tw);
   }
@@ -326,50 +291,47 @@ template <int PREC> struct Row3T<PREC, 8192> { using type = March<PREC, 8192, 16
 template <int PREC> struct Row3T<PREC, 16384> { using type = March<PREC, 16384, 16, 8, 8, 8, 8, 4>; };
 
 template <int PREC, int L>
-int launch_row3_l(bool blue, int rows, const Row3Params& p, hipStream_t s) {
+int launch_row3_l(int rows, const Row3Params& p, hipStream_t s) {
   using M = typename Row3T<PREC, L>::type;
   if constexpr ((PREC == BPM_PREC_FP64 ? 2 : 1) * L > 16384) {
     return BPM_EUNSUPPORTED;   // an FP64 row of this length does not fit in LDS
   } else {
-    if (blue)
-      hipLaunchKernelGGL((row3_kernel<M, true>), dim3(rows), dim3(M::T), 0, s, p);
-    else
-      hipLaunchKernelGGL((row3_kernel<M, false>), dim3(rows), dim3(M::T), 0, s, p);
+    hipLaunchKernelGGL((row3_kernel<M>), dim3(rows), dim3(M::T), 0, s, p);
     return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
   }
 }
 
 template <int PREC>
-int launch_row3_p(int L, bool blue, int rows, const Row3Params& p, hipStream_t s) {
+int launch_row3_p(int L, int rows, const Row3Params& p, hipStream_t s) {
   switch (L) {
-    case 64: return launch_row3_l<PREC, 64>(blue, rows, p, s);
-    case 128: return launch_row3_l<PREC, 128>(blue, rows, p, s);
-    case 256: return launch_row3_l<PREC, 256>(blue, rows, p, s);
-    case 512: return launch_row3_l<PREC, 512>(blue, rows, p, s);
-    case 1024: return launch_row3_l<PREC, 1024>(blue, rows, p, s);
-    case 2048: return launch_row3_l<PREC, 2048>(blue, rows, p, s);
-    case 4096: return launch_row3_l<PREC, 4096>(blue, rows, p, s);
-    case 8192: return launch_row3_l<PREC, 8192>(blue, rows, p, s);
-    case 16384: return launch_row3_l<PREC, 16384>(blue, rows, p, s);
+    case 64: return launch_row3_l<PREC, 64>(rows, p, s);
+    case 128: return launch_row3_l<PREC, 128>(rows, p, s);
+    case 256: return launch_row3_l<PREC, 256>(rows, p, s);
+    case 512: return launch_row3_l<PREC, 512>(rows, p, s);
+    case 1024: return launch_row3_l<PREC, 1024>(rows, p, s);
+    case 2048: return launch_row3_l<PREC, 2048>(rows, p, s);
+    case 4096: return launch_row3_l<PREC, 4096>(rows, p, s);
+    case 8192: return launch_row3_l<PREC, 8192>(rows, p, s);
+    case 16384: return launch_row3_l<PREC, 16384>(rows, p, s);
     default: return BPM_EUNSUPPORTED;
   }
 }
 
 }  // namespace
 
+int launch_prop3(void* P, const SliceConst* sc, int Nx, int Ny, int Nomega, double dx,
+                 double dy, double dz, double h_half, hipStream_t s) {
+  const size_t n = size_t(Nomega) * 2 * Ny * Nx;
+  const int block = 256;
+  const size_t want = (n + block - 1) / block;
+  const int grid = static_cast<int>(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(prop3_kernel, dim3(grid), dim3(block), 0, s, static_cast<cx<double>*>(P),
+                     sc, Nx, Ny, Nomega, dx, dy, dz, h_half);
+  return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
+}
+
 int launch_march3(const March3Params& q, hipStream_t s) {
   if (q.Ny < 1 || q.Ny > kMaxNy) return BPM_EUNSUPPORTED;
-  // propagator table
-  {
-    const size_t n = size_t(q.Nomega) * 2 * q.Ny * q.Nx;
-    const int block = 256;
-    const size_t want = (n + block - 1) / block;
-    const int grid = static_cast<int>(want < 8192 ? want : 8192);
-    hipLaunchKernelGGL(prop3_kernel, dim3(grid), dim3(block), 0, s,
-                       static_cast<cx<double>*>(q.P), q.sc, q.Nx, q.Ny, q.Nomega, q.dx, q.dy,
-                       q.dz, q.h_half);
-    if (hipGetLastError() != hipSuccess) return BPM_EHIP;
-  }
   Col3Params c{};
   c.E0_in = q.E0_in;
   c.a = q.E0_out;
@@ -385,9 +347,7 @@ int launch_march3(const March3Params& q, hipStream_t s) {
   Row3Params r{};
   r.a = q.E0_out;
   r.b = q.Eh_out;
-  r.P = static_cast<const cx<double>*>(q.P);
-  r.chirp = static_cast<const cx<double>*>(q.chirp);
-  r.G = static_cast<const cx<double>*>(q.G);
+  r.Q = static_cast<const cx<double>*>(q.rows);
   r.tw = static_cast<const cx<double>*>(q.tw);
   r.Nx = q.Nx;
   r.Ny = q.Ny;
@@ -405,9 +365,9 @@ int launch_march3(const March3Params& q, hipStream_t s) {
   };
   auto row = [&]() -> int {
     switch (q.prec) {
-      case BPM_PREC_FP64: return launch_row3_p<BPM_PREC_FP64>(q.L, q.bluestein, rows, r, s);
-      case BPM_PREC_FP32: return launch_row3_p<BPM_PREC_FP32>(q.L, q.bluestein, rows, r, s);
-      case BPM_PREC_FP32S: return launch_row3_p<BPM_PREC_FP32S>(q.L, q.bluestein, rows, r, s);
+      case BPM_PREC_FP64: return launch_row3_p<BPM_PREC_FP64>(q.L, rows, r, s);
+      case BPM_PREC_FP32: return launch_row3_p<BPM_PREC_FP32>(q.L, rows, r, s);
+      case BPM_PREC_FP32S: return launch_row3_p<BPM_PREC_FP32S>(q.L, rows, r, s);
       default: return BPM_EUNSUPPORTED;
     }
   };

@@ -12,7 +12,9 @@
 #include <queue>
 #include <tuple>
 #include <string>
+#include <thread>
 #include <utility>
+#include <vector>
 
 #include "bpm_internal.h"
 
@@ -112,11 +114,15 @@ int compute_slice_constants(bpm_plan* p) {
   return BPM_OK;
 }
 
+cplx mul_h(cplx a, cplx b) {
+  return cplx(a.real() * b.real() - a.imag() * b.imag(),
+              a.real() * b.imag() + a.imag() * b.real());
+}
+
 // Forward FFT (kernel exp(-2 pi i jk / n), no scaling) of a power-of-two
-// length in FP64, in place: iterative radix 2, every twiddle evaluated
-// directly (no recurrence).
-void fft_host(std::vector<cplx>& a) {
-  const size_t n = a.size();
+// length n in FP64, in place: iterative radix 2, twiddles from the table
+// tab[m] = exp(-2 pi i m / n).
+void fft_host(cplx* a, size_t n, const cplx* tab) {
   for (size_t i = 1, j = 0; i < n; ++i) {
     size_t bit = n >> 1;
     for (; j & bit; bit >>= 1) j ^= bit;
@@ -124,11 +130,10 @@ void fft_host(std::vector<cplx>& a) {
     if (i < j) std::swap(a[i], a[j]);
   }
   for (size_t len = 2; len <= n; len <<= 1) {
-    for (size_t k = 0; k < len / 2; ++k) {
-      const double ang = -2.0 * M_PI * double(k) / double(len);
-      const cplx w(std::cos(ang), std::sin(ang));
-      for (size_t i = 0; i < n; i += len) {
-        const cplx u = a[i + k], v = a[i + k + len / 2] * w;
+    const size_t stride = n / len;
+    for (size_t i = 0; i < n; i += len) {
+      for (size_t k = 0; k < len / 2; ++k) {
+        const cplx u = a[i + k], v = mul_h(a[i + k + len / 2], tab[k * stride]);
         a[i + k] = u + v;
         a[i + k + len / 2] = u - v;
       }
@@ -136,38 +141,84 @@ void fft_host(std::vector<cplx>& a) {
   }
 }
 
-// FP64 tables of a 3D plan, concatenated: the chirp w_n = exp(-i pi n^2/Nx)
-// (n^2 reduced modulo 2 Nx in integers), G = FFT_L(conj(w) wrapped
-// circularly) / L, the length-L twiddles exp(-2 pi i m / L) and the y-DFT
-// twiddles exp(-2 pi i j / Ny).
-std::vector<cplx> tables3(const bpm_plan* p) {
+// FP64 tables of a 3D plan: the length-L twiddles exp(-2 pi i m / L), the
+// y-DFT twiddles exp(-2 pi i j / Ny) (both on the device), and for lengths
+// Nx that are not transformed directly the chirp w_n = exp(-i pi n^2 / Nx)
+// (n^2 reduced modulo 2 Nx in integers) and G = FFT_L(conj(w) wrapped
+// circularly) / L of Bluestein's algorithm (host only).
+struct Tables3 {
+  std::vector<cplx> tw, wy, chirp, G;
+};
+
+Tables3 tables3(const bpm_plan* p) {
   const int N = p->Nx, L = p->L3, Ny = p->Ny;
-  std::vector<cplx> out;
-  out.reserve(size_t(N) + 2 * size_t(L) + Ny);
-  std::vector<cplx> w(N);
-  for (int n = 0; n < N; ++n) {
-    const long long m = (static_cast<long long>(n) * n) % (2LL * N);
-    const double ang = -M_PI * double(m) / double(N);
-    w[n] = cplx(std::cos(ang), std::sin(ang));
-  }
-  std::vector<cplx> h(L, cplx(0.0, 0.0));
-  if (p->bluestein) {
-    for (int m = 0; m < N; ++m) h[m] = std::conj(w[m]);
-    for (int m = 1; m < N; ++m) h[L - m] = std::conj(w[m]);
-    fft_host(h);
-    for (auto& v : h) v /= double(L);
-  }
-  out.insert(out.end(), w.begin(), w.end());
-  out.insert(out.end(), h.begin(), h.end());
+  Tables3 t;
+  t.tw.resize(L);
   for (int m = 0; m < L; ++m) {
     const double ang = -2.0 * M_PI * double(m) / double(L);
-    out.emplace_back(std::cos(ang), std::sin(ang));
+    t.tw[m] = cplx(std::cos(ang), std::sin(ang));
   }
+  t.wy.resize(Ny);
   for (int j = 0; j < Ny; ++j) {
     const double ang = -2.0 * M_PI * double(j) / double(Ny);
-    out.emplace_back(std::cos(ang), std::sin(ang));
+    t.wy[j] = cplx(std::cos(ang), std::sin(ang));
   }
-  return out;
+  if (p->bluestein) {
+    t.chirp.resize(N);
+    for (int n = 0; n < N; ++n) {
+      const long long m = (static_cast<long long>(n) * n) % (2LL * N);
+      const double ang = -M_PI * double(m) / double(N);
+      t.chirp[n] = cplx(std::cos(ang), std::sin(ang));
+    }
+    t.G.assign(L, cplx(0.0, 0.0));
+    for (int m = 0; m < N; ++m) t.G[m] = std::conj(t.chirp[m]);
+    for (int m = 1; m < N; ++m) t.G[L - m] = std::conj(t.chirp[m]);
+    fft_host(t.G.data(), L, t.tw.data());
+    for (auto& v : t.G) v /= double(L);
+  }
+  return t;
+}
+
+// Row tables Q = FFT_L(q) / L of a plan whose Nx is not transformed
+// directly, from its propagator rows P (length Nx, FP64): p = IDFT_Nx(P)
+// (unnormalised) = conj(DFT_Nx(conj(P))) by Bluestein's algorithm
+// (X_k = w_k (a * conj(w))_k, a_n = x_n w_n, the cyclic convolution on L),
+// then q_d = p_d and q_{L-Nx+d} = p_d (d >= 1), zero elsewhere.  Rows are
+// shared out over host threads.
+void rows3_bluestein(const bpm_plan* p, const Tables3& t, const std::vector<cplx>& P,
+                     std::vector<cplx>& Q) {
+  const int N = p->Nx;
+  const size_t L = size_t(p->L3);
+  const size_t rows = size_t(p->Nomega) * 2 * p->Ny;
+  Q.assign(rows * L, cplx(0.0, 0.0));
+  auto work = [&](size_t r0, size_t r1) {
+    std::vector<cplx> buf(L), q(L);
+    for (size_t r = r0; r < r1; ++r) {
+      const cplx* Pr = P.data() + r * N;
+      std::fill(buf.begin(), buf.end(), cplx(0.0, 0.0));
+      for (int n = 0; n < N; ++n) buf[n] = mul_h(std::conj(Pr[n]), t.chirp[n]);
+      fft_host(buf.data(), L, t.tw.data());
+      // conj of the unnormalised inverse transform: buf = conj(a * conj(w))
+      for (size_t j = 0; j < L; ++j) buf[j] = std::conj(mul_h(buf[j], t.G[j]));
+      fft_host(buf.data(), L, t.tw.data());
+      std::fill(q.begin(), q.end(), cplx(0.0, 0.0));
+      for (int d = 0; d < N; ++d) {
+        const cplx pd = mul_h(std::conj(t.chirp[d]), buf[d]);   // conj(X_d)
+        q[d] = pd;
+        if (d > 0) q[L - N + d] = pd;
+      }
+      fft_host(q.data(), L, t.tw.data());
+      cplx* Qr = Q.data() + r * L;
+      for (size_t j = 0; j < L; ++j) Qr[j] = q[j] / double(L);
+    }
+  };
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nt = std::min<size_t>({size_t(hw), size_t(16), rows});
+  std::vector<std::thread> pool;
+  for (size_t i = 1; i < nt; ++i)
+    pool.emplace_back(work, rows * i / nt, rows * (i + 1) / nt);
+  work(0, rows / nt);
+  for (auto& th : pool) th.join();
 }
 
 // Freeze the plan's host state on first use: constants computed once, no
@@ -180,12 +231,66 @@ int freeze_host_locked(bpm_plan* p) {
   return BPM_OK;
 }
 
-// Freeze the plan and upload its constants (and general mask) once.
-int freeze(bpm_plan* p) {
-  std::lock_guard<std::mutex> lock(p->mu);
-  int rc = freeze_host_locked(p);
-  if (rc != BPM_OK) return rc;
-  if (p->dev_sc) return BPM_OK;
+// Device tables of a 3D plan: twiddles and the row propagator tables
+// (rows of length L; for L = Nx the propagator itself, evaluated on the
+// device; otherwise Q from the device propagator via the host).  Uses the
+// null stream and waits for it.  Caller holds p->mu, after dev_sc.
+int upload_tables3(bpm_plan* p) {
+  const Tables3 t = tables3(p);
+  const size_t L = size_t(p->L3);
+  const size_t rows = size_t(p->Nomega) * 2 * p->Ny;
+  hipError_t e = hipMalloc(&p->dev_tables3, (L + t.wy.size()) * sizeof(cplx));
+  if (e != hipSuccess) {
+    p->dev_tables3 = nullptr;
+    return fail(BPM_ENOMEM, std::string("hipMalloc(3D tables): ") + hipGetErrorString(e));
+  }
+  cplx* dt = static_cast<cplx*>(p->dev_tables3);
+  e = hipMemcpy(dt, t.tw.data(), L * sizeof(cplx), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(dt + L, t.wy.data(), t.wy.size() * sizeof(cplx), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D tables)");
+  e = hipMalloc(&p->dev_rows3, rows * L * sizeof(cplx));
+  if (e != hipSuccess) {
+    p->dev_rows3 = nullptr;
+    return fail(BPM_ENOMEM, std::string("hipMalloc(3D row propagators): ") +
+                                hipGetErrorString(e));
+  }
+  void* P = p->dev_rows3;
+  if (p->bluestein) {
+    e = hipMalloc(&P, rows * size_t(p->Nx) * sizeof(cplx));
+    if (e != hipSuccess)
+      return fail(BPM_ENOMEM, std::string("hipMalloc(3D propagator): ") + hipGetErrorString(e));
+  }
+  int rc = bpm::launch_prop3(P, p->dev_sc, p->Nx, p->Ny, p->Nomega, p->dx, p->dy, p->dz,
+                             0.5 * p->h, nullptr);
+  if (rc == BPM_OK && p->bluestein) {
+    std::vector<cplx> hP(rows * size_t(p->Nx)), Q;
+    e = hipMemcpy(hP.data(), P, hP.size() * sizeof(cplx), hipMemcpyDeviceToHost);
+    (void)hipFree(P);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D propagator)");
+    rows3_bluestein(p, t, hP, Q);
+    e = hipMemcpy(p->dev_rows3, Q.data(), Q.size() * sizeof(cplx), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D row propagators)");
+  } else if (rc == BPM_OK) {
+    e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return hip_fail(e, "3D propagator table");
+  } else {
+    if (p->bluestein) (void)hipFree(P);
+    return fail(rc, "3D propagator table launch failed");
+  }
+  return BPM_OK;
+}
+
+// Frees whatever device copies of the plan exist.  Caller holds p->mu.
+void drop_device_locked(bpm_plan* p) {
+  for (void** q : {reinterpret_cast<void**>(&p->dev_sc), reinterpret_cast<void**>(&p->dev_mask),
+                   &p->dev_tables3, &p->dev_rows3}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+}
+
+int upload_locked(bpm_plan* p) {
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   e = hipMalloc(&p->dev_sc, sizeof(bpm::SliceConst) * p->Nomega);
@@ -206,17 +311,21 @@ int freeze(bpm_plan* p) {
     e = hipMemcpy(p->dev_mask, p->mask.data(), p->mask.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(crystal mask)");
   }
-  if (p->three_d && !p->dev_tables3) {
-    const std::vector<cplx> t = tables3(p);
-    e = hipMalloc(&p->dev_tables3, t.size() * sizeof(cplx));
-    if (e != hipSuccess) {
-      p->dev_tables3 = nullptr;
-      return fail(BPM_ENOMEM, std::string("hipMalloc(3D tables): ") + hipGetErrorString(e));
-    }
-    e = hipMemcpy(p->dev_tables3, t.data(), t.size() * sizeof(cplx), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D tables)");
-  }
+  if (p->three_d) return upload_tables3(p);
   return BPM_OK;
+}
+
+// Freeze the plan and upload its constants (general mask, 3D tables) once;
+// a failed upload leaves no device copy behind.
+int freeze(bpm_plan* p) {
+  std::lock_guard<std::mutex> lock(p->mu);
+  int rc = freeze_host_locked(p);
+  if (rc != BPM_OK) return rc;
+  if (p->dev_sc && (!p->three_d || p->dev_rows3)) return BPM_OK;
+  drop_device_locked(p);
+  rc = upload_locked(p);
+  if (rc != BPM_OK) drop_device_locked(p);
+  return rc;
 }
 
 // A 3D plan can only propagate whole marches (bpm_propagate, _ws).
@@ -226,13 +335,8 @@ int reject_3d(const bpm_plan* p, const char* what) {
   return BPM_OK;
 }
 
-// Propagator-table bytes of a 3D plan's workspace (256-byte aligned).
-size_t prop3_bytes(const bpm_plan* p) {
-  return (size_t(p->Nomega) * 2 * p->Ny * p->Nx * 16 + 255) & ~size_t(255);
-}
-
-// The whole 3D march: deformation table, propagator table, then the row
-// and column launches of every step (bpm3d.hip).
+// The whole 3D march: deformation table, then the row and column launches
+// of every step (bpm3d.hip).
 int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_out,
                void* Eh_out, void* workspace, hipStream_t s) {
   if (p->precision == BPM_PREC_FP64 && p->L3 > 8192)
@@ -243,7 +347,7 @@ int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_o
   char* ws = static_cast<char*>(workspace);
   void* table = nullptr;
   if (u_field) {
-    table = ws + prop3_bytes(p);
+    table = ws;
     rc = bpm::launch_deform(p->precision, p->Nx * p->Ny, p->Nz, p->h, u_field, table, s);
     if (rc) return fail(rc, "deformation pre-pass launch failed");
   }
@@ -255,11 +359,7 @@ int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_o
   q.Nz = p->Nz;
   q.Nomega = p->Nomega;
   q.L = p->L3;
-  q.bluestein = p->bluestein;
   q.dx = p->dx;
-  q.dy = p->dy;
-  q.dz = p->dz;
-  q.h_half = 0.5 * p->h;
   q.x_front = p->x_front;
   q.x_end = p->x_front + p->thickness;
   q.E0_in = E0_in;
@@ -267,11 +367,9 @@ int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_o
   q.Eh_out = Eh_out;
   q.table = table;
   q.sc = p->dev_sc;
-  q.P = ws;
-  q.chirp = t3;
-  q.G = t3 + p->Nx;
-  q.tw = t3 + p->Nx + p->L3;
-  q.wy = t3 + p->Nx + 2 * size_t(p->L3);
+  q.rows = p->dev_rows3;
+  q.tw = t3;
+  q.wy = t3 + p->L3;
   rc = bpm::launch_march3(q, s);
   if (rc == BPM_EUNSUPPORTED) return fail(rc, "unsupported 3D size/precision");
   if (rc) return fail(rc, "3D march launch failed");
@@ -726,8 +824,7 @@ int bpm_plan_get_constants(const bpm_plan* cp, int w, double* out) {
 size_t bpm_workspace_bytes(const bpm_plan* p) {
   if (!p) return 0;
   const size_t cell = p->precision == BPM_PREC_FP64 ? 16 : 8;
-  if (p->three_d)
-    return prop3_bytes(p) + size_t(p->Nx) * size_t(p->Ny) * size_t(p->Nz) * cell;
+  if (p->three_d) return size_t(p->Nx) * size_t(p->Ny) * size_t(p->Nz) * cell;
   return size_t(p->Nx) * size_t(p->Nz) * cell;
 }
 
@@ -828,7 +925,7 @@ int bpm_propagate_ws(const bpm_plan* cp, const void* E0_in,
   if (E0_in == E0_out || E0_in == Eh_out || E0_out == Eh_out)
     return fail(BPM_EINVAL, "output buffers must not alias each other or E0_in");
   if (cp->three_d) {
-    if (!workspace) return fail(BPM_EINVAL, "a 3D propagate needs a workspace");
+    if (u_field && !workspace) return fail(BPM_EINVAL, "a deformed propagate needs a workspace");
     return propagate3(const_cast<bpm_plan*>(cp), E0_in, u_field, E0_out, Eh_out, workspace,
                       static_cast<hipStream_t>(stream));
   }
@@ -848,9 +945,8 @@ int bpm_propagate(const bpm_plan* p, const void* E0_in, const double* u_field,
   if (!p) return fail(BPM_EINVAL, "plan is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* ws = nullptr;
-  if (u_field || p->three_d) {
-    const size_t bytes = p->three_d && !u_field ? prop3_bytes(p) : bpm_workspace_bytes(p);
-    hipError_t e = hipMallocAsync(&ws, bytes, s);
+  if (u_field) {
+    hipError_t e = hipMallocAsync(&ws, bpm_workspace_bytes(p), s);
     if (e != hipSuccess)
       return fail(BPM_ENOMEM, std::string("hipMallocAsync(workspace): ") +
                                   hipGetErrorString(e));
@@ -923,6 +1019,7 @@ int bpm_propagate_batch(const bpm_job* jobs, int njobs, void* stream) {
 void bpm_plan_destroy(bpm_plan* p) {
   if (!p) return;
   if (p->dev_tables3) (void)hipFree(p->dev_tables3);
+  if (p->dev_rows3) (void)hipFree(p->dev_rows3);
   if (p->dev_sc) (void)hipFree(p->dev_sc);
   if (p->dev_mask) (void)hipFree(p->dev_mask);
   delete p;

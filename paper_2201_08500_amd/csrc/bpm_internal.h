@@ -89,19 +89,20 @@ int default_schedule(int prec, int Nx);
 // wy [Ny] are the plan's FP64 tables (complex, interleaved).
 struct March3Params {
   int prec, Nx, Ny, Nz, Nomega, L;
-  bool bluestein;
-  double dx, dy, dz, h_half, x_front, x_end;
+  double dx, x_front, x_end;
   const void* E0_in;
   void* E0_out;
   void* Eh_out;
   const void* table;        // [Nz][Ny][Nx] exp(i h u), or nullptr
   const SliceConst* sc;
-  void* P;
-  const void* chirp;
-  const void* G;
-  const void* tw;
-  const void* wy;
+  const void* rows;         // [Nomega][2][Ny][L] row propagator (FP64)
+  const void* tw;           // [L] exp(-2 pi i m / L)
+  const void* wy;           // [Ny] exp(-2 pi i j / Ny)
 };
+// The FP64 propagator exp(i dz kz(K_x, K_y)) / (Nx Ny) of every (slice,
+// envelope, K_y, K_x), rows of length Nx, into P (device).
+int launch_prop3(void* P, const SliceConst* sc, int Nx, int Ny, int Nomega, double dx,
+                 double dy, double dz, double h_half, hipStream_t stream);
 int launch_march3(const March3Params& q, hipStream_t stream);
 
 }  // namespace bpm
@@ -145,7 +146,8 @@ struct bpm_plan {
   double dy = 0.0;
   int L3 = 0;
   bool bluestein = false;
-  void* dev_tables3 = nullptr;          // chirp [Nx], G [L], tw [L], wy [Ny]
+  void* dev_tables3 = nullptr;          // tw [L], wy [Ny]
+  void* dev_rows3 = nullptr;            // [Nomega][2][Ny][L] row propagator
   int device = -1;
   bool frozen = false;                   // constants computed, setters closed
   std::mutex mu;
