@@ -44,11 +44,16 @@ BPM_INLINE void phase_fence() { asm volatile("" ::: "memory"); }
 // registers per pass), spilling.
 BPM_INLINE int opaque(int v) {
   asm volatile("" : "+v"(v));
+  __builtin_assume(v >= 0);
   return v;
 }
 
 // Twiddle W_{Ns Rp}^{r j} of pass P of transform M as W_L^{r j L/(Ns Rp)}
-// from the table tab[m] = exp(-2 pi i m / L), loaded where it is used.
+// from the table tab[m] = exp(-2 pi i m / L), loaded where it is used.  The
+// thread index is opaque per pass (kOpaqueIndex), so a pass's loads can be
+// neither hoisted into an earlier pass nor shared with another transform;
+// within a pass, the butterflies s of a thread share j while Ns <= T, and
+// their loads are one.
 template <class M>
 struct TwGlobal {
   static constexpr bool kOpaqueIndex = true;
@@ -57,8 +62,7 @@ struct TwGlobal {
   BPM_INLINE Tw<typename M::CT> get(int t, int s, int r) const {
     constexpr int Ns = M::ns(P);
     constexpr int Rp = M::rad[P];
-    const int j = (t + s * M::T) & (Ns - 1);
-    phase_fence();
+    const int j = (Ns <= M::T ? t : t + s * M::T) & (Ns - 1);
     return Tw<typename M::CT>{tab[(r * j) * (M::N / (Ns * Rp))]};
   }
 };

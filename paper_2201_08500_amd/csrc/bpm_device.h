@@ -417,7 +417,10 @@ struct wants_opaque<TWS, std::void_t<decltype(TWS::kOpaqueIndex)>>
     : std::integral_constant<bool, TWS::kOpaqueIndex> {};
 template <class TWS>
 BPM_INLINE int opaque_index(int t) {
-  if constexpr (wants_opaque<TWS>::value) asm volatile("" : "+v"(t));
+  if constexpr (wants_opaque<TWS>::value) {
+    asm volatile("" : "+v"(t));
+    __builtin_assume(t >= 0);     // a thread index: divisions become shifts
+  }
   return t;
 }
 
