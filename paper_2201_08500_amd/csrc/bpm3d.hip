@@ -49,12 +49,12 @@ BPM_INLINE int opaque(int v) {
 }
 
 // Twiddle W_{Ns Rp}^{r j} of pass P of transform M as W_L^{r j L/(Ns Rp)}
-// from the table tab[m] = exp(-2 pi i m / L), loaded where it is used.  The
+// from the table tab[m] = exp(-2 pi i m / NT), loaded where it is used.  The
 // thread index is opaque per pass (kOpaqueIndex), so a pass's loads can be
 // neither hoisted into an earlier pass nor shared with another transform;
 // within a pass, the butterflies s of a thread share j while Ns <= T, and
 // their loads are one.
-template <class M>
+template <class M, int NT = M::N>   // NT: table length, a multiple of M::N
 struct TwGlobal {
   static constexpr bool kOpaqueIndex = true;
   const cx<double>* tab;
@@ -63,7 +63,7 @@ struct TwGlobal {
     constexpr int Ns = M::ns(P);
     constexpr int Rp = M::rad[P];
     const int j = (Ns <= M::T ? t : t + s * M::T) & (Ns - 1);
-    return Tw<typename M::CT>{tab[(r * j) * (M::N / (Ns * Rp))]};
+    return Tw<typename M::CT>{tab[(r * j) * (NT / (Ns * Rp))]};
   }
 };
 
@@ -175,6 +175,187 @@ __global__ void __launch_bounds__(M::T) row3_kernel(Row3Params p) {
       line[n] = s;
     }
   }
+}
+
+// W16^{j} (INV: conjugated) for an index that is constant once the loops
+// around it are unrolled.
+template <bool INV, class T>
+BPM_INLINE cx<T> tw16_at(cx<T> a, int j) {
+  switch (j & 15) {
+    case 0: return a;
+    case 1: return tw16<1, INV>(a);
+    case 2: return tw16<2, INV>(a);
+    case 3: return tw16<3, INV>(a);
+    case 4: return tw16<4, INV>(a);
+    case 6: return tw16<6, INV>(a);
+    case 9: return tw16<9, INV>(a);
+    default: return tw16<15, INV>(tw16<1, INV>(tw16<15, INV>(a)));  // not reached
+  }
+}
+
+// Long rows (L = 8192, 16384) in the four-step layout of the 2D march:
+// L = W M with an M-point in-wavefront transform In, T = 64 W threads;
+// thread t owns m_j = t + T j (j < J = R / W) and holds x[m_j + M q] in
+// slot j + J q.  Forward: the radix-W DFT over q in registers, the twiddle
+// W_L^{m k1}, one block exchange that gives wavefront k1 the M values of
+// its k1 (lane l, slot i <- m = l + 64 i), then the in-wavefront transform,
+// whose exchanges need no barrier.  Slot i of lane l of wavefront w ends
+// with bin K = w + W (l + 64 i); the inverse runs the steps backwards.  Two
+// work-group barriers per row step instead of one or two per Stockham pass.
+// Each wavefront's region of LDS is first the target of the block exchange
+// and then its own exchange buffer.
+template <class In_, int W>
+struct RowFour {
+  using In = In_;
+  using CT = typename In::CT;
+  using ST = typename In::ST;
+  using SV = typename In::SV;
+  static constexpr int M = In::N, R = In::R, N = W * M, T = 64 * W, J = R / W;
+  static_assert(In::T == 64 && R % W == 0, "one wavefront per in-wave transform, R a multiple of W");
+  static constexpr int kRegion = In::kEnv;
+  static constexpr size_t kLdsSlots = size_t(W) * kRegion;
+  static_assert(kLdsSlots * sizeof(SV) <= 160 * 1024, "row does not fit in LDS");
+
+  BPM_INLINE static void put(SV* lds, int idx, cx<CT> v) {
+    SV s;
+    s.x = static_cast<ST>(v.x);
+    s.y = static_cast<ST>(v.y);
+    lds[idx] = s;
+  }
+
+  // W = 16 (J = 1), forward: the radix-16 DFT over q as 4 x 4 (q = 4 n1 +
+  // n2, K = k1 + 4 k2), the inner results rounded to the storage type in
+  // the state's own slots, so that at most four values are live in the
+  // arithmetic type (all sixteen in FP64 here spill at the 128 registers of
+  // a 1024-thread work group; in the inverse they do not, and the inverse
+  // keeps the plain radix-16 DFT).
+  BPM_INLINE static void forward16(cx<ST> (&v)[1][R], const cx<double>* tab, SV* lds, int t_in) {
+    // opaque: the twiddle addresses are formed here, not shared with the
+    // inverse and kept live across the whole row step
+    const int t = opaque(t_in);
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cx<CT> a[4];
+#pragma unroll
+      for (int n1 = 0; n1 < 4; ++n1) a[n1] = conv<CT>(v[0][4 * n1 + n2]);
+      dft4<false>(a[0], a[1], a[2], a[3]);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) v[0][4 * k1 + n2] = conv<ST>(tw16_at<false>(a[k1], n2 * k1));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cx<CT> b[4];
+#pragma unroll
+      for (int n2 = 0; n2 < 4; ++n2) b[n2] = conv<CT>(v[0][4 * k1 + n2]);
+      dft4<false>(b[0], b[1], b[2], b[3]);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) {
+        const int K = k1 + 4 * k2;
+        put(lds + K * kRegion, t, K ? Tw<CT>{tab[t * K]}.mul(b[k2]) : b[k2]);
+      }
+    }
+  }
+  BPM_INLINE static void forward(cx<ST> (&v)[1][R], const cx<double>* tab, SV* lds, int t) {
+    const int l = t & 63;
+    SV* own = lds + (t >> 6) * kRegion;
+    if constexpr (W == 16) forward16(v, tab, lds, t);
+    else
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int m = opaque(t) + T * j;
+      cx<CT> va[W];
+#pragma unroll
+      for (int q = 0; q < W; ++q) va[q] = conv<CT>(v[0][j + J * q]);
+      dft<W, false>(va);
+#pragma unroll
+      for (int k1 = 0; k1 < W; ++k1) {
+        if (k1 > 0) va[k1] = Tw<CT>{tab[m * k1]}.mul(va[k1]);
+        put(lds + k1 * kRegion, m, va[k1]);
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[0][i] = In::template load_as<ST>(own, l + 64 * i);
+    wave_sync();
+    int xbuf = 0;
+    In::template fft_n<false, In::kWave, 1>(v, TwGlobal<In, N>{tab}, own, opaque(l), xbuf);
+  }
+
+  BPM_INLINE static void inverse(cx<ST> (&v)[1][R], const cx<double>* tab, SV* lds, int t) {
+    const int l = t & 63;
+    SV* own = lds + (t >> 6) * kRegion;
+    int xbuf = 0;
+    In::template fft_n<true, In::kWave, 1>(v, TwGlobal<In, N>{tab}, own, opaque(l), xbuf);
+#pragma unroll
+    for (int i = 0; i < R; ++i) put(own, l + 64 * i, conv<CT>(v[0][i]));
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int m = opaque(t) + T * j;
+      cx<CT> va[W];
+#pragma unroll
+      for (int k1 = 0; k1 < W; ++k1) {
+        va[k1] = In::template load_as<CT>(lds + k1 * kRegion, m);
+        if (k1 > 0) va[k1] = Tw<CT>{tab[m * k1]}.mulc(va[k1]);
+      }
+      dft<W, true>(va);
+#pragma unroll
+      for (int q = 0; q < W; ++q) v[0][j + J * q] = conv<ST>(va[q]);
+    }
+  }
+};
+
+// One row per work group with the four-step transform: Q holds each row's
+// table in the kernel's bin order, Q[i T + t] = row bin w + W (l + 64 i) of
+// thread t = 64 w + l, so its loads are contiguous.
+template <class F>
+__global__ void __launch_bounds__(F::T) row3_four_kernel(Row3Params p) {
+  using ST = typename F::ST;
+  using SV = typename F::SV;
+  constexpr int R = F::R, T = F::T, M = F::M, J = F::J, W = F::N / F::M;
+  __shared__ __align__(16) SV lds[F::kLdsSlots];
+  const int t = threadIdx.x;
+  const int row = blockIdx.x;
+  const int ky = row % p.Ny;
+  const int env = (row / p.Ny) & 1;
+  const int w = row / (2 * p.Ny);
+  SV* line = static_cast<SV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
+  const cx<double>* Qrow = p.Q + size_t(row) * F::N;
+  cx<ST> v[1][R];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const int n = t + T * j + M * q;
+      SV s;
+      s.x = 0;
+      s.y = 0;
+      if (n < p.Nx) s = line[n];
+      v[0][j + J * q] = {s.x, s.y};
+    }
+  F::forward(v, p.tw, lds, t);
+  phase_fence();
+  const int tq = opaque(t);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (i % 4 == 0) phase_fence();     // table loads in groups of four
+    v[0][i] = conv<ST>(cmul(to_d(v[0][i]), Qrow[i * T + tq]));
+  }
+  phase_fence();
+  F::inverse(v, p.tw, lds, t);
+  const int ts = opaque(t);   // store addresses formed here, not kept from the loads
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const int n = ts + T * j + M * q;
+      if (n < p.Nx) {
+        SV s;
+        s.x = v[0][j + J * q].x;
+        s.y = v[0][j + J * q].y;
+        line[n] = s;
+      }
+    }
 }
 
 struct Col3Params {
@@ -291,8 +472,8 @@ template <int PREC> struct Row3T<PREC, 512> { using type = March<PREC, 512, 8, 8
 template <int PREC> struct Row3T<PREC, 1024> { using type = March<PREC, 1024, 8, 8, 8, 4, 4>; };
 template <int PREC> struct Row3T<PREC, 2048> { using type = March<PREC, 2048, 8, 8, 8, 8, 4>; };
 template <int PREC> struct Row3T<PREC, 4096> { using type = March<PREC, 4096, 8, 8, 8, 8, 8>; };
-template <int PREC> struct Row3T<PREC, 8192> { using type = March<PREC, 8192, 16, 8, 8, 8, 4, 4>; };
-template <int PREC> struct Row3T<PREC, 16384> { using type = March<PREC, 16384, 16, 8, 8, 8, 8, 4>; };
+template <int PREC> struct Row3T<PREC, 8192> { using type = RowFour<InWave1024<PREC>, 8>; };
+template <int PREC> struct Row3T<PREC, 16384> { using type = RowFour<InWave1024<PREC>, 16>; };
 
 template <int PREC, int L>
 int launch_row3_l(int rows, const Row3Params& p, hipStream_t s) {
@@ -300,7 +481,10 @@ int launch_row3_l(int rows, const Row3Params& p, hipStream_t s) {
   if constexpr ((PREC == BPM_PREC_FP64 ? 2 : 1) * L > 16384) {
     return BPM_EUNSUPPORTED;   // an FP64 row of this length does not fit in LDS
   } else {
-    hipLaunchKernelGGL((row3_kernel<M>), dim3(rows), dim3(M::T), 0, s, p);
+    if constexpr (L >= kRow3FourStepMin)
+      hipLaunchKernelGGL((row3_four_kernel<M>), dim3(rows), dim3(M::T), 0, s, p);
+    else
+      hipLaunchKernelGGL((row3_kernel<M>), dim3(rows), dim3(M::T), 0, s, p);
     return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
   }
 }

@@ -231,10 +231,25 @@ int freeze_host_locked(bpm_plan* p) {
   return BPM_OK;
 }
 
+// Rows of length L >= kRow3FourStepMin are read by the four-step row
+// kernel in its bin order: entry i T + t of a row is bin w + W (l + 64 i)
+// of thread t = 64 w + l (W = L / 1024, T = 64 W, i < 16).
+void permute_rows3(std::vector<cplx>& Q, size_t rows, int L) {
+  const int W = L / 1024, T = 64 * W, R = L / T;
+  std::vector<cplx> tmp(L);
+  for (size_t r = 0; r < rows; ++r) {
+    cplx* q = Q.data() + r * size_t(L);
+    for (int i = 0; i < R; ++i)
+      for (int t = 0; t < T; ++t) tmp[size_t(i) * T + t] = q[(t >> 6) + W * ((t & 63) + 64 * i)];
+    std::copy(tmp.begin(), tmp.end(), q);
+  }
+}
+
 // Device tables of a 3D plan: twiddles and the row propagator tables
 // (rows of length L; for L = Nx the propagator itself, evaluated on the
-// device; otherwise Q from the device propagator via the host).  Uses the
-// null stream and waits for it.  Caller holds p->mu, after dev_sc.
+// device; otherwise Q from the device propagator via the host; long rows
+// permuted to the four-step bin order).  Uses the null stream and waits for
+// it.  Caller holds p->mu, after dev_sc.
 int upload_tables3(bpm_plan* p) {
   const Tables3 t = tables3(p);
   const size_t L = size_t(p->L3);
@@ -255,29 +270,37 @@ int upload_tables3(bpm_plan* p) {
     return fail(BPM_ENOMEM, std::string("hipMalloc(3D row propagators): ") +
                                 hipGetErrorString(e));
   }
+  // The propagator is evaluated on the device; the rows go through the host
+  // when they need the cyclic-convolution table or the four-step bin order.
+  const bool via_host = p->bluestein || p->L3 >= bpm::kRow3FourStepMin;
   void* P = p->dev_rows3;
-  if (p->bluestein) {
+  if (via_host) {
     e = hipMalloc(&P, rows * size_t(p->Nx) * sizeof(cplx));
     if (e != hipSuccess)
       return fail(BPM_ENOMEM, std::string("hipMalloc(3D propagator): ") + hipGetErrorString(e));
   }
   int rc = bpm::launch_prop3(P, p->dev_sc, p->Nx, p->Ny, p->Nomega, p->dx, p->dy, p->dz,
                              0.5 * p->h, nullptr);
-  if (rc == BPM_OK && p->bluestein) {
-    std::vector<cplx> hP(rows * size_t(p->Nx)), Q;
-    e = hipMemcpy(hP.data(), P, hP.size() * sizeof(cplx), hipMemcpyDeviceToHost);
-    (void)hipFree(P);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D propagator)");
-    rows3_bluestein(p, t, hP, Q);
-    e = hipMemcpy(p->dev_rows3, Q.data(), Q.size() * sizeof(cplx), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D row propagators)");
-  } else if (rc == BPM_OK) {
-    e = hipStreamSynchronize(nullptr);
-    if (e != hipSuccess) return hip_fail(e, "3D propagator table");
-  } else {
-    if (p->bluestein) (void)hipFree(P);
+  if (rc != BPM_OK) {
+    if (via_host) (void)hipFree(P);
     return fail(rc, "3D propagator table launch failed");
   }
+  if (!via_host) {
+    e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return hip_fail(e, "3D propagator table");
+    return BPM_OK;
+  }
+  std::vector<cplx> hP(rows * size_t(p->Nx)), Q;
+  e = hipMemcpy(hP.data(), P, hP.size() * sizeof(cplx), hipMemcpyDeviceToHost);
+  (void)hipFree(P);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D propagator)");
+  if (p->bluestein)
+    rows3_bluestein(p, t, hP, Q);
+  else
+    Q.swap(hP);
+  if (p->L3 >= bpm::kRow3FourStepMin) permute_rows3(Q, rows, p->L3);
+  e = hipMemcpy(p->dev_rows3, Q.data(), Q.size() * sizeof(cplx), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D row propagators)");
   return BPM_OK;
 }
 

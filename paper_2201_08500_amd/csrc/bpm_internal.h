@@ -104,6 +104,11 @@ struct March3Params {
 int launch_prop3(void* P, const SliceConst* sc, int Nx, int Ny, int Nomega, double dx,
                  double dy, double dz, double h_half, hipStream_t stream);
 int launch_march3(const March3Params& q, hipStream_t stream);
+// Row lengths from which the 3D row kernel uses the four-step layout
+// (W = L / 1024 wavefronts, 1024-point in-wavefront transforms): its row
+// tables are stored with entry i T + t holding bin w + W (l + 64 i) of
+// thread t = 64 w + l, T = 64 W, i < 16.
+constexpr int kRow3FourStepMin = 8192;
 
 }  // namespace bpm
 

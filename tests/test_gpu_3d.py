@@ -93,6 +93,16 @@ def test_3d_undeformed_and_long_rows():
     check3(w, "fp32s")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32s", "fp32"])
+def test_3d_four_step_rows(prec):
+    """Rows of 8192 and 16384 samples run in the four-step row kernel, whose
+    tables are stored in its bin order: a power of two Nx = 8192 (L = Nx)
+    and, where LDS allows (not FP64), Nx = 5000 (L = 16384)."""
+    check3(W.small3d(Nx=8192, Ny=2, Nz=6, Nomega=1, seed=8), prec)
+    if prec != "fp64":
+        check3(W.small3d(Nx=5000, Ny=3, Nz=5, Nomega=2, seed=9), prec)
+
+
 def test_3d_one_row_matches_the_2d_march():
     """Ny = 1 on a power-of-two x grid: the 3D kernels and the 2D march
     compute the same problem (different transforms, so to rounding)."""
