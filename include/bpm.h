@@ -109,7 +109,7 @@ bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
  * else the smallest L >= max(2 Nx - 1, 64), Ny in [1, 32]; BPM_PREC_FP64
  * needs L <= 8192 (otherwise the propagate returns BPM_EUNSUPPORTED).  On
  * its first propagate the plan builds and keeps on the device FP64 row
- * tables of 32 Nomega Ny L bytes (for L != Nx with host FFTs of the
+ * tables of 32 Nomega (Ny/2 + 1) L bytes (for L != Nx with host FFTs of the
  * device-evaluated propagator, once).  Other arguments and defaults as
  * bpm_plan_create.  A 3D plan supports bpm_propagate, bpm_propagate_ws (the
  * workspace holds the deformation table, as for a 2D plan), the precision,

@@ -97,29 +97,39 @@ __device__ cx<double> propagator3(int mx, int my, int Nx, int Ny, double dx, dou
   return {c * inv_n, s * inv_n};
 }
 
-// Propagator table P[((w * 2 + env) * Ny + ky) * Nx + kx], one thread per
-// entry (grid-stride).
+// Propagator table P[((w * 2 + env) * Nyc + c) * Nx + kx], Nyc = Ny / 2 + 1
+// rows per (slice, envelope): the propagator depends on K_y only through
+// K_y^2, so row c serves the bins K_y = +-2 pi c / (Ny dy), i.e. ky = c and
+// ky = Ny - c.  One thread per entry (grid-stride).
 __global__ void prop3_kernel(cx<double>* __restrict__ P, const SliceConst* __restrict__ sc,
                              int Nx, int Ny, int Nomega, double dx, double dy, double dz,
                              double h_half) {
-  const size_t n = size_t(Nomega) * 2 * Ny * Nx;
+  const int Nyc = Ny / 2 + 1;
+  const size_t n = size_t(Nomega) * 2 * Nyc * Nx;
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
        i += size_t(gridDim.x) * blockDim.x) {
     const int kx = static_cast<int>(i % Nx);
     const size_t r = i / Nx;
-    const int ky = static_cast<int>(r % Ny);
-    const int env = static_cast<int>((r / Ny) & 1);
-    const int w = static_cast<int>(r / (2 * size_t(Ny)));
+    const int c = static_cast<int>(r % Nyc);
+    const int env = static_cast<int>((r / Nyc) & 1);
+    const int w = static_cast<int>(r / (2 * size_t(Nyc)));
     const int mx = kx < (Nx + 1) / 2 ? kx : kx - Nx;
-    const int my = ky < (Ny + 1) / 2 ? ky : ky - Ny;
-    P[i] = propagator3(mx, my, Nx, Ny, dx, dy, sc[w].k, h_half, env ? -1.0 : 1.0, dz);
+    P[i] = propagator3(mx, c, Nx, Ny, dx, dy, sc[w].k, h_half, env ? -1.0 : 1.0, dz);
   }
+}
+
+// Row r = (w * 2 + env) * Ny + ky of the state uses table row
+// (w * 2 + env) * Nyc + min(ky, Ny - ky).
+BPM_INLINE int table_row(int row, int Ny) {
+  const int ky = row % Ny;
+  const int c = ky <= Ny - ky ? ky : Ny - ky;
+  return (row / Ny) * (Ny / 2 + 1) + c;
 }
 
 struct Row3Params {
   void* a;                    // psi~_+ state [Nomega][Ny][Nx] (storage type)
   void* b;                    // psi~_- state
-  const cx<double>* Q;        // [Nomega][2][Ny][L] row propagator
+  const cx<double>* Q;        // [Nomega][2][Ny / 2 + 1][L] row propagator
   const cx<double>* tw;       // [L] exp(-2 pi i m / L)
   int Nx, Ny;
 };
@@ -143,7 +153,7 @@ __global__ void __launch_bounds__(M::T) row3_kernel(Row3Params p) {
   const int env = (row / p.Ny) & 1;
   const int w = row / (2 * p.Ny);
   SV* line = static_cast<SV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
-  const cx<double>* Qrow = p.Q + size_t(row) * M::N;
+  const cx<double>* Qrow = p.Q + size_t(table_row(row, p.Ny)) * M::N;
   const TwGlobal<M> tws{p.tw};
   int xbuf = 0;
   cx<CT> v[1][R];
@@ -320,7 +330,7 @@ __global__ void __launch_bounds__(F::T) row3_four_kernel(Row3Params p) {
   const int env = (row / p.Ny) & 1;
   const int w = row / (2 * p.Ny);
   SV* line = static_cast<SV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
-  const cx<double>* Qrow = p.Q + size_t(row) * F::N;
+  const cx<double>* Qrow = p.Q + size_t(table_row(row, p.Ny)) * F::N;
   cx<ST> v[1][R];
 #pragma unroll
   for (int j = 0; j < J; ++j)
@@ -509,7 +519,7 @@ int launch_row3_p(int L, int rows, const Row3Params& p, hipStream_t s) {
 
 int launch_prop3(void* P, const SliceConst* sc, int Nx, int Ny, int Nomega, double dx,
                  double dy, double dz, double h_half, hipStream_t s) {
-  const size_t n = size_t(Nomega) * 2 * Ny * Nx;
+  const size_t n = size_t(Nomega) * 2 * (Ny / 2 + 1) * Nx;
   const int block = 256;
   const size_t want = (n + block - 1) / block;
   const int grid = static_cast<int>(want < 8192 ? want : 8192);

@@ -189,7 +189,7 @@ void rows3_bluestein(const bpm_plan* p, const Tables3& t, const std::vector<cplx
                      std::vector<cplx>& Q) {
   const int N = p->Nx;
   const size_t L = size_t(p->L3);
-  const size_t rows = size_t(p->Nomega) * 2 * p->Ny;
+  const size_t rows = size_t(p->Nomega) * 2 * (p->Ny / 2 + 1);   // table rows
   Q.assign(rows * L, cplx(0.0, 0.0));
   auto work = [&](size_t r0, size_t r1) {
     std::vector<cplx> buf(L), q(L);
@@ -253,7 +253,7 @@ void permute_rows3(std::vector<cplx>& Q, size_t rows, int L) {
 int upload_tables3(bpm_plan* p) {
   const Tables3 t = tables3(p);
   const size_t L = size_t(p->L3);
-  const size_t rows = size_t(p->Nomega) * 2 * p->Ny;
+  const size_t rows = size_t(p->Nomega) * 2 * (p->Ny / 2 + 1);   // table rows
   hipError_t e = hipMalloc(&p->dev_tables3, (L + t.wy.size()) * sizeof(cplx));
   if (e != hipSuccess) {
     p->dev_tables3 = nullptr;

@@ -95,12 +95,13 @@ struct March3Params {
   void* Eh_out;
   const void* table;        // [Nz][Ny][Nx] exp(i h u), or nullptr
   const SliceConst* sc;
-  const void* rows;         // [Nomega][2][Ny][L] row propagator (FP64)
+  const void* rows;         // [Nomega][2][Ny / 2 + 1][L] row propagator (FP64)
   const void* tw;           // [L] exp(-2 pi i m / L)
   const void* wy;           // [Ny] exp(-2 pi i j / Ny)
 };
 // The FP64 propagator exp(i dz kz(K_x, K_y)) / (Nx Ny) of every (slice,
-// envelope, K_y, K_x), rows of length Nx, into P (device).
+// envelope, |K_y|, K_x): Nomega x 2 x (Ny / 2 + 1) rows of length Nx, into P
+// (device).
 int launch_prop3(void* P, const SliceConst* sc, int Nx, int Ny, int Nomega, double dx,
                  double dy, double dz, double h_half, hipStream_t stream);
 int launch_march3(const March3Params& q, hipStream_t stream);
@@ -152,7 +153,7 @@ struct bpm_plan {
   int L3 = 0;
   bool bluestein = false;
   void* dev_tables3 = nullptr;          // tw [L], wy [Ny]
-  void* dev_rows3 = nullptr;            // [Nomega][2][Ny][L] row propagator
+  void* dev_rows3 = nullptr;            // [Nomega][2][Ny / 2 + 1][L] row propagator
   int device = -1;
   bool frozen = false;                   // constants computed, setters closed
   std::mutex mu;
