@@ -9,7 +9,7 @@
 //   row kernel    -- one work group per (slice, envelope, K_y) row: FFT along
 //                    x, the band propagator exp(i dz sqrt(k^2 - (K_x +- h/2)^2
 //                    - K_y^2)) / (Nx Ny), inverse FFT along x, in place;
-//   column kernel -- 32 x-columns x Ny threads per work group: inverse DFT
+//   column kernel -- 64 x-columns x Ny/2 threads per work group: inverse DFT
 //                    along y (back to x space), the coupling of the step with
 //                    the deformation row and the slab, forward DFT along y
 //                    for the next step (the last step stores x space).
@@ -380,96 +380,134 @@ struct Col3Params {
   double dx, x_front, x_end;
 };
 
-constexpr int kCol = 32;      // x-columns per work group
+constexpr int kCol = 64;      // x-columns per work group (one wavefront per row pair)
 constexpr int kMaxNy = 32;
 
-// blockDim = (32, Ny), grid = (ceil(Nx / 32), Nomega).  Thread (xl, i)
-// holds sample y_i (x space) or bin K_y = i of column x of both envelopes.
+// blockDim = (64, H), H = (Ny + 1) / 2, grid = (ceil(Nx / 64), Nomega).
+// Thread (xl, r) holds rows y = r and r + H (the second while < Ny) of
+// column x of both envelopes: samples in x space, bins K_y in k space.  All
+// lanes of a wavefront share r, so each DFT twiddle is one wavefront-wide
+// value, and every input read from LDS serves both of the thread's outputs.
 template <class ST>
-__global__ void __launch_bounds__(kCol * kMaxNy) col3_kernel(Col3Params p) {
+__global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
   using SV = typename vec2<ST>::type;
   __shared__ cx<double> sa[kMaxNy * kCol];
   __shared__ cx<double> sb[kMaxNy * kCol];
-  __shared__ cx<double> sw[kMaxNy];
-  const int xl = threadIdx.x, i = threadIdx.y;
+  const int xl = threadIdx.x;
+  const int Ny = p.Ny, H = (Ny + 1) / 2;
+  const int i0 = __builtin_amdgcn_readfirstlane(threadIdx.y);   // blockDim.x = 64
+  const int i1 = i0 + H;
+  const bool two = i1 < Ny;
   const int x = blockIdx.x * kCol + xl;
   const int w = blockIdx.y;
-  const int Ny = p.Ny;
   const bool valid = x < p.Nx;
-  const size_t at = (size_t(w) * Ny + i) * p.Nx + x;
-  if (i == 0 && xl < Ny) sw[xl] = p.wy[xl];
-  cx<double> ax = {0.0, 0.0}, bx = {0.0, 0.0};
+  const size_t at0 = (size_t(w) * Ny + i0) * p.Nx + x;
+  const size_t at1 = (size_t(w) * Ny + i1) * p.Nx + x;
+  auto ld = [](const void* f, size_t i) -> cx<double> {
+    const SV s = static_cast<const SV*>(f)[i];
+    return {static_cast<double>(s.x), static_cast<double>(s.y)};
+  };
+  auto st = [](void* f, size_t i, cx<double> v) {
+    SV s;
+    s.x = static_cast<ST>(v.x);
+    s.y = static_cast<ST>(v.y);
+    static_cast<SV*>(f)[i] = s;
+  };
+  // coupling of step n inside the slab (Eq. fov10, Eq. Authier) at (x, y_i)
+  const double xp = static_cast<double>(x - p.Nx / 2) * p.dx;
+  const bool inside = valid && xp >= p.x_front && xp < p.x_end;
+  auto couple = [&](cx<double>& a, cx<double>& b, int i) {
+    const SliceConst& c = p.sc[w];
+    const cx<double> d0 = {c.d[0][0], c.d[0][1]};
+    cx<double> cp = {c.d[0][2], c.d[0][3]}, cm = {c.d[0][4], c.d[0][5]};
+    if (p.table) {
+      const cx<double> e = ld(p.table, (size_t(p.n) * Ny + i) * p.Nx + x);
+      cp = cmul(cp, e);
+      cm = cmulc(cm, e);
+    }
+    const cx<double> a0 = a;
+    a = cmuladd(d0, a0, cp, b);
+    b = cmuladd(d0, b, cm, a0);
+  };
+  cx<double> a0 = {0.0, 0.0}, b0 = {0.0, 0.0}, a1 = {0.0, 0.0}, b1 = {0.0, 0.0};
   if (p.mode == 0) {
     if (valid) {
-      const SV s = static_cast<const SV*>(p.E0_in)[at];
-      ax = {static_cast<double>(s.x), static_cast<double>(s.y)};
+      a0 = ld(p.E0_in, at0);
+      if (two) a1 = ld(p.E0_in, at1);
     }
-    lds_barrier();
   } else {
     if (valid) {
-      const SV s = static_cast<const SV*>(p.a)[at];
-      const SV q = static_cast<const SV*>(p.b)[at];
-      sa[i * kCol + xl] = {static_cast<double>(s.x), static_cast<double>(s.y)};
-      sb[i * kCol + xl] = {static_cast<double>(q.x), static_cast<double>(q.y)};
+      sa[i0 * kCol + xl] = ld(p.a, at0);
+      sb[i0 * kCol + xl] = ld(p.b, at0);
+      if (two) {
+        sa[i1 * kCol + xl] = ld(p.a, at1);
+        sb[i1 * kCol + xl] = ld(p.b, at1);
+      }
     }
     lds_barrier();
     // inverse DFT along y (unnormalised; 1/Ny is in the propagator)
-    for (int k = 0, ik = 0; k < Ny; ++k) {      // ik = i k mod Ny
-      const cx<double> tw = conjd(sw[ik]);
-      ax = ax + cmul(sa[k * kCol + xl], tw);
-      bx = bx + cmul(sb[k * kCol + xl], tw);
-      ik += i;
-      if (ik >= Ny) ik -= Ny;
-    }
-    // coupling of step n inside the slab (Eq. fov10, Eq. Authier)
-    const double xp = static_cast<double>(x - p.Nx / 2) * p.dx;
-    if (valid && xp >= p.x_front && xp < p.x_end) {
-      const SliceConst& c = p.sc[w];
-      const cx<double> d0 = {c.d[0][0], c.d[0][1]};
-      cx<double> cp = {c.d[0][2], c.d[0][3]}, cm = {c.d[0][4], c.d[0][5]};
-      if (p.table) {
-        const SV e = static_cast<const SV*>(p.table)[(size_t(p.n) * Ny + i) * p.Nx + x];
-        const cx<double> ee = {static_cast<double>(e.x), static_cast<double>(e.y)};
-        cp = cmul(cp, ee);
-        cm = cmulc(cm, ee);
+    for (int k = 0, m0 = 0, m1 = 0; k < Ny; ++k) {   // m = i k mod Ny
+      const cx<double> A = sa[k * kCol + xl], B = sb[k * kCol + xl];
+      const cx<double> t0 = conjd(p.wy[m0]);
+      a0 = a0 + cmul(A, t0);
+      b0 = b0 + cmul(B, t0);
+      if (two) {
+        const cx<double> t1 = conjd(p.wy[m1]);
+        a1 = a1 + cmul(A, t1);
+        b1 = b1 + cmul(B, t1);
       }
-      const cx<double> a0 = ax;
-      ax = cmuladd(d0, a0, cp, bx);
-      bx = cmuladd(d0, bx, cm, a0);
+      m0 += i0;
+      if (m0 >= Ny) m0 -= Ny;
+      m1 += i1 - Ny;             // i1 < Ny: one correction suffices
+      if (m1 < 0) m1 += Ny;
+    }
+    if (inside) {
+      couple(a0, b0, i0);
+      if (two) couple(a1, b1, i1);
     }
     lds_barrier();        // every column read before it is overwritten
   }
   if (p.mode == 2) {
     if (valid) {
-      SV s, q;
-      s.x = static_cast<ST>(ax.x);
-      s.y = static_cast<ST>(ax.y);
-      q.x = static_cast<ST>(bx.x);
-      q.y = static_cast<ST>(bx.y);
-      static_cast<SV*>(p.a)[at] = s;
-      static_cast<SV*>(p.b)[at] = q;
+      st(p.a, at0, a0);
+      st(p.b, at0, b0);
+      if (two) {
+        st(p.a, at1, a1);
+        st(p.b, at1, b1);
+      }
     }
     return;
   }
-  sa[i * kCol + xl] = ax;
-  sb[i * kCol + xl] = bx;
+  sa[i0 * kCol + xl] = a0;
+  sb[i0 * kCol + xl] = b0;
+  if (two) {
+    sa[i1 * kCol + xl] = a1;
+    sb[i1 * kCol + xl] = b1;
+  }
   lds_barrier();
-  cx<double> A = {0.0, 0.0}, B = {0.0, 0.0};
-  for (int j = 0, ij = 0; j < Ny; ++j) {      // ij = i j mod Ny
-    const cx<double> tw = sw[ij];
-    ij += i;
-    if (ij >= Ny) ij -= Ny;
-    A = A + cmul(sa[j * kCol + xl], tw);
-    B = B + cmul(sb[j * kCol + xl], tw);
+  cx<double> A0 = {0.0, 0.0}, B0 = {0.0, 0.0}, A1 = {0.0, 0.0}, B1 = {0.0, 0.0};
+  for (int j = 0, m0 = 0, m1 = 0; j < Ny; ++j) {
+    const cx<double> A = sa[j * kCol + xl], B = sb[j * kCol + xl];
+    const cx<double> t0 = p.wy[m0];
+    A0 = A0 + cmul(A, t0);
+    B0 = B0 + cmul(B, t0);
+    if (two) {
+      const cx<double> t1 = p.wy[m1];
+      A1 = A1 + cmul(A, t1);
+      B1 = B1 + cmul(B, t1);
+    }
+    m0 += i0;
+    if (m0 >= Ny) m0 -= Ny;
+    m1 += i1 - Ny;
+    if (m1 < 0) m1 += Ny;
   }
   if (valid) {
-    SV s, q;
-    s.x = static_cast<ST>(A.x);
-    s.y = static_cast<ST>(A.y);
-    q.x = static_cast<ST>(B.x);
-    q.y = static_cast<ST>(B.y);
-    static_cast<SV*>(p.a)[at] = s;
-    static_cast<SV*>(p.b)[at] = q;
+    st(p.a, at0, A0);
+    st(p.b, at0, B0);
+    if (two) {
+      st(p.a, at1, A1);
+      st(p.b, at1, B1);
+    }
   }
 }
 
@@ -550,7 +588,7 @@ int launch_march3(const March3Params& q, hipStream_t s) {
   r.Nx = q.Nx;
   r.Ny = q.Ny;
   const dim3 cgrid((q.Nx + kCol - 1) / kCol, q.Nomega);
-  const dim3 cblock(kCol, q.Ny);
+  const dim3 cblock(kCol, (q.Ny + 1) / 2);
   const int rows = q.Nomega * 2 * q.Ny;
   auto col = [&](int mode, int n) -> int {
     c.mode = mode;
