@@ -24,8 +24,10 @@ Readings (listed with their reasons in the design notes): the crystal is the
 symmetric-Bragg slab x_front <= x < x_front + thickness for every y;
 cos(alpha) = sqrt(1 - (h/2k)^2) as in 2D (the mean angular spectrum has no
 k_y component); y_i = (i - Ny/2) dy like x; periodic window in both axes;
-first-order splitting.  The propagator phase is formed and reduced modulo
-2 pi in extended precision, as in oracle.bpm.
+the splitting schemes of Eq. split-op (first, second and fourth order) with
+the sub-steps of a step using that step's deformation and crystal, as in
+oracle.bpm.  The propagator phase is formed and reduced modulo 2 pi in
+extended precision, as in oracle.bpm.
 """
 
 from __future__ import annotations
@@ -44,7 +46,8 @@ class Problem3D:
     """Parameters of one 3D problem (all slices share them except delta)."""
 
     def __init__(self, Nx, Ny, dx, dy, dz, Nz, chi0, chih, chihbar, theta_B,
-                 lam, delta, x_front=0.0, thickness=math.inf, zassenhaus=True):
+                 lam, delta, x_front=0.0, thickness=math.inf, zassenhaus=True,
+                 split_order=1):
         self.Nx, self.Ny = int(Nx), int(Ny)
         self.dx, self.dy, self.dz = float(dx), float(dy), float(dz)
         self.Nz = int(Nz)
@@ -53,6 +56,7 @@ class Problem3D:
         self.delta = np.atleast_1d(np.asarray(delta, dtype=np.float64))
         self.x_front, self.thickness = float(x_front), float(thickness)
         self.zassenhaus = bool(zassenhaus)
+        self.split_order = int(split_order)
 
     @classmethod
     def from_workload(cls, w, **over):
@@ -73,7 +77,7 @@ class Problem3D:
         return bpm.Problem(self.Nx, self.dx, self.dz, self.Nz, self.chi0,
                            self.chih, self.chihbar, self.theta_B, self.lam,
                            self.delta, self.x_front, self.thickness,
-                           self.zassenhaus)
+                           self.zassenhaus, split_order=self.split_order)
 
 
 def wavenumbers_y(Ny: int, dy: float) -> np.ndarray:
@@ -82,17 +86,18 @@ def wavenumbers_y(Ny: int, dy: float) -> np.ndarray:
     return bpm.TWO_PI_X * m / (np.longdouble(Ny) * np.longdouble(dy))
 
 
-def propagator3d(p: Problem3D, delta: float, band: int) -> np.ndarray:
-    """(Ny, Nx) free-propagation multiplier of one band for one step:
-    exp(i dz sqrt(k^2 - (K_x + band h/2)^2 - K_y^2)), principal root (decay)
-    where evanescent; the phase reduced modulo 2 pi in extended precision."""
+def propagator3d(p: Problem3D, delta: float, band: int, frac: float = 1.0) -> np.ndarray:
+    """(Ny, Nx) free-propagation multiplier of one band for a sub-step of
+    frac*dz: exp(i frac dz sqrt(k^2 - (K_x + band h/2)^2 - K_y^2)),
+    principal root (decay) where evanescent; the phase reduced modulo 2 pi
+    in extended precision."""
     k0, h = bpm.beam_constants(p.along_x())
     k = np.longdouble(k0 * (1.0 + delta))
     Kx = bpm.wavenumbers(p.Nx, p.dx)[None, :]
     Ky = wavenumbers_y(p.Ny, p.dy)[:, None]
     kp = Kx + np.longdouble(band) * np.longdouble(h) / 2
     kz2 = k * k - kp * kp - Ky * Ky
-    L = np.longdouble(p.dz)
+    L = np.longdouble(frac) * np.longdouble(p.dz)
     prop = kz2 >= 0
     phi = np.where(prop, L * np.sqrt(np.where(prop, kz2, 0)), 0)
     phi = np.fmod(phi, bpm.TWO_PI_X).astype(np.float64)
@@ -122,21 +127,30 @@ def march3d(p: Problem3D, E0_in, u=None, n_steps=None, Eh_in=None):
     n_steps = p.Nz if n_steps is None else int(n_steps)
     p2 = p.along_x()
     _, h = bpm.beam_constants(p2)
-    Pp = np.stack([propagator3d(p, d, +1) for d in p.delta])
-    Pm = np.stack([propagator3d(p, d, -1) for d in p.delta])
-    cc = np.array([bpm.coupling_constants(p2, d) for d in p.delta])
-    d0, dp1, dm1 = (cc[:, i][:, None, None] for i in range(3))
+    A, Bc = bpm.split_coefficients(p.split_order)
+    props = [None if ai == 0.0 else
+             (np.stack([propagator3d(p, d, +1, ai) for d in p.delta]),
+              np.stack([propagator3d(p, d, -1, ai) for d in p.delta]))
+             for ai in A]
+    coup = []
+    for bi in Bc:
+        cc = np.array([bpm.coupling_constants(p2, d, bi) for d in p.delta])
+        coup.append(tuple(cc[:, i][:, None, None] for i in range(3)))
     mask = crystal_mask3d(p)[None]
     for n in range(n_steps):
-        a = np.fft.ifft2(Pp * np.fft.fft2(a, axes=(-2, -1)), axes=(-2, -1))
-        b = np.fft.ifft2(Pm * np.fft.fft2(b, axes=(-2, -1)), axes=(-2, -1))
-        if u is None:
-            a_new = d0 * a + dp1 * b
-            b_new = d0 * b + dm1 * a
-        else:
-            e = np.exp(1j * (h * np.asarray(u[n], dtype=np.float64)))[None]
-            a_new = d0 * a + dp1 * e * b
-            b_new = d0 * b + dm1 * np.conj(e) * a
-        a = np.where(mask, a_new, a)
-        b = np.where(mask, b_new, b)
+        e = None if u is None else np.exp(1j * (h * np.asarray(u[n], dtype=np.float64)))[None]
+        for i in range(len(A)):
+            if props[i] is not None:
+                Pp, Pm = props[i]
+                a = np.fft.ifft2(Pp * np.fft.fft2(a, axes=(-2, -1)), axes=(-2, -1))
+                b = np.fft.ifft2(Pm * np.fft.fft2(b, axes=(-2, -1)), axes=(-2, -1))
+            d0, dp1, dm1 = coup[i]
+            if e is None:
+                a_new = d0 * a + dp1 * b
+                b_new = d0 * b + dm1 * a
+            else:
+                a_new = d0 * a + dp1 * e * b
+                b_new = d0 * b + dm1 * np.conj(e) * a
+            a = np.where(mask, a_new, a)
+            b = np.where(mask, b_new, b)
     return a, b
