@@ -13,8 +13,9 @@ mode, with the FP32-butterfly and FP64 modes and their errors against the
 FP64 GPU run beside it.
 
 The same JSON line carries the served request stream (Poisson arrivals,
-mixed sizes, half fp64 requests): p50/p99 latency and cell-updates/s, and the
-same trace served all in fp64.
+mixed sizes, half fp64 requests) at 200 req/s (above what one GPU
+delivers: the latencies are queueing) and at 150 req/s (below it): p50/p99
+latency and cell-updates/s, and the 200 req/s trace served all in fp64.
 
 --workload bent-crystal runs the march measurement on the 2048 x 4000 x 256
 bent crystal; batch, serve and extensions time the batched launch, the
@@ -593,7 +594,7 @@ def main():
                     help="frequency slices of the 3D workload")
     ap.add_argument("--no-serve", action="store_true",
                     help="leave the served stream out of the march measurement")
-    ap.add_argument("--serve-rates", default="200",
+    ap.add_argument("--serve-rates", default="200,150",
                     help="arrival rates (req/s) of the mixed-precision served runs")
     ap.add_argument("--serve-fp64-rates", default="200",
                     help="arrival rates of the same traces served all in fp64")

@@ -114,8 +114,9 @@ bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
  * bpm_plan_create.  A 3D plan supports bpm_propagate, bpm_propagate_ws (the
  * workspace holds the deformation table, as for a 2D plan), the precision,
  * crystal, detuning and time-grid setters (the pulse transforms treat every
- * (y, x) sample as a column; Ny Nx must be even), and first-order splitting
- * with or without the Zassenhaus factor; the segment, batch, mask, schedule,
+ * (y, x) sample as a column; Ny Nx must be even), and the splitting options
+ * (orders 1, 2, 4, with or without the Zassenhaus factor; one row-table set
+ * per distinct A sub-step length, two for order 4); the segment, batch, mask, schedule,
  * deformation-table and no-allocation calls return BPM_EUNSUPPORTED for it.
  * Returns NULL on invalid input. */
 bpm_plan* bpm_plan_create_3d(int Nx, int Ny, double dx, double dy, double dz, int Nz,

@@ -369,11 +369,12 @@ class Plan3D(Plan):
     """A plan on a 3D grid (bpm_plan_create_3d): Ny rows of dy along y, any Nx
     along x; fields (Nomega, Ny, Nx), displacement (Nz, Ny, Nx).  Supports
     propagate (with or without a caller workspace), the pulse transforms and
-    the precision, crystal, detuning and time-grid settings of Plan."""
+    the precision, crystal, detuning, splitting and time-grid settings of
+    Plan."""
 
     def __init__(self, Nx, Ny, dx, dy, dz, Nz, chi0, chih, chihbar, theta_B, lam,
                  Nomega, precision="fp64", x_front=None, thickness=None,
-                 delta=None, zassenhaus=True, time_step=None):
+                 delta=None, split_order=1, zassenhaus=True, time_step=None):
         h = lib().bpm_plan_create_3d(int(Nx), int(Ny), float(dx), float(dy), float(dz),
                                      int(Nz), _cx(chi0), _cx(chih), _cx(chihbar),
                                      float(theta_B), float(lam), int(Nomega))
@@ -382,8 +383,8 @@ class Plan3D(Plan):
         self.Ny = int(Ny)
         super().__init__(Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam, Nomega,
                          precision=precision, x_front=x_front, thickness=thickness,
-                         delta=delta, zassenhaus=zassenhaus, time_step=time_step,
-                         _handle=h)
+                         delta=delta, split_order=split_order, zassenhaus=zassenhaus,
+                         time_step=time_step, _handle=h)
 
     @classmethod
     def from_workload(cls, w, precision="fp64", **kw):

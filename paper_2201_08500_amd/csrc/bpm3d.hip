@@ -73,11 +73,12 @@ BPM_INLINE cx<double> to_d(cx<T> a) {
 }
 BPM_INLINE cx<double> conjd(cx<double> a) { return {a.x, -a.y}; }
 
-// exp(i dz sqrt(k^2 - (K_x + band h/2)^2 - K_y^2)) / (Nx Ny) for signed bins
+// exp(i frac dz sqrt(k^2 - (K_x + band h/2)^2 - K_y^2)) / (Nx Ny) for signed bins
 // (mx, my), K = 2 pi m / (N d), evaluated and reduced modulo 2 pi in
 // double-double; principal root (decay) where evanescent.
 __device__ cx<double> propagator3(int mx, int my, int Nx, int Ny, double dx, double dy,
-                                  double k, double h_half, double band, double dz) {
+                                  double k, double h_half, double band, double dz,
+                                  double frac) {
   const dd two_pi = {kTwoPiHi, kTwoPiLo};
   const dd Kx = dd_div_d(dd_mul_d(two_pi, static_cast<double>(mx)),
                          static_cast<double>(Nx) * dx);
@@ -86,8 +87,10 @@ __device__ cx<double> propagator3(int mx, int my, int Nx, int Ny, double dx, dou
   const dd kp = dd_add(Kx, dd{band * h_half, 0.0});
   const dd kz2 = dd_add(dd_add(two_prod(k, k), dd_neg(dd_mul(kp, kp))), dd_neg(dd_mul(Ky, Ky)));
   const double inv_n = 1.0 / (static_cast<double>(Nx) * static_cast<double>(Ny));
-  if (kz2.hi < 0.0) return {exp(-dz * sqrt(-kz2.hi)) * inv_n, 0.0};
-  dd phi = dd_mul_d(dd_sqrt(kz2), dz);
+  if (kz2.hi < 0.0) return {exp(-frac * dz * sqrt(-kz2.hi)) * inv_n, 0.0};
+  // sub-step length frac*dz kept exact (two_prod) for fractional sub-steps
+  dd phi = frac == 1.0 ? dd_mul_d(dd_sqrt(kz2), dz)
+                       : dd_mul(dd_sqrt(kz2), two_prod(frac, dz));
   const double n = floor(phi.hi / kTwoPiHi);
   phi = dd_add(phi, dd_neg(dd_mul_d(two_pi, n)));
   if (phi.hi < 0.0) phi = dd_add(phi, two_pi);
@@ -103,7 +106,7 @@ __device__ cx<double> propagator3(int mx, int my, int Nx, int Ny, double dx, dou
 // ky = Ny - c.  One thread per entry (grid-stride).
 __global__ void prop3_kernel(cx<double>* __restrict__ P, const SliceConst* __restrict__ sc,
                              int Nx, int Ny, int Nomega, double dx, double dy, double dz,
-                             double h_half) {
+                             double frac, double h_half) {
   const int Nyc = Ny / 2 + 1;
   const size_t n = size_t(Nomega) * 2 * Nyc * Nx;
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
@@ -114,7 +117,7 @@ __global__ void prop3_kernel(cx<double>* __restrict__ P, const SliceConst* __res
     const int env = static_cast<int>((r / Nyc) & 1);
     const int w = static_cast<int>(r / (2 * size_t(Nyc)));
     const int mx = kx < (Nx + 1) / 2 ? kx : kx - Nx;
-    P[i] = propagator3(mx, c, Nx, Ny, dx, dy, sc[w].k, h_half, env ? -1.0 : 1.0, dz);
+    P[i] = propagator3(mx, c, Nx, Ny, dx, dy, sc[w].k, h_half, env ? -1.0 : 1.0, dz, frac);
   }
 }
 
@@ -375,8 +378,10 @@ struct Col3Params {
   const void* table;          // [Nz][Ny][Nx] exp(i h u), or nullptr
   const SliceConst* sc;
   const cx<double>* wy;       // [Ny] exp(-2 pi i j / Ny)
-  int Nx, Ny, n;              // n: the step whose coupling this launch applies
-  int mode;                   // 0 first, 1 step, 2 last
+  int Nx, Ny;
+  int nb;                     // coupling sub-steps this launch applies (0..2),
+  int sub[2], row[2];         //   in order: B sub-step index, step (u row)
+  int mode;                   // 0 first (x-space input), 1 step, 2 last
   double dx, x_front, x_end;
 };
 
@@ -413,15 +418,16 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
     s.y = static_cast<ST>(v.y);
     static_cast<SV*>(f)[i] = s;
   };
-  // coupling of step n inside the slab (Eq. fov10, Eq. Authier) at (x, y_i)
+  // coupling sub-step j of this launch inside the slab (Eq. fov10, Eq.
+  // Authier, the sub-step constants of Eq. split-op) at (x, y_i)
   const double xp = static_cast<double>(x - p.Nx / 2) * p.dx;
   const bool inside = valid && xp >= p.x_front && xp < p.x_end;
-  auto couple = [&](cx<double>& a, cx<double>& b, int i) {
-    const SliceConst& c = p.sc[w];
-    const cx<double> d0 = {c.d[0][0], c.d[0][1]};
-    cx<double> cp = {c.d[0][2], c.d[0][3]}, cm = {c.d[0][4], c.d[0][5]};
+  auto couple = [&](cx<double>& a, cx<double>& b, int i, int j) {
+    const double* d = p.sc[w].d[p.sub[j]];
+    const cx<double> d0 = {d[0], d[1]};
+    cx<double> cp = {d[2], d[3]}, cm = {d[4], d[5]};
     if (p.table) {
-      const cx<double> e = ld(p.table, (size_t(p.n) * Ny + i) * p.Nx + x);
+      const cx<double> e = ld(p.table, (size_t(p.row[j]) * Ny + i) * p.Nx + x);
       cp = cmul(cp, e);
       cm = cmulc(cm, e);
     }
@@ -429,11 +435,18 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
     a = cmuladd(d0, a0, cp, b);
     b = cmuladd(d0, b, cm, a0);
   };
+  auto couple_all = [&](cx<double>& a, cx<double>& b, int i) {
+    for (int j = 0; j < p.nb; ++j) couple(a, b, i, j);
+  };
   cx<double> a0 = {0.0, 0.0}, b0 = {0.0, 0.0}, a1 = {0.0, 0.0}, b1 = {0.0, 0.0};
   if (p.mode == 0) {
     if (valid) {
       a0 = ld(p.E0_in, at0);
       if (two) a1 = ld(p.E0_in, at1);
+    }
+    if (inside) {
+      couple_all(a0, b0, i0);
+      if (two) couple_all(a1, b1, i1);
     }
   } else {
     if (valid) {
@@ -462,8 +475,8 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
       if (m1 < 0) m1 += Ny;
     }
     if (inside) {
-      couple(a0, b0, i0);
-      if (two) couple(a1, b1, i1);
+      couple_all(a0, b0, i0);
+      if (two) couple_all(a1, b1, i1);
     }
     lds_barrier();        // every column read before it is overwritten
   }
@@ -556,13 +569,13 @@ int launch_row3_p(int L, int rows, const Row3Params& p, hipStream_t s) {
 }  // namespace
 
 int launch_prop3(void* P, const SliceConst* sc, int Nx, int Ny, int Nomega, double dx,
-                 double dy, double dz, double h_half, hipStream_t s) {
+                 double dy, double dz, double frac, double h_half, hipStream_t s) {
   const size_t n = size_t(Nomega) * 2 * (Ny / 2 + 1) * Nx;
   const int block = 256;
   const size_t want = (n + block - 1) / block;
   const int grid = static_cast<int>(want < 8192 ? want : 8192);
   hipLaunchKernelGGL(prop3_kernel, dim3(grid), dim3(block), 0, s, static_cast<cx<double>*>(P),
-                     sc, Nx, Ny, Nomega, dx, dy, dz, h_half);
+                     sc, Nx, Ny, Nomega, dx, dy, dz, frac, h_half);
   return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
 }
 
@@ -583,23 +596,23 @@ int launch_march3(const March3Params& q, hipStream_t s) {
   Row3Params r{};
   r.a = q.E0_out;
   r.b = q.Eh_out;
-  r.Q = static_cast<const cx<double>*>(q.rows);
   r.tw = static_cast<const cx<double>*>(q.tw);
   r.Nx = q.Nx;
   r.Ny = q.Ny;
   const dim3 cgrid((q.Nx + kCol - 1) / kCol, q.Nomega);
   const dim3 cblock(kCol, (q.Ny + 1) / 2);
   const int rows = q.Nomega * 2 * q.Ny;
-  auto col = [&](int mode, int n) -> int {
+  auto col = [&](int mode) -> int {
     c.mode = mode;
-    c.n = n;
     if (q.prec == BPM_PREC_FP64)
       hipLaunchKernelGGL(col3_kernel<double>, cgrid, cblock, 0, s, c);
     else
       hipLaunchKernelGGL(col3_kernel<float>, cgrid, cblock, 0, s, c);
+    c.nb = 0;
     return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
   };
-  auto row = [&]() -> int {
+  auto row = [&](int set) -> int {
+    r.Q = static_cast<const cx<double>*>(q.rows) + size_t(set) * q.set_elems;
     switch (q.prec) {
       case BPM_PREC_FP64: return launch_row3_p<BPM_PREC_FP64>(q.L, rows, r, s);
       case BPM_PREC_FP32: return launch_row3_p<BPM_PREC_FP32>(q.L, rows, r, s);
@@ -607,11 +620,26 @@ int launch_march3(const March3Params& q, hipStream_t s) {
       default: return BPM_EUNSUPPORTED;
     }
   };
-  int rc = col(0, 0);
+  // The sub-steps A(a_i dz) B(b_i dz) of every step in order (Eq. split-op);
+  // the B sub-steps between two A sub-steps go to one column launch (at
+  // most two: the last of a step and the first of the next).
+  int rc = BPM_OK;
+  int mode = 0;
+  c.nb = 0;
   for (int n = 0; rc == BPM_OK && n < q.Nz; ++n) {
-    rc = row();
-    if (rc == BPM_OK) rc = col(n + 1 < q.Nz ? 1 : 2, n);
+    for (int i = 0; rc == BPM_OK && i < q.nsub; ++i) {
+      if (q.a_set[i] >= 0) {
+        rc = col(mode);
+        mode = 1;
+        if (rc == BPM_OK) rc = row(q.a_set[i]);
+      }
+      if (c.nb == 2) return BPM_EUNSUPPORTED;   // not produced by the schemes built
+      c.sub[c.nb] = i;
+      c.row[c.nb] = n;
+      ++c.nb;
+    }
   }
+  if (rc == BPM_OK) rc = col(2);
   return rc;
 }
 

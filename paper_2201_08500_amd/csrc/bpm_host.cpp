@@ -12,6 +12,7 @@
 #include <queue>
 #include <tuple>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <utility>
 #include <vector>
@@ -215,9 +216,16 @@ void rows3_bluestein(const bpm_plan* p, const Tables3& t, const std::vector<cplx
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
   const size_t nt = std::min<size_t>({size_t(hw), size_t(16), rows});
   std::vector<std::thread> pool;
-  for (size_t i = 1; i < nt; ++i)
-    pool.emplace_back(work, rows * i / nt, rows * (i + 1) / nt);
+  size_t started = 1;   // ranges 1..started-1 run on pool threads
+  for (; started < nt; ++started) {
+    try {
+      pool.emplace_back(work, rows * started / nt, rows * (started + 1) / nt);
+    } catch (const std::system_error&) {
+      break;            // no more threads: the calling thread takes the rest
+    }
+  }
   work(0, rows / nt);
+  work(rows * started / nt, rows);
   for (auto& th : pool) th.join();
 }
 
@@ -245,15 +253,38 @@ void permute_rows3(std::vector<cplx>& Q, size_t rows, int L) {
   }
 }
 
-// Device tables of a 3D plan: twiddles and the row propagator tables
-// (rows of length L; for L = Nx the propagator itself, evaluated on the
-// device; otherwise Q from the device propagator via the host; long rows
-// permuted to the four-step bin order).  Uses the null stream and waits for
-// it.  Caller holds p->mu, after dev_sc.
+// Distinct A sub-step lengths (fractions of dz) of the plan's scheme, and
+// for each sub-step the index of its length (-1 where a_i = 0).
+int a_sets3(const bpm_plan* p, double frac[4], int set_of[4]) {
+  int nsub;
+  double a[4], b[4];
+  split_fractions(p->split_order, nsub, a, b);
+  int n = 0;
+  for (int i = 0; i < nsub; ++i) {
+    set_of[i] = -1;
+    if (a[i] == 0.0) continue;
+    for (int j = 0; j < n; ++j)
+      if (frac[j] == a[i]) set_of[i] = j;
+    if (set_of[i] < 0) {
+      frac[n] = a[i];
+      set_of[i] = n++;
+    }
+  }
+  return n;
+}
+
+// Device tables of a 3D plan: twiddles and, for each distinct A sub-step
+// length, the row propagator tables (rows of length L; for L = Nx the
+// propagator itself, evaluated on the device; otherwise Q from the device
+// propagator via the host; long rows permuted to the four-step bin order).
+// Uses the null stream and waits for it.  Caller holds p->mu, after dev_sc.
 int upload_tables3(bpm_plan* p) {
   const Tables3 t = tables3(p);
   const size_t L = size_t(p->L3);
   const size_t rows = size_t(p->Nomega) * 2 * (p->Ny / 2 + 1);   // table rows
+  double frac[4];
+  int set_of[4];
+  const int nsets = a_sets3(p, frac, set_of);
   hipError_t e = hipMalloc(&p->dev_tables3, (L + t.wy.size()) * sizeof(cplx));
   if (e != hipSuccess) {
     p->dev_tables3 = nullptr;
@@ -264,7 +295,7 @@ int upload_tables3(bpm_plan* p) {
   if (e == hipSuccess)
     e = hipMemcpy(dt + L, t.wy.data(), t.wy.size() * sizeof(cplx), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D tables)");
-  e = hipMalloc(&p->dev_rows3, rows * L * sizeof(cplx));
+  e = hipMalloc(&p->dev_rows3, size_t(nsets) * rows * L * sizeof(cplx));
   if (e != hipSuccess) {
     p->dev_rows3 = nullptr;
     return fail(BPM_ENOMEM, std::string("hipMalloc(3D row propagators): ") +
@@ -273,34 +304,37 @@ int upload_tables3(bpm_plan* p) {
   // The propagator is evaluated on the device; the rows go through the host
   // when they need the cyclic-convolution table or the four-step bin order.
   const bool via_host = p->bluestein || p->L3 >= bpm::kRow3FourStepMin;
-  void* P = p->dev_rows3;
-  if (via_host) {
-    e = hipMalloc(&P, rows * size_t(p->Nx) * sizeof(cplx));
-    if (e != hipSuccess)
-      return fail(BPM_ENOMEM, std::string("hipMalloc(3D propagator): ") + hipGetErrorString(e));
+  for (int set = 0; set < nsets; ++set) {
+    cplx* dst = static_cast<cplx*>(p->dev_rows3) + size_t(set) * rows * L;
+    void* P = dst;
+    if (via_host) {
+      e = hipMalloc(&P, rows * size_t(p->Nx) * sizeof(cplx));
+      if (e != hipSuccess)
+        return fail(BPM_ENOMEM, std::string("hipMalloc(3D propagator): ") + hipGetErrorString(e));
+    }
+    int rc = bpm::launch_prop3(P, p->dev_sc, p->Nx, p->Ny, p->Nomega, p->dx, p->dy, p->dz,
+                               frac[set], 0.5 * p->h, nullptr);
+    if (rc != BPM_OK) {
+      if (via_host) (void)hipFree(P);
+      return fail(rc, "3D propagator table launch failed");
+    }
+    if (!via_host) {
+      e = hipStreamSynchronize(nullptr);
+      if (e != hipSuccess) return hip_fail(e, "3D propagator table");
+      continue;
+    }
+    std::vector<cplx> hP(rows * size_t(p->Nx)), Q;
+    e = hipMemcpy(hP.data(), P, hP.size() * sizeof(cplx), hipMemcpyDeviceToHost);
+    (void)hipFree(P);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D propagator)");
+    if (p->bluestein)
+      rows3_bluestein(p, t, hP, Q);
+    else
+      Q.swap(hP);
+    if (p->L3 >= bpm::kRow3FourStepMin) permute_rows3(Q, rows, p->L3);
+    e = hipMemcpy(dst, Q.data(), Q.size() * sizeof(cplx), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D row propagators)");
   }
-  int rc = bpm::launch_prop3(P, p->dev_sc, p->Nx, p->Ny, p->Nomega, p->dx, p->dy, p->dz,
-                             0.5 * p->h, nullptr);
-  if (rc != BPM_OK) {
-    if (via_host) (void)hipFree(P);
-    return fail(rc, "3D propagator table launch failed");
-  }
-  if (!via_host) {
-    e = hipStreamSynchronize(nullptr);
-    if (e != hipSuccess) return hip_fail(e, "3D propagator table");
-    return BPM_OK;
-  }
-  std::vector<cplx> hP(rows * size_t(p->Nx)), Q;
-  e = hipMemcpy(hP.data(), P, hP.size() * sizeof(cplx), hipMemcpyDeviceToHost);
-  (void)hipFree(P);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D propagator)");
-  if (p->bluestein)
-    rows3_bluestein(p, t, hP, Q);
-  else
-    Q.swap(hP);
-  if (p->L3 >= bpm::kRow3FourStepMin) permute_rows3(Q, rows, p->L3);
-  e = hipMemcpy(p->dev_rows3, Q.data(), Q.size() * sizeof(cplx), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D row propagators)");
   return BPM_OK;
 }
 
@@ -391,6 +425,14 @@ int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_o
   q.table = table;
   q.sc = p->dev_sc;
   q.rows = p->dev_rows3;
+  q.set_elems = size_t(p->Nomega) * 2 * (p->Ny / 2 + 1) * size_t(p->L3);
+  {
+    int nsub;
+    double a[4], b[4], frac[4];
+    split_fractions(p->split_order, nsub, a, b);
+    q.nsub = nsub;
+    a_sets3(p, frac, q.a_set);
+  }
   q.tw = t3;
   q.wy = t3 + p->L3;
   rc = bpm::launch_march3(q, s);
@@ -801,7 +843,6 @@ int bpm_plan_set_options(bpm_plan* p, int split_order, int zassenhaus) {
     return fail(BPM_EINVAL, "split_order must be 1, 2 or 4");
   if (zassenhaus != 0 && zassenhaus != 1)
     return fail(BPM_EINVAL, "zassenhaus must be 0 or 1");
-  if (split_order != 1 && p->three_d) return reject_3d(p, "higher-order splitting");
   p->split_order = split_order;
   p->zassenhaus = zassenhaus;
   return BPM_OK;

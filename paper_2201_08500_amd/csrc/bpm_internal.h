@@ -95,15 +95,18 @@ struct March3Params {
   void* Eh_out;
   const void* table;        // [Nz][Ny][Nx] exp(i h u), or nullptr
   const SliceConst* sc;
-  const void* rows;         // [Nomega][2][Ny / 2 + 1][L] row propagator (FP64)
+  const void* rows;         // per table set [Nomega][2][Ny / 2 + 1][L] row propagator (FP64)
+  size_t set_elems;         // complex entries per table set
+  int nsub;                 // sub-steps of Eq. split-op per step (1, 2, 4)
+  int a_set[4];             // table set of sub-step i's A (-1: no A)
   const void* tw;           // [L] exp(-2 pi i m / L)
   const void* wy;           // [Ny] exp(-2 pi i j / Ny)
 };
-// The FP64 propagator exp(i dz kz(K_x, K_y)) / (Nx Ny) of every (slice,
+// The FP64 propagator exp(i frac dz kz(K_x, K_y)) / (Nx Ny) of every (slice,
 // envelope, |K_y|, K_x): Nomega x 2 x (Ny / 2 + 1) rows of length Nx, into P
 // (device).
 int launch_prop3(void* P, const SliceConst* sc, int Nx, int Ny, int Nomega, double dx,
-                 double dy, double dz, double h_half, hipStream_t stream);
+                 double dy, double dz, double frac, double h_half, hipStream_t stream);
 int launch_march3(const March3Params& q, hipStream_t stream);
 // Row lengths from which the 3D row kernel uses the four-step layout
 // (W = L / 1024 wavefronts, 1024-point in-wavefront transforms): its row
@@ -153,7 +156,7 @@ struct bpm_plan {
   int L3 = 0;
   bool bluestein = false;
   void* dev_tables3 = nullptr;          // tw [L], wy [Ny]
-  void* dev_rows3 = nullptr;            // [Nomega][2][Ny / 2 + 1][L] row propagator
+  void* dev_rows3 = nullptr;            // per A length [Nomega][2][Ny / 2 + 1][L] row propagator
   int device = -1;
   bool frozen = false;                   // constants computed, setters closed
   std::mutex mu;

@@ -193,7 +193,8 @@ def test_plan_3d_workspace_and_setters():
     # the deformation table only (the plan keeps its row propagators)
     assert p.workspace_bytes() == 60 * 4 * 10 * 8
     assert p.field_shape == (3, 4, 60) and p.u_shape == (10, 4, 60)
-    assert L.bpm_plan_set_options(p.handle, 2, 1) == -4          # order 2: unsupported
+    assert L.bpm_plan_set_options(p.handle, 3, 1) == -1          # no such order
+    assert L.bpm_plan_set_options(p.handle, 4, 1) == 0
     assert L.bpm_plan_set_options(p.handle, 1, 0) == 0
     assert L.bpm_plan_set_mask(p.handle, ctypes.c_void_p(1)) == -4
     assert L.bpm_plan_set_schedule(p.handle, 1) == -4

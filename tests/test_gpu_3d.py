@@ -1,8 +1,9 @@
 """GPU parity of the march on a 3D grid (bpm_plan_create_3d) against the FP64
-3D oracle: power-of-two x lengths (direct transform) and others (Bluestein),
-odd and even Ny up to the maximum, every precision, slab geometries, the
-undeformed crystal, agreement with the 2D march when Ny = 1, the paper's
-22 x 4267 x 1842 grid on a sampled slice, and the calls a 3D plan refuses.
+3D oracle: power-of-two x lengths (direct transform) and others (cyclic
+convolution on a padded length), odd and even Ny up to the maximum, every
+precision, slab geometries, the undeformed crystal, the splitting orders,
+agreement with the 2D march when Ny = 1, the paper's 22 x 4267 x 1842 grid
+on a sampled slice, and the calls a 3D plan refuses.
 
 Tolerances as for the 2D march: FP64 1e-12 + 1e-14 Nz, the FP32-storage
 modes 1e-5 (relL2 over both fields and per field, elementwise maximum,
@@ -25,9 +26,9 @@ def tol(prec, Nz):
     return 1e-12 + 1e-14 * Nz if prec == "fp64" else 1e-5
 
 
-def gpu3(w, prec, workspace=False):
+def gpu3(w, prec, workspace=False, order=1):
     from paper_2201_08500_amd import Plan3D
-    p = Plan3D.from_workload(w, precision=prec)
+    p = Plan3D.from_workload(w, precision=prec, split_order=order)
     E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
     u = None if w.u is None else torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
     ws = None
@@ -38,15 +39,15 @@ def gpu3(w, prec, workspace=False):
     return a.cpu().numpy().astype(np.complex128), b.cpu().numpy().astype(np.complex128)
 
 
-def oracle3(w, prec, slices=None):
+def oracle3(w, prec, slices=None, order=1):
     ws = w if slices is None else w.subset(slices)
     E0 = ws.E0_in if prec == "fp64" else ws.E0_in.astype(np.complex64).astype(np.complex128)
-    return O.march3d(O.Problem3D.from_workload(ws), E0, ws.u)
+    return O.march3d(O.Problem3D.from_workload(ws, split_order=order), E0, ws.u)
 
 
-def check3(w, prec, workspace=False):
-    a, b = gpu3(w, prec, workspace)
-    ra, rb = oracle3(w, prec)
+def check3(w, prec, workspace=False, order=1):
+    a, b = gpu3(w, prec, workspace, order)
+    ra, rb = oracle3(w, prec, order=order)
     r = report(a, b, ra, rb)
     print(f"\n{w.name} {prec}: {r}", flush=True)
     bad = within(r, tol(prec, w.Nz), phase_tol=None if prec == "fp64" else 1e-4)
@@ -67,6 +68,23 @@ def check3(w, prec, workspace=False):
 def test_3d_parity(Nx, Ny, prec):
     w = W.small3d(Nx=Nx, Ny=Ny, Nz=17, Nomega=2, seed=Nx + Ny)
     check3(w, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+@pytest.mark.parametrize("Nx,Ny", [(2, 2), (3, 1), (5, 3)])
+def test_3d_smallest_grids(Nx, Ny, prec):
+    """The smallest transform lengths (Nx = 2, 3, 5 on L = 64) and Ny = 1."""
+    check3(W.small3d(Nx=Nx, Ny=Ny, Nz=7, Nomega=2, seed=Nx), prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("Nx,Ny", [(60, 5), (256, 4), (3000, 2)])
+def test_3d_splitting_orders(Nx, Ny, order, prec):
+    """Second- and fourth-order splitting (Eq. split-op) on the 3D grid:
+    Bluestein, direct and four-step rows (Nx = 3000: L = 8192); order 4
+    uses two row-table sets (A lengths t dz and (1 - 2t) dz)."""
+    check3(W.small3d(Nx=Nx, Ny=Ny, Nz=9, Nomega=2, seed=Nx + order), prec, order=order)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32s"])
@@ -103,15 +121,17 @@ def test_3d_four_step_rows(prec):
         check3(W.small3d(Nx=5000, Ny=3, Nz=5, Nomega=2, seed=9), prec)
 
 
-def test_3d_one_row_matches_the_2d_march():
+@pytest.mark.parametrize("order", [1, 2, 4])
+def test_3d_one_row_matches_the_2d_march(order):
     """Ny = 1 on a power-of-two x grid: the 3D kernels and the 2D march
-    compute the same problem (different transforms, so to rounding)."""
+    compute the same problem (different transforms, so to rounding), for
+    every splitting order."""
     from paper_2201_08500_amd import Plan
     w3 = W.small3d(Nx=512, Ny=1, Nz=40, Nomega=3, seed=12)
-    a3, b3 = gpu3(w3, "fp64")
+    a3, b3 = gpu3(w3, "fp64", order=order)
     p2 = Plan(w3.Nx, w3.dx, w3.dz, w3.Nz, w3.chi0, w3.chih, w3.chihbar, w3.theta_B,
               w3.lam, w3.Nomega, precision="fp64", x_front=w3.x_front,
-              thickness=w3.thickness, delta=w3.delta)
+              thickness=w3.thickness, delta=w3.delta, split_order=order)
     E0 = torch.from_numpy(np.ascontiguousarray(w3.E0_in[:, 0, :])).cuda()
     u = torch.from_numpy(np.ascontiguousarray(w3.u[:, 0, :])).cuda()
     a2, b2 = p2.propagate(E0, u)
