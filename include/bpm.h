@@ -116,8 +116,11 @@ bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
  * crystal, detuning and time-grid setters (the pulse transforms treat every
  * (y, x) sample as a column; Ny Nx must be even), and the splitting options
  * (orders 1, 2, 4, with or without the Zassenhaus factor; one row-table set
- * per distinct A sub-step length, two for order 4); the segment, batch, mask, schedule,
- * deformation-table and no-allocation calls return BPM_EUNSUPPORTED for it.
+ * per distinct A sub-step length, two for order 4), bpm_deformation_table
+ * (Nz Ny Nx cells), bpm_march and bpm_march_segment (which chain bitwise
+ * for BPM_PREC_FP64 only: between the two coupling sub-steps at a segment
+ * boundary the state is stored in the storage type); the batch, mask,
+ * schedule and no-allocation calls return BPM_EUNSUPPORTED for it.
  * Returns NULL on invalid input. */
 bpm_plan* bpm_plan_create_3d(int Nx, int Ny, double dx, double dy, double dz, int Nz,
                              bpm_complex chi0, bpm_complex chih, bpm_complex chihbar,

@@ -368,9 +368,9 @@ class Plan:
 class Plan3D(Plan):
     """A plan on a 3D grid (bpm_plan_create_3d): Ny rows of dy along y, any Nx
     along x; fields (Nomega, Ny, Nx), displacement (Nz, Ny, Nx).  Supports
-    propagate (with or without a caller workspace), the pulse transforms and
-    the precision, crystal, detuning, splitting and time-grid settings of
-    Plan."""
+    propagate (with or without a caller workspace), deformation_table, march,
+    march_segment, the pulse transforms and the precision, crystal,
+    detuning, splitting and time-grid settings of Plan."""
 
     def __init__(self, Nx, Ny, dx, dy, dz, Nz, chi0, chih, chihbar, theta_B, lam,
                  Nomega, precision="fp64", x_front=None, thickness=None,

@@ -372,7 +372,8 @@ __global__ void __launch_bounds__(F::T) row3_four_kernel(Row3Params p) {
 }
 
 struct Col3Params {
-  const void* E0_in;          // x-space input (first launch)
+  const void* E0_in;          // x-space input psi~_+ (first launch)
+  const void* Eh_in;          // x-space input psi~_- (first launch), or nullptr: zero
   void* a;                    // psi~_+ state / output
   void* b;                    // psi~_- state / output
   const void* table;          // [Nz][Ny][Nx] exp(i h u), or nullptr
@@ -443,6 +444,10 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
     if (valid) {
       a0 = ld(p.E0_in, at0);
       if (two) a1 = ld(p.E0_in, at1);
+      if (p.Eh_in) {
+        b0 = ld(p.Eh_in, at0);
+        if (two) b1 = ld(p.Eh_in, at1);
+      }
     }
     if (inside) {
       couple_all(a0, b0, i0);
@@ -583,6 +588,7 @@ int launch_march3(const March3Params& q, hipStream_t s) {
   if (q.Ny < 1 || q.Ny > kMaxNy) return BPM_EUNSUPPORTED;
   Col3Params c{};
   c.E0_in = q.E0_in;
+  c.Eh_in = q.Eh_in;
   c.a = q.E0_out;
   c.b = q.Eh_out;
   c.table = q.table;
@@ -626,7 +632,7 @@ int launch_march3(const March3Params& q, hipStream_t s) {
   int rc = BPM_OK;
   int mode = 0;
   c.nb = 0;
-  for (int n = 0; rc == BPM_OK && n < q.Nz; ++n) {
+  for (int n = q.n0; rc == BPM_OK && n < q.n0 + q.Nz; ++n) {
     for (int i = 0; rc == BPM_OK && i < q.nsub; ++i) {
       if (q.a_set[i] >= 0) {
         rc = col(mode);

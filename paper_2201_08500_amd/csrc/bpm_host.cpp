@@ -392,34 +392,30 @@ int reject_3d(const bpm_plan* p, const char* what) {
   return BPM_OK;
 }
 
-// The whole 3D march: deformation table, then the row and column launches
-// of every step (bpm3d.hip).
-int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_out,
-               void* Eh_out, void* workspace, hipStream_t s) {
+// Steps [n0, n0 + nsteps) of the 3D march from x-space envelopes (Eh_in
+// NULL: zero), reading the deformation table (or none): the row and column
+// launches of every sub-step (bpm3d.hip).
+int march3(bpm_plan* p, const void* E0_in, const void* Eh_in, const void* table, int n0,
+           int nsteps, void* E0_out, void* Eh_out, hipStream_t s) {
   if (p->precision == BPM_PREC_FP64 && p->L3 > 8192)
     return fail(BPM_EUNSUPPORTED, "FP64 3D rows need a transform length <= 8192 "
                                   "(Nx <= 4096, or a power of two <= 8192)");
   int rc = freeze(p);
   if (rc) return rc;
-  char* ws = static_cast<char*>(workspace);
-  void* table = nullptr;
-  if (u_field) {
-    table = ws;
-    rc = bpm::launch_deform(p->precision, p->Nx * p->Ny, p->Nz, p->h, u_field, table, s);
-    if (rc) return fail(rc, "deformation pre-pass launch failed");
-  }
   const cplx* t3 = static_cast<const cplx*>(p->dev_tables3);
   bpm::March3Params q{};
   q.prec = p->precision;
   q.Nx = p->Nx;
   q.Ny = p->Ny;
-  q.Nz = p->Nz;
+  q.Nz = nsteps;
+  q.n0 = n0;
   q.Nomega = p->Nomega;
   q.L = p->L3;
   q.dx = p->dx;
   q.x_front = p->x_front;
   q.x_end = p->x_front + p->thickness;
   q.E0_in = E0_in;
+  q.Eh_in = Eh_in;
   q.E0_out = E0_out;
   q.Eh_out = Eh_out;
   q.table = table;
@@ -439,6 +435,23 @@ int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_o
   if (rc == BPM_EUNSUPPORTED) return fail(rc, "unsupported 3D size/precision");
   if (rc) return fail(rc, "3D march launch failed");
   return BPM_OK;
+}
+
+// The whole 3D march: deformation table, then every step.
+int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_out,
+               void* Eh_out, void* workspace, hipStream_t s) {
+  if (p->precision == BPM_PREC_FP64 && p->L3 > 8192)
+    return fail(BPM_EUNSUPPORTED, "FP64 3D rows need a transform length <= 8192 "
+                                  "(Nx <= 4096, or a power of two <= 8192)");
+  int rc = freeze(p);
+  if (rc) return rc;
+  void* table = nullptr;
+  if (u_field) {
+    table = workspace;
+    rc = bpm::launch_deform(p->precision, p->Nx * p->Ny, p->Nz, p->h, u_field, table, s);
+    if (rc) return fail(rc, "deformation pre-pass launch failed");
+  }
+  return march3(p, E0_in, nullptr, table, 0, p->Nz, E0_out, Eh_out, s);
 }
 
 int plan_schedule(const bpm_plan* p) {
@@ -921,14 +934,14 @@ int bpm_deformation_table(const bpm_plan* cp, const double* u_field,
                           void* workspace, void* stream) {
   g_error.clear();
   if (!cp) return fail(BPM_EINVAL, "plan is NULL");
-  if (int rc = reject_3d(cp, "bpm_deformation_table")) return rc;
   if (!u_field || !workspace)
     return fail(BPM_EINVAL, "u_field and workspace must be non-NULL");
   bpm_plan* p = const_cast<bpm_plan*>(cp);
   int rc = freeze(p);
   if (rc) return rc;
-  rc = bpm::launch_deform(p->precision, p->Nx, p->Nz, p->h, u_field, workspace,
-                          static_cast<hipStream_t>(stream));
+  // a 3D plan's cells are its (y, x) samples
+  rc = bpm::launch_deform(p->precision, p->three_d ? p->Nx * p->Ny : p->Nx, p->Nz, p->h,
+                          u_field, workspace, static_cast<hipStream_t>(stream));
   if (rc) return fail(rc, "deformation pre-pass launch failed");
   return BPM_OK;
 }
@@ -937,12 +950,14 @@ int bpm_march(const bpm_plan* cp, const void* E0_in, const void* table,
               void* E0_out, void* Eh_out, void* stream) {
   g_error.clear();
   if (!cp) return fail(BPM_EINVAL, "plan is NULL");
-  if (int rc = reject_3d(cp, "bpm_march")) return rc;
   if (!E0_in || !E0_out || !Eh_out)
     return fail(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
   if (E0_in == E0_out || E0_in == Eh_out || E0_out == Eh_out)
     return fail(BPM_EINVAL, "output buffers must not alias each other or E0_in");
   bpm_plan* p = const_cast<bpm_plan*>(cp);
+  if (p->three_d)
+    return march3(p, E0_in, nullptr, table, 0, p->Nz, E0_out, Eh_out,
+                  static_cast<hipStream_t>(stream));
   int rc = freeze(p);
   if (rc) return rc;
   const bpm::MarchParams m = march_params(p, E0_in, table, E0_out, Eh_out);
@@ -958,7 +973,6 @@ int bpm_march_segment(const bpm_plan* cp, const void* E0_in, const void* Eh_in,
                       void* Eh_out, void* stream) {
   g_error.clear();
   if (!cp) return fail(BPM_EINVAL, "plan is NULL");
-  if (int rc = reject_3d(cp, "bpm_march_segment")) return rc;
   if (!E0_in || !E0_out || !Eh_out)
     return fail(BPM_EINVAL, "E0_in, E0_out and Eh_out must be non-NULL");
   if (E0_out == Eh_out || (Eh_in && (E0_out == Eh_in || Eh_out == E0_in)))
@@ -966,6 +980,9 @@ int bpm_march_segment(const bpm_plan* cp, const void* E0_in, const void* Eh_in,
   if (n0 < 0 || nsteps < 1 || n0 > cp->Nz - nsteps)
     return fail(BPM_EINVAL, "steps [n0, n0 + nsteps) must lie in [0, Nz)");
   bpm_plan* p = const_cast<bpm_plan*>(cp);
+  if (p->three_d)
+    return march3(p, E0_in, Eh_in, table, n0, nsteps, E0_out, Eh_out,
+                  static_cast<hipStream_t>(stream));
   int rc = freeze(p);
   if (rc) return rc;
   bpm::MarchParams m = march_params(p, E0_in, table, E0_out, Eh_out);

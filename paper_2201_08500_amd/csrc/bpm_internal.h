@@ -88,9 +88,11 @@ int default_schedule(int prec, int Nx);
 // ([Nomega][2][Ny][Nx] complex FP64); chirp [Nx], G [L], tw [L] and
 // wy [Ny] are the plan's FP64 tables (complex, interleaved).
 struct March3Params {
-  int prec, Nx, Ny, Nz, Nomega, L;
+  int prec, Nx, Ny, Nz, Nomega, L;  // Nz: steps of this launch sequence
+  int n0;                   // index of its first step (deformation row)
   double dx, x_front, x_end;
   const void* E0_in;
+  const void* Eh_in;        // nullptr: psi~_- starts at zero
   void* E0_out;
   void* Eh_out;
   const void* table;        // [Nz][Ny][Nx] exp(i h u), or nullptr

@@ -140,6 +140,59 @@ def test_3d_one_row_matches_the_2d_march(order):
     assert not within(r, 1e-12 + 1e-14 * w3.Nz), r
 
 
+@pytest.mark.parametrize("order", [1, 2, 4])
+def test_3d_segments_chain_bitwise_fp64(order):
+    """bpm_deformation_table, bpm_march and bpm_march_segment on a 3D plan:
+    three segments chained through their outputs (the last in place) equal
+    the whole march bitwise in FP64, and a segment resumed from a checkpoint
+    of both envelopes matches the oracle started from that checkpoint."""
+    from paper_2201_08500_amd import Plan3D
+    w = W.small3d(Nx=100, Ny=5, Nz=12, Nomega=2, seed=40 + order)
+    p = Plan3D.from_workload(w, precision="fp64", split_order=order)
+    E0 = torch.from_numpy(w.E0_in).cuda()
+    u = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
+    ws = torch.empty(p.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    p.deformation_table(u, ws)
+    a, b = torch.empty_like(E0), torch.empty_like(E0)
+    p.march(E0, ws, a, b)
+    a1, b1 = torch.empty_like(E0), torch.empty_like(E0)
+    p.march_segment(E0, None, ws, 0, 5, a1, b1)
+    a2, b2 = torch.empty_like(E0), torch.empty_like(E0)
+    p.march_segment(a1, b1, ws, 5, 4, a2, b2)
+    p.march_segment(a2, b2, ws, 9, 3, a2, b2)
+    torch.cuda.synchronize()
+    assert torch.equal(a2, a) and torch.equal(b2, b)
+    # the whole march against the oracle, and the resumed part against the
+    # oracle started at step 5 from the first segment's output
+    r = report(a.cpu().numpy(), b.cpu().numpy(), *oracle3(w, "fp64", order=order))
+    assert not within(r, tol("fp64", w.Nz)), r
+    ra, rb = O.march3d(O.Problem3D.from_workload(w, split_order=order),
+                       a1.cpu().numpy(), w.u[5:], n_steps=7, Eh_in=b1.cpu().numpy())
+    r = report(a2.cpu().numpy(), b2.cpu().numpy(), ra, rb)
+    assert not within(r, tol("fp64", 7)), r
+
+
+def test_3d_segments_fp32s_within_rounding():
+    """FP32 storage: each segment boundary stores the state in FP32, so the
+    chained march differs from the whole one at the mode's rounding level."""
+    from paper_2201_08500_amd import Plan3D
+    w = W.small3d(Nx=3000, Ny=2, Nz=10, Nomega=1, seed=50)
+    p = Plan3D.from_workload(w, precision="fp32s", split_order=2)
+    E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
+    u = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
+    ws = torch.empty(p.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    p.deformation_table(u, ws)
+    a, b = torch.empty_like(E0), torch.empty_like(E0)
+    p.march(E0, ws, a, b)
+    c, d = torch.empty_like(E0), torch.empty_like(E0)
+    p.march_segment(E0, None, ws, 0, 6, c, d)
+    p.march_segment(c, d, ws, 6, 4, c, d)
+    torch.cuda.synchronize()
+    r = report(c.cpu().numpy().astype(np.complex128), d.cpu().numpy().astype(np.complex128),
+               a.cpu().numpy().astype(np.complex128), b.cpu().numpy().astype(np.complex128))
+    assert not within(r, 1e-6), r
+
+
 def test_3d_paper_grid_sampled_slice():
     """The grid of the paper's finite-element example, 22 x 4267 x 1842
     (Bluestein on L = 16384), two slices in fp32s; the oracle recomputes
@@ -159,9 +212,7 @@ def test_3d_plan_refuses_what_it_does_not_support():
     E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
     u = torch.from_numpy(w.u).cuda()
     a, b = torch.empty_like(E0), torch.empty_like(E0)
-    for call in (lambda: p.march(E0, None, a, b),
-                 lambda: p.march_segment(E0, None, None, 0, 2, a, b),
-                 lambda: p.propagate_noalloc(E0, u, a, b),
+    for call in (lambda: p.propagate_noalloc(E0, u, a, b),
                  lambda: propagate_batch([Job(p, E0, u)])):
         with pytest.raises(BpmError):
             call()
