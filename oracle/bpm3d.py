@@ -21,7 +21,8 @@ the paper's order, for every frequency slice:
     exp(+-i h u(x, y, z)) and the crystal mask.
 
 Readings (listed with their reasons in the design notes): the crystal is the
-symmetric-Bragg slab x_front <= x < x_front + thickness for every y;
+symmetric-Bragg slab x_front <= x < x_front + thickness for every y, or a
+general mask Pi(x, y, z) with one (y, x) row per step;
 cos(alpha) = sqrt(1 - (h/2k)^2) as in 2D (the mean angular spectrum has no
 k_y component); y_i = (i - Ny/2) dy like x; periodic window in both axes;
 the splitting schemes of Eq. split-op (first, second and fourth order) with
@@ -47,7 +48,7 @@ class Problem3D:
 
     def __init__(self, Nx, Ny, dx, dy, dz, Nz, chi0, chih, chihbar, theta_B,
                  lam, delta, x_front=0.0, thickness=math.inf, zassenhaus=True,
-                 split_order=1):
+                 split_order=1, mask=None):
         self.Nx, self.Ny = int(Nx), int(Ny)
         self.dx, self.dy, self.dz = float(dx), float(dy), float(dz)
         self.Nz = int(Nz)
@@ -57,6 +58,10 @@ class Problem3D:
         self.x_front, self.thickness = float(x_front), float(thickness)
         self.zassenhaus = bool(zassenhaus)
         self.split_order = int(split_order)
+        # general crystal mask Pi(x, y, z): (Nz, Ny, Nx) booleans, row n used
+        # by every sub-step of step n; None selects the slab
+        self.mask = None if mask is None else np.asarray(mask, dtype=bool).reshape(
+            self.Nz, self.Ny, self.Nx)
 
     @classmethod
     def from_workload(cls, w, **over):
@@ -105,9 +110,12 @@ def propagator3d(p: Problem3D, delta: float, band: int, frac: float = 1.0) -> np
     return np.exp(1j * phi - decay.astype(np.float64))
 
 
-def crystal_mask3d(p: Problem3D) -> np.ndarray:
-    """(Ny, Nx) crystal mask: the slab x_front <= x_j < x_front + thickness,
-    x_j = (j - Nx/2) dx, the same for every y."""
+def crystal_mask3d(p: Problem3D, n: int = 0) -> np.ndarray:
+    """(Ny, Nx) crystal mask of step n: the general mask p.mask[n] when one
+    is given, otherwise the slab x_front <= x_j < x_front + thickness,
+    x_j = (j - Nx/2) dx, the same for every y and step."""
+    if p.mask is not None:
+        return p.mask[n]
     x = (np.arange(p.Nx) - p.Nx // 2) * p.dx
     row = (x >= p.x_front) & (x < p.x_front + p.thickness)
     return np.broadcast_to(row, (p.Ny, p.Nx))
@@ -136,9 +144,9 @@ def march3d(p: Problem3D, E0_in, u=None, n_steps=None, Eh_in=None):
     for bi in Bc:
         cc = np.array([bpm.coupling_constants(p2, d, bi) for d in p.delta])
         coup.append(tuple(cc[:, i][:, None, None] for i in range(3)))
-    mask = crystal_mask3d(p)[None]
     for n in range(n_steps):
         e = None if u is None else np.exp(1j * (h * np.asarray(u[n], dtype=np.float64)))[None]
+        mask = crystal_mask3d(p, n)[None]
         for i in range(len(A)):
             if props[i] is not None:
                 Pp, Pm = props[i]

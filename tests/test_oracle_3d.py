@@ -117,6 +117,39 @@ def test_fourth_order_3d_beats_second_order():
     assert all(a < 0.3 * b for a, b in zip(e4, e2)), (e4, e2)
 
 
+def test_mask_shaped_like_the_slab_is_the_slab():
+    """A general mask that reproduces the slab in every step gives the slab
+    march bitwise; an empty mask is free propagation."""
+    rng = np.random.default_rng(21)
+    Nx, Ny, Nz = 40, 4, 9
+    kw = dict(x_front=-4e-6, thickness=9e-6)
+    p = p3(Nx, Ny, Nz, [0.0, 2e-6], **kw)
+    E0 = rand_field(rng, 2, Ny, Nx)
+    u = rng.normal(scale=3e-11, size=(Nz, Ny, Nx))
+    slab = np.broadcast_to(O.crystal_mask3d(p), (Nz, Ny, Nx))
+    a, b = O.march3d(p, E0, u)
+    am, bm = O.march3d(p3(Nx, Ny, Nz, [0.0, 2e-6], mask=slab, **kw), E0, u)
+    assert np.array_equal(a, am) and np.array_equal(b, bm)
+    av, bv = O.march3d(p3(Nx, Ny, Nz, [0.0, 2e-6], **VACUUM), E0, u)
+    ae, be = O.march3d(p3(Nx, Ny, Nz, [0.0, 2e-6], mask=np.zeros((Nz, Ny, Nx)), **kw), E0, u)
+    assert np.array_equal(av, ae) and np.array_equal(bv, be)
+
+
+def test_one_row_with_a_mask_is_the_masked_2d_march():
+    """Ny = 1 with a general mask that changes from step to step is the
+    pinned masked 2D march (Laue block, shaped entrance)."""
+    rng = np.random.default_rng(22)
+    Nx, Nz = 64, 15
+    m2 = rng.random((Nz, Nx)) < 0.6
+    E0 = rand_field(rng, 1, 1, Nx)
+    u = rng.normal(scale=3e-11, size=(Nz, 1, Nx))
+    a, b = O.march3d(p3(Nx, 1, Nz, mask=m2[:, None, :], split_order=2), E0, u)
+    q = O.Problem(Nx, 0.5e-6, 0.5e-6, Nz, CHI0, CHIH, CHIH, TH, LAM, [0.0],
+                  split_order=2, mask=m2)
+    a2, b2 = O.march(q, E0[:, 0, :], u[:, 0, :])
+    assert rel(a[:, 0], a2) < 1e-13 and rel(b[:, 0], b2) < 1e-13
+
+
 @pytest.mark.parametrize("Ny", [6, 5])
 def test_y_independent_problem_has_2d_rows(Ny):
     """A field and a displacement that do not depend on y stay independent
