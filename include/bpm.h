@@ -119,8 +119,9 @@ bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
  * per distinct A sub-step length, two for order 4), bpm_deformation_table
  * (Nz Ny Nx cells), bpm_march and bpm_march_segment (which chain bitwise
  * for BPM_PREC_FP64 only: between the two coupling sub-steps at a segment
- * boundary the state is stored in the storage type); the batch, mask,
- * schedule and no-allocation calls return BPM_EUNSUPPORTED for it.
+ * boundary the state is stored in the storage type), and a general crystal
+ * mask [Nz][Ny][Nx]; the batch, schedule and no-allocation calls return
+ * BPM_EUNSUPPORTED for it.
  * Returns NULL on invalid input. */
 bpm_plan* bpm_plan_create_3d(int Nx, int Ny, double dx, double dy, double dz, int Nz,
                              bpm_complex chi0, bpm_complex chih, bpm_complex chihbar,
@@ -139,7 +140,8 @@ int bpm_plan_set_crystal(bpm_plan* plan, double x_front, double thickness);
  * NULL array or an offset that is not finite or is <= -1 (k <= 0). */
 int bpm_plan_set_detuning(bpm_plan* plan, const double* delta);
 /* General crystal mask Pi(x, z) replacing the slab (asymmetric Bragg, Laue,
- * wedges, any shape in the (x, z) plane): host array [Nz][Nx] of bytes,
+ * wedges, any shape in the (x, z) plane): host array [Nz][Nx] of bytes
+ * ([Nz][Ny][Nx], Pi(x, y, z), for a 3D plan),
  * nonzero = crystal, row n used by every sub-step of step n; copied into
  * the plan (uploaded to the device once, on first use); NULL returns to the
  * slab of bpm_plan_set_crystal.  Outside the crystal the coupling is the

@@ -187,8 +187,8 @@ class Plan:
         if mask is not None:
             import numpy as np
             m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
-            if m.shape != (self.Nz, self.Nx):
-                raise ValueError(f"mask must have shape ({self.Nz}, {self.Nx})")
+            if m.shape != self.u_shape:
+                raise ValueError(f"mask must have shape {self.u_shape}")
             _check(L.bpm_plan_set_mask(self._h, m.ctypes.data_as(ctypes.c_void_p)))
         if split_order != 1 or not zassenhaus:
             _check(L.bpm_plan_set_options(self._h, int(split_order),
@@ -369,12 +369,13 @@ class Plan3D(Plan):
     """A plan on a 3D grid (bpm_plan_create_3d): Ny rows of dy along y, any Nx
     along x; fields (Nomega, Ny, Nx), displacement (Nz, Ny, Nx).  Supports
     propagate (with or without a caller workspace), deformation_table, march,
-    march_segment, the pulse transforms and the precision, crystal,
-    detuning, splitting and time-grid settings of Plan."""
+    march_segment, the pulse transforms and the precision, crystal (slab or
+    a general mask of shape (Nz, Ny, Nx)), detuning, splitting and time-grid
+    settings of Plan."""
 
     def __init__(self, Nx, Ny, dx, dy, dz, Nz, chi0, chih, chihbar, theta_B, lam,
                  Nomega, precision="fp64", x_front=None, thickness=None,
-                 delta=None, split_order=1, zassenhaus=True, time_step=None):
+                 delta=None, split_order=1, zassenhaus=True, time_step=None, mask=None):
         h = lib().bpm_plan_create_3d(int(Nx), int(Ny), float(dx), float(dy), float(dz),
                                      int(Nz), _cx(chi0), _cx(chih), _cx(chihbar),
                                      float(theta_B), float(lam), int(Nomega))
@@ -384,7 +385,7 @@ class Plan3D(Plan):
         super().__init__(Nx, dx, dz, Nz, chi0, chih, chihbar, theta_B, lam, Nomega,
                          precision=precision, x_front=x_front, thickness=thickness,
                          delta=delta, split_order=split_order, zassenhaus=zassenhaus,
-                         time_step=time_step, _handle=h)
+                         time_step=time_step, mask=mask, _handle=h)
 
     @classmethod
     def from_workload(cls, w, precision="fp64", **kw):

@@ -377,6 +377,7 @@ struct Col3Params {
   void* a;                    // psi~_+ state / output
   void* b;                    // psi~_- state / output
   const void* table;          // [Nz][Ny][Nx] exp(i h u), or nullptr
+  const unsigned char* mask;  // [Nz][Ny][Nx] crystal mask, or nullptr: the slab
   const SliceConst* sc;
   const cx<double>* wy;       // [Ny] exp(-2 pi i j / Ny)
   int Nx, Ny;
@@ -419,11 +420,13 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
     s.y = static_cast<ST>(v.y);
     static_cast<SV*>(f)[i] = s;
   };
-  // coupling sub-step j of this launch inside the slab (Eq. fov10, Eq.
-  // Authier, the sub-step constants of Eq. split-op) at (x, y_i)
+  // coupling sub-step j of this launch inside the crystal (Eq. fov10, Eq.
+  // Authier, the sub-step constants of Eq. split-op) at (x, y_i): the slab,
+  // or the general mask row of the sub-step's step
   const double xp = static_cast<double>(x - p.Nx / 2) * p.dx;
-  const bool inside = valid && xp >= p.x_front && xp < p.x_end;
+  const bool in_slab = xp >= p.x_front && xp < p.x_end;
   auto couple = [&](cx<double>& a, cx<double>& b, int i, int j) {
+    if (p.mask ? !p.mask[(size_t(p.row[j]) * Ny + i) * p.Nx + x] : !in_slab) return;
     const double* d = p.sc[w].d[p.sub[j]];
     const cx<double> d0 = {d[0], d[1]};
     cx<double> cp = {d[2], d[3]}, cm = {d[4], d[5]};
@@ -449,7 +452,7 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
         if (two) b1 = ld(p.Eh_in, at1);
       }
     }
-    if (inside) {
+    if (valid) {
       couple_all(a0, b0, i0);
       if (two) couple_all(a1, b1, i1);
     }
@@ -479,7 +482,7 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
       m1 += i1 - Ny;             // i1 < Ny: one correction suffices
       if (m1 < 0) m1 += Ny;
     }
-    if (inside) {
+    if (valid) {
       couple_all(a0, b0, i0);
       if (two) couple_all(a1, b1, i1);
     }
@@ -592,6 +595,7 @@ int launch_march3(const March3Params& q, hipStream_t s) {
   c.a = q.E0_out;
   c.b = q.Eh_out;
   c.table = q.table;
+  c.mask = static_cast<const unsigned char*>(q.mask);
   c.sc = q.sc;
   c.wy = static_cast<const cx<double>*>(q.wy);
   c.Nx = q.Nx;

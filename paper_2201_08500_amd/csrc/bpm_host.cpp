@@ -419,6 +419,7 @@ int march3(bpm_plan* p, const void* E0_in, const void* Eh_in, const void* table,
   q.E0_out = E0_out;
   q.Eh_out = Eh_out;
   q.table = table;
+  q.mask = p->mask.empty() ? nullptr : p->dev_mask;
   q.sc = p->dev_sc;
   q.rows = p->dev_rows3;
   q.set_elems = size_t(p->Nomega) * 2 * (p->Ny / 2 + 1) * size_t(p->L3);
@@ -815,12 +816,11 @@ int bpm_plan_set_detuning(bpm_plan* p, const double* delta) {
 int bpm_plan_set_mask(bpm_plan* p, const unsigned char* mask) {
   int rc = check_mutable(p);
   if (rc) return rc;
-  if (mask && p->three_d) return reject_3d(p, "a general crystal mask");
   if (!mask) {
     p->mask.clear();
     return BPM_OK;
   }
-  const size_t n = size_t(p->Nx) * size_t(p->Nz);
+  const size_t n = size_t(p->Nx) * size_t(p->Nz) * size_t(p->three_d ? p->Ny : 1);
   p->mask.resize(n);
   for (size_t i = 0; i < n; ++i) p->mask[i] = mask[i] ? 1 : 0;
   return BPM_OK;

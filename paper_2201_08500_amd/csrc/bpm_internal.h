@@ -96,6 +96,7 @@ struct March3Params {
   void* E0_out;
   void* Eh_out;
   const void* table;        // [Nz][Ny][Nx] exp(i h u), or nullptr
+  const void* mask;         // [Nz][Ny][Nx] crystal mask (device), or nullptr: the slab
   const SliceConst* sc;
   const void* rows;         // per table set [Nomega][2][Ny / 2 + 1][L] row propagator (FP64)
   size_t set_elems;         // complex entries per table set

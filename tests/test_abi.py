@@ -196,6 +196,8 @@ def test_plan_3d_workspace_and_setters():
     assert L.bpm_plan_set_options(p.handle, 3, 1) == -1          # no such order
     assert L.bpm_plan_set_options(p.handle, 4, 1) == 0
     assert L.bpm_plan_set_options(p.handle, 1, 0) == 0
-    assert L.bpm_plan_set_mask(p.handle, ctypes.c_void_p(1)) == -4
+    m = np.ones((10, 4, 60), dtype=np.uint8)          # [Nz][Ny][Nx]
+    assert L.bpm_plan_set_mask(p.handle, m.ctypes.data_as(ctypes.c_void_p)) == 0
+    assert L.bpm_plan_set_mask(p.handle, None) == 0
     assert L.bpm_plan_set_schedule(p.handle, 1) == -4
     p.close()

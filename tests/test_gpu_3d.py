@@ -140,6 +140,31 @@ def test_3d_one_row_matches_the_2d_march(order):
     assert not within(r, 1e-12 + 1e-14 * w3.Nz), r
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+def test_3d_general_mask(prec):
+    """A crystal mask Pi(x, y, z) that changes with y and z (a wedge whose
+    front moves with y, a hole in a few steps), with Strang splitting,
+    against the oracle with the same mask."""
+    from paper_2201_08500_amd import Plan3D
+    w = W.small3d(Nx=90, Ny=6, Nz=14, Nomega=2, seed=31)
+    x = (np.arange(w.Nx) - w.Nx // 2) * w.dx
+    mask = np.zeros((w.Nz, w.Ny, w.Nx), dtype=bool)
+    for n in range(w.Nz):
+        for i in range(w.Ny):
+            mask[n, i] = x >= (-6 + 2 * i - 0.5 * n) * 1e-6
+    mask[5:8, :, ::7] = False
+    p = Plan3D.from_workload(w, precision=prec, split_order=2, mask=mask)
+    E0 = torch.from_numpy(w.E0_in).to(p.field_dtype).cuda()
+    u = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
+    a, b = p.propagate(E0, u)
+    torch.cuda.synchronize()
+    E0r = w.E0_in if prec == "fp64" else w.E0_in.astype(np.complex64).astype(np.complex128)
+    ra, rb = O.march3d(O.Problem3D.from_workload(w, split_order=2, mask=mask), E0r, w.u)
+    r = report(a.cpu().numpy().astype(np.complex128), b.cpu().numpy().astype(np.complex128),
+               ra, rb)
+    assert not within(r, tol(prec, w.Nz), phase_tol=None if prec == "fp64" else 1e-4), r
+
+
 @pytest.mark.parametrize("order", [1, 2, 4])
 def test_3d_segments_chain_bitwise_fp64(order):
     """bpm_deformation_table, bpm_march and bpm_march_segment on a 3D plan:
