@@ -10,10 +10,15 @@ cache:
      "choices": {"fp32s": {"2048": "split", ...}, ...},
      "times_ms": {"fp32s": {"2048": {"stockham": 2.1, ...}}}}
 
-Plan(schedule=None) applies a cached choice when the environment variable
-BPM_SCHEDULE_CACHE names such a file; otherwise the library's built-in
-default (measured the same way) is used.
+Plan(schedule=None) applies a cached choice from the file named by the
+environment variable BPM_SCHEDULE_CACHE or, when that is unset, from the
+default cache file ($XDG_CACHE_HOME or ~/.cache, then
+bpm_mi355x/schedules.json) if it exists; BPM_SCHEDULE_CACHE set to an empty
+string disables the cache.  Without a cache the library's built-in default
+(measured the same way) is used.  The cache is not checked against the
+device it was measured on.
 
+    python -m paper_2201_08500_amd.autotune              # writes the default cache
     python -m paper_2201_08500_amd.autotune --out schedules.json
 """
 
@@ -101,10 +106,26 @@ def tune(precisions: Iterable[str] = PRECISIONS, sizes: Iterable[int] = SIZES,
     return res
 
 
-def cached_choice(prec: str, Nx: int) -> Optional[str]:
-    """Schedule chosen by the cache named in BPM_SCHEDULE_CACHE, or None."""
-    global _cache, _cache_path
+def default_cache_path() -> str:
+    """$XDG_CACHE_HOME (or ~/.cache)/bpm_mi355x/schedules.json."""
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "bpm_mi355x", "schedules.json")
+
+
+def cache_path() -> Optional[str]:
+    """The cache file in effect: BPM_SCHEDULE_CACHE when set (empty: none),
+    else the default cache file when it exists, else None."""
     path = os.environ.get(ENV)
+    if path is not None:
+        return path or None
+    path = default_cache_path()
+    return path if os.path.exists(path) else None
+
+
+def cached_choice(prec: str, Nx: int) -> Optional[str]:
+    """Schedule chosen by the cache in effect (cache_path), or None."""
+    global _cache, _cache_path
+    path = cache_path()
     if not path:
         return None
     if _cache is None or _cache_path != path:
@@ -119,14 +140,17 @@ def cached_choice(prec: str, Nx: int) -> Optional[str]:
 
 def main():
     ap = argparse.ArgumentParser(description="time the march schedules")
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", default=None,
+                    help="cache file to write (default: the default cache file)")
     ap.add_argument("--precisions", default=",".join(PRECISIONS))
     ap.add_argument("--sizes", default=",".join(str(s) for s in SIZES))
     ap.add_argument("--nz", type=int, default=400)
     ap.add_argument("--reps", type=int, default=5)
     a = ap.parse_args()
+    out = a.out or default_cache_path()
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     res = tune(a.precisions.split(","), [int(s) for s in a.sizes.split(",")],
-               a.nz, a.reps, a.out)
+               a.nz, a.reps, out)
     print(json.dumps(res["choices"]))
 
 

@@ -49,3 +49,23 @@ def test_bad_cache_entry_is_rejected(tmp_path, monkeypatch):
     monkeypatch.setenv(autotune.ENV, str(out))
     with pytest.raises(ValueError):
         autotune.cached_choice("fp32", 1024)
+
+
+def test_default_cache_file_applies_without_the_variable(tmp_path, monkeypatch):
+    """With BPM_SCHEDULE_CACHE unset, a cache in the default location is the
+    plans' default; set to an empty string, the variable disables it."""
+    monkeypatch.delenv(autotune.ENV, raising=False)
+    monkeypatch.setenv("XDG_CACHE_HOME", str(tmp_path))
+    assert autotune.cache_path() is None
+    path = autotune.default_cache_path()
+    assert path == str(tmp_path / "bpm_mi355x" / "schedules.json")
+    (tmp_path / "bpm_mi355x").mkdir()
+    autotune.tune(["fp64"], [2048], nz=10, reps=1, out=path, timer=fake_timer,
+                  device_name="test")
+    assert autotune.cached_choice("fp64", 2048) == "split"
+    from paper_2201_08500_amd import Plan
+    p = Plan(2048, 0.5e-6, 0.5e-6, 10, -1.5e-5, 3.8e-6, 3.8e-6, math.pi / 4,
+             1.24e-10, 2, precision="fp64")
+    assert p.schedule == 2
+    monkeypatch.setenv(autotune.ENV, "")
+    assert autotune.cached_choice("fp64", 2048) is None
