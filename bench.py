@@ -530,6 +530,7 @@ def run_serve(rate, duration, all_fp64, args) -> dict:
               precisions=sorted(set(prec_map.values())), submit_lag_s=lag,
               budget_GB=args.serve_budget_gb, streams=args.serve_streams,
               materialize_parts_s=dict(backend.timing),
+              staging_fallbacks=backend.ring.fallbacks if backend.ring else None,
               offered_cell_updates_per_s=sum(
                   s["Nx"] * s["Nz"] * s["Nomega"] for _, s, _ in trace) / duration)
     del srv, backend

@@ -553,6 +553,45 @@ int validate_job(const bpm_job& j, int idx) {
 
 // Build a batch; with a non-null stream the device work lists are
 // allocated stream-ordered on it.
+// Page-locked host blocks for the work-list uploads of bpm_propagate_batch.
+// The runtime stages a copy from pageable memory through a copy kernel,
+// which has to wait for compute units that a running persistent march
+// holds; a copy from page-locked memory goes to the DMA engines.  A block
+// returns to the pool from a host callback on the stream once its copy has
+// run; blocks are kept until the process ends.
+struct PinnedBlock {
+  void* ptr;
+  size_t cap;
+};
+std::mutex g_pinned_mu;
+std::vector<PinnedBlock> g_pinned_free;
+
+bool pinned_get(size_t bytes, PinnedBlock* out) {
+  {
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    size_t best = g_pinned_free.size();
+    for (size_t i = 0; i < g_pinned_free.size(); ++i)
+      if (g_pinned_free[i].cap >= bytes &&
+          (best == g_pinned_free.size() || g_pinned_free[i].cap < g_pinned_free[best].cap))
+        best = i;
+    if (best < g_pinned_free.size()) {
+      *out = g_pinned_free[best];
+      g_pinned_free.erase(g_pinned_free.begin() + static_cast<long>(best));
+      return true;
+    }
+  }
+  const size_t cap = std::max<size_t>(size_t(1) << 20, (bytes + 0xFFFFF) & ~size_t(0xFFFFF));
+  void* ptr = nullptr;
+  if (hipHostMalloc(&ptr, cap, hipHostMallocDefault) != hipSuccess || !ptr) return false;
+  *out = {ptr, cap};
+  return true;
+}
+
+void pinned_put(const PinnedBlock& b) {
+  std::lock_guard<std::mutex> lock(g_pinned_mu);
+  g_pinned_free.push_back(b);
+}
+
 int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
                 bool stream_ordered, bpm_batch** out) {
   *out = nullptr;
@@ -561,8 +600,13 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
     int rc = validate_job(jobs[i], i);
     if (rc) return rc;
   }
+  // The batch carries a copy of every plan's constants in its own device
+  // allocation, so a plan needs no device copy of its own (no per-plan
+  // allocation or blocking upload at launch time), except for a general
+  // crystal mask, which the plan uploads once.
   for (int i = 0; i < njobs; ++i) {
-    int rc = freeze(const_cast<bpm_plan*>(jobs[i].plan));
+    bpm_plan* p = const_cast<bpm_plan*>(jobs[i].plan);
+    int rc = p->mask.empty() ? bpm::plan_freeze_host(p) : freeze(p);
     if (rc) return fail(rc, "job " + std::to_string(i) + ": " + g_error);
   }
   int dev = 0, n_cu = 0;
@@ -591,6 +635,7 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
     std::vector<int> offsets;
   };
   std::vector<HostGroup> host;
+  std::vector<std::vector<const bpm_plan*>> item_plan;   // per group, per item
   for (auto& kv : by_variant) {
     const int prec = std::get<0>(kv.first), Nx = std::get<1>(kv.first);
     const int sched = std::get<2>(kv.first);
@@ -621,6 +666,7 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
       heap.push(l);
     }
     HostGroup hg{prec, Nx, sched, order, masked, G, {}, {0}};
+    std::vector<const bpm_plan*> plans_of_items;
     for (int g = 0; g < G; ++g) {
       for (auto& s : per_group[g]) {
         const bpm_job& j = jobs[s.first];
@@ -629,12 +675,15 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
                             j.E0_out, j.Eh_out);
         it.slice = s.second;
         hg.items.push_back(it);
+        plans_of_items.push_back(j.plan);
       }
       hg.offsets.push_back(static_cast<int>(hg.items.size()));
     }
     host.push_back(std::move(hg));
+    item_plan.push_back(std::move(plans_of_items));
   }
-  // One device allocation: [items of every group][offsets of every group].
+  // One device allocation: [items of every group][offsets of every group]
+  // [constants of every distinct plan].
   size_t bytes = 0;
   std::vector<size_t> item_off, offs_off;
   for (auto& hg : host) {
@@ -646,6 +695,14 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
     offs_off.push_back(bytes);
     bytes += hg.offsets.size() * sizeof(int);
   }
+  std::map<const bpm_plan*, size_t> sc_off;
+  for (int i = 0; i < njobs; ++i) {
+    const bpm_plan* p = jobs[i].plan;
+    if (sc_off.count(p)) continue;
+    bytes = (bytes + 255) & ~size_t(255);
+    sc_off[p] = bytes;
+    bytes += sizeof(bpm::SliceConst) * size_t(p->Nomega);
+  }
   e = stream_ordered ? hipMallocAsync(&b->d_mem, bytes, alloc_stream)
                      : hipMalloc(&b->d_mem, bytes);
   if (e != hipSuccess) {
@@ -653,20 +710,48 @@ int batch_build(const bpm_job* jobs, int njobs, hipStream_t alloc_stream,
     return fail(BPM_ENOMEM, std::string("batch work lists: ") + hipGetErrorString(e));
   }
   b->stream_ordered = stream_ordered;
-  auto* staging = new std::vector<char>(bytes);
+  char* const dbase = static_cast<char*>(b->d_mem);
+  // host image of the allocation: page-locked for the stream-ordered upload
+  // when a block is available, otherwise ordinary memory
+  PinnedBlock pin{nullptr, 0};
+  const bool pinned = stream_ordered && pinned_get(bytes, &pin);
+  std::vector<char>* staging = pinned ? nullptr : new std::vector<char>(bytes);
+  char* const hbase = pinned ? static_cast<char*>(pin.ptr) : staging->data();
+  for (const auto& kv : sc_off)
+    std::memcpy(hbase + kv.second, kv.first->sc.data(),
+                sizeof(bpm::SliceConst) * size_t(kv.first->Nomega));
   for (size_t g = 0; g < host.size(); ++g) {
-    std::memcpy(staging->data() + item_off[g], host[g].items.data(),
+    for (size_t k = 0; k < host[g].items.size(); ++k) {
+      bpm::BatchItem& it = host[g].items[k];
+      it.p.sc = reinterpret_cast<const bpm::SliceConst*>(dbase + sc_off.at(item_plan[g][k]));
+    }
+    std::memcpy(hbase + item_off[g], host[g].items.data(),
                 host[g].items.size() * sizeof(bpm::BatchItem));
-    std::memcpy(staging->data() + offs_off[g], host[g].offsets.data(),
+    std::memcpy(hbase + offs_off[g], host[g].offsets.data(),
                 host[g].offsets.size() * sizeof(int));
-    char* base = static_cast<char*>(b->d_mem);
+    char* base = dbase;
     b->groups.push_back({host[g].prec, host[g].Nx, host[g].sched, host[g].order,
                          host[g].masked, host[g].n_groups,
                          static_cast<int>(host[g].items.size()),
                          reinterpret_cast<bpm::BatchItem*>(base + item_off[g]),
                          reinterpret_cast<int*>(base + offs_off[g])});
   }
-  if (stream_ordered) {
+  if (stream_ordered && pinned) {
+    // The page-locked block returns to the pool once the copy ran.
+    e = hipMemcpyAsync(b->d_mem, hbase, bytes, hipMemcpyHostToDevice, alloc_stream);
+    if (e == hipSuccess) {
+      e = hipLaunchHostFunc(
+          alloc_stream,
+          [](void* v) {
+            auto* blk = static_cast<PinnedBlock*>(v);
+            pinned_put(*blk);
+            delete blk;
+          },
+          new PinnedBlock(pin));
+    }
+    // a failed enqueue leaks the block rather than risk reusing it while a
+    // copy might still read it
+  } else if (stream_ordered) {
     // The host staging buffer is released by the stream once the copy ran.
     e = hipMemcpyAsync(b->d_mem, staging->data(), bytes, hipMemcpyHostToDevice,
                        alloc_stream);

@@ -405,6 +405,72 @@ class StreamSlots:
         self.last[i] = event
 
 
+class PinnedRing:
+    """Page-locked host staging for request inputs.
+
+    A host array is copied into the next region of a ring of pinned memory
+    and sent to the device with an asynchronous copy on the current stream.
+    Copies from pinned memory go to the DMA engines; copies from pageable
+    memory are staged by the runtime through a copy kernel, which has to
+    wait for compute units that a running persistent march holds, so
+    materialising the next requests stalled for as long as the running
+    launch.  A region is written again only after the event recorded
+    behind its copy has completed; the ring never waits for one (a copy
+    can sit behind kernels of the same batch that wait for the running
+    launch): when the next region is still in use, or an array is larger
+    than the ring, that array takes the ordinary (pageable) path."""
+
+    ALIGN = 256
+
+    def __init__(self, torch, nbytes: int, device):
+        import numpy as np
+        self.torch = torch
+        self.device = device
+        self.n = int(nbytes)
+        self.buf = torch.empty(self.n, dtype=torch.uint8, pin_memory=True)
+        self.host = self.buf.numpy()
+        self.head = 0
+        self.live = collections.deque()      # (start, end, event), oldest first
+        self.fallbacks = 0                   # arrays sent the pageable way
+        self._tdt = {np.dtype(np.complex128): torch.complex128,
+                     np.dtype(np.complex64): torch.complex64,
+                     np.dtype(np.float64): torch.float64}
+
+    def _reserve(self, nbytes: int):
+        size = (nbytes + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+        if size > self.n:
+            return None
+        start = 0 if self.head + size > self.n else self.head
+        end = start + size
+        self.live = collections.deque(r for r in self.live if not r[2].query())
+        if any(a < end and start < b for (a, b, _) in self.live):
+            self.fallbacks += 1
+            return None                       # still being copied: do not wait
+        self.head = end
+        return start, end
+
+    def to_device(self, arr, dtype=None):
+        """Device copy of host array arr (cast to numpy dtype `dtype` on the
+        way), asynchronous on the current stream."""
+        import numpy as np
+        torch = self.torch
+        dt = np.dtype(dtype) if dtype is not None else np.asarray(arr).dtype
+        nbytes = int(np.prod(np.shape(arr))) * dt.itemsize
+        region = self._reserve(nbytes) if dt in self._tdt else None
+        if region is None:
+            return torch.from_numpy(np.ascontiguousarray(arr, dtype=dt)).to(self.device)
+        start, end = region
+        view = self.host[start:start + nbytes].view(dt).reshape(np.shape(arr))
+        np.copyto(view, arr, casting="same_kind")
+        src = self.buf[start:start + nbytes].view(self._tdt[dt]).view(np.shape(arr))
+        out = torch.empty(np.shape(arr), dtype=self._tdt[dt], device=self.device)
+        out.copy_(src, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        self.live.append((start, end, ev))
+        return out
+
+
 class GpuBackend:
     """Device side over libbpm.so: buffers from torch, one bpm_propagate_batch
     per launch on a pool of streams, completion by events.
@@ -414,7 +480,7 @@ class GpuBackend:
     u[n, j] = row[j] + (amp gz[n]) gx[j], or `u` as an array, or no u)."""
 
     def __init__(self, streams: int = 2, device: int = 0, keep_outputs=True,
-                 headroom_bytes: float = 0.0):
+                 headroom_bytes: float = 0.0, staging_bytes: int = 2 << 30):
         """streams: launch streams, one launch in flight on each.  Torch
         caches freed blocks per stream, so each extra stream splits the
         allocator's cache (with four, the split cache filled the memory cap
@@ -422,7 +488,10 @@ class GpuBackend:
 
         headroom_bytes > 0 caps torch's caching allocator at the device's
         memory minus that much, so the HIP runtime (queues, kernel scratch)
-        can always allocate while the allocator holds cached blocks."""
+        can always allocate while the allocator holds cached blocks.
+
+        staging_bytes: size of the pinned host ring that request inputs go
+        through (PinnedRing); 0 copies from pageable memory."""
         import torch
         self.keep_outputs = keep_outputs
         self.torch = torch
@@ -440,6 +509,7 @@ class GpuBackend:
         # launches run
         self.max_retired = 20000
         self.timing = {"plan_s": 0.0, "fields_s": 0.0, "u_s": 0.0, "job_s": 0.0}
+        self.ring = PinnedRing(torch, staging_bytes, self.device) if staging_bytes > 0 else None
 
     @staticmethod
     def _cell(prec):
@@ -493,17 +563,16 @@ class GpuBackend:
                 t1 = time.perf_counter()
                 host_dtype = np.complex128 if plan.field_dtype == torch.complex128 \
                     else np.complex64
-                E0 = torch.from_numpy(np.ascontiguousarray(
-                    w.E0_in, dtype=host_dtype)).to(self.device)
+                E0 = self._to_device(w.E0_in, host_dtype)
                 t2 = time.perf_counter()
                 u = None
                 if w.u is not None:
-                    u = torch.from_numpy(w.u).to(self.device)
+                    u = self._to_device(w.u, np.float64)
                 elif "u_factors" in w.meta:
                     row, gz, gx, amp = w.meta["u_factors"]
-                    gzs = torch.from_numpy(amp * gz).to(self.device)
-                    u = torch.outer(gzs, torch.from_numpy(gx).to(self.device))
-                    u.add_(torch.from_numpy(row).to(self.device))
+                    gzs = self._to_device(amp * gz, np.float64)
+                    u = torch.outer(gzs, self._to_device(gx, np.float64))
+                    u.add_(self._to_device(row, np.float64))
                 t3 = time.perf_counter()
                 req.device = Job(plan, E0, u)
                 t4 = time.perf_counter()
@@ -514,6 +583,12 @@ class GpuBackend:
         except torch.OutOfMemoryError as e:
             req.device = None
             raise Retry(str(e)) from e
+
+    def _to_device(self, arr, dtype):
+        import numpy as np
+        if self.ring is not None:
+            return self.ring.to_device(arr, dtype)
+        return self.torch.from_numpy(np.ascontiguousarray(arr, dtype=dtype)).to(self.device)
 
     def launch(self, reqs):
         from . import propagate_batch

@@ -148,3 +148,31 @@ def test_served_separable_displacement_equals_host_u():
     for r, s, (_, prec) in zip(rs, specs, reqs):
         a, b = standalone(W.c4_problem(s, with_u=True), prec)
         assert torch.equal(r.outputs[0].cpu(), a) and torch.equal(r.outputs[1].cpu(), b), r.rid
+
+
+def test_pinned_staging_ring_wraps_without_overwriting_live_copies():
+    """Inputs go through a pinned host ring with asynchronous copies: with a
+    ring much smaller than the data (regions reused many times, arrays sent
+    the pageable way while their region is still being copied, copies of
+    several dtypes, one array larger than the ring) every device copy equals
+    its host array, including ones cast on the way."""
+    from paper_2201_08500_amd.serve import PinnedRing
+    ring = PinnedRing(torch, 64 << 10, torch.device("cuda", 0))
+    rng = np.random.default_rng(3)
+    s = torch.cuda.Stream()
+    pairs = []
+    with torch.cuda.stream(s):
+        for k in range(200):
+            n = int(rng.integers(1, 3000))
+            if k % 3 == 0:
+                a = rng.normal(size=n)
+                pairs.append((a, ring.to_device(a, np.float64)))
+            else:
+                a = rng.normal(size=(2, n)) + 1j * rng.normal(size=(2, n))
+                dt = np.complex64 if k % 3 == 1 else np.complex128
+                pairs.append((a.astype(dt), ring.to_device(a, dt)))
+        big = rng.normal(size=20000)              # 160 KB: larger than the ring
+        pairs.append((big, ring.to_device(big, np.float64)))
+    torch.cuda.synchronize()
+    for a, d in pairs:
+        assert np.array_equal(d.cpu().numpy(), a)
