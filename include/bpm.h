@@ -105,9 +105,11 @@ bpm_plan* bpm_plan_create(int Nx, double dx, double dz, int Nz,
  * division); the crystal is the slab of bpm_plan_set_crystal for every y.
  * Fields are device [Nomega][Ny][Nx] and u_field device float64
  * [Nz][Ny][Nx].  Nx in [2, 8192]: the propagator step of a row, a cyclic
- * convolution of length Nx, runs on the power of two L = Nx (Nx >= 64) or
- * else the smallest L >= max(2 Nx - 1, 64), Ny in [1, 32]; BPM_PREC_FP64
- * needs L <= 8192 (otherwise the propagate returns BPM_EUNSUPPORTED).  On
+ * convolution of length Nx, runs on L = Nx for powers of two Nx >= 64, else
+ * on the smallest L >= 2 Nx - 1 among the powers of two >= 64 and 4608 =
+ * 9 x 512, 9216 = 9 x 1024; Ny in [1, 32]; BPM_PREC_FP64 needs L <= 9216
+ * (Nx <= 4608 or a power of two <= 8192; otherwise the propagate returns
+ * BPM_EUNSUPPORTED).  On
  * its first propagate the plan builds and keeps on the device FP64 row
  * tables of 32 Nomega (Ny/2 + 1) L bytes (for L != Nx with host FFTs of the
  * device-evaluated propagator, once).  Other arguments and defaults as

@@ -17,8 +17,9 @@
 //
 // Transforms along x of any length: the propagator step of a row is the
 // cyclic convolution of the row with p = IDFT_Nx(P), so for any Nx it is
-// computed on a power of two L: L = Nx for powers of two >= 64, otherwise
-// the smallest power of two >= max(2 Nx - 1, 64).  The row, zero-padded to
+// computed on a length L with small factors: L = Nx for powers of two >= 64,
+// otherwise the smallest L >= 2 Nx - 1 among the powers of two >= 64 and
+// 4608, 9216 (9 M, M = 512, 1024).  The row, zero-padded to
 // L, is transformed, multiplied by the row's table Q = FFT_L(q) / L, where q
 // holds p at offsets -(Nx-1)..Nx-1 wrapped to length L (no two offsets meet
 // for L >= 2 Nx - 1), and transformed back; its first Nx samples are the
@@ -371,6 +372,215 @@ __global__ void __launch_bounds__(F::T) row3_four_kernel(Row3Params p) {
     }
 }
 
+// ------------------------------------------------ rows of length 9 M --
+// exp(-+2 pi i j / 9) for j = 1, 2, 4 and sqrt(3) / 2, correctly rounded.
+constexpr double kC9[3] = {0.766044443118978, 0.17364817766693036, -0.9396926207859084};
+constexpr double kS9[3] = {0.6427876096865394, 0.984807753012208, 0.3420201433256687};
+constexpr double kHalfSqrt3 = 0.8660254037844386;
+
+// a * (c + i si); in FP32 arithmetic the product is formed in FP64 and
+// rounded once, as for every twiddle (see Tw).
+template <class T>
+BPM_INLINE cx<T> cmul_const(cx<T> a, double c, double si) {
+  const double xr = a.x, xi = a.y;
+  return {static_cast<T>(xr * c - xi * si), static_cast<T>(xr * si + xi * c)};
+}
+
+// a * W9^j (INV: conjugated) for j in {1, 2, 4}
+template <int J, bool INV, class T>
+BPM_INLINE cx<T> tw9(cx<T> a) {
+  constexpr int i = J == 1 ? 0 : J == 2 ? 1 : 2;
+  static_assert(J == 1 || J == 2 || J == 4, "W9 power");
+  return cmul_const(a, kC9[i], INV ? kS9[i] : -kS9[i]);
+}
+
+// 3-point DFT (a, b, c) -> (X0, X1, X2): s = b + c, d = b - c,
+// X0 = a + s, X1,2 = a - s / 2 -+ i (sqrt 3 / 2) d (forward; +- inverse).
+// NZ: inputs that can be nonzero (3, or 2 with c = 0, or 1 with b = c = 0).
+template <bool INV, int NZ, class T>
+BPM_INLINE void dft3(cx<T>& a, cx<T>& b, cx<T>& c) {
+  if constexpr (NZ == 1) {
+    b = a;
+    c = a;
+  } else {
+    const cx<T> s = NZ == 3 ? b + c : b;
+    const cx<T> d = NZ == 3 ? b - c : b;
+    const cx<T> m = {a.x - T(0.5) * s.x, a.y - T(0.5) * s.y};
+    const cx<T> rd = rot<INV>(d);
+    a = a + s;
+    if constexpr (sizeof(T) == 8) {
+      b = {m.x + kHalfSqrt3 * rd.x, m.y + kHalfSqrt3 * rd.y};
+      c = {m.x - kHalfSqrt3 * rd.x, m.y - kHalfSqrt3 * rd.y};
+    } else {
+      // the product formed in FP64 and rounded once (see Tw)
+      const cx<T> r = {static_cast<T>(kHalfSqrt3 * static_cast<double>(rd.x)),
+                       static_cast<T>(kHalfSqrt3 * static_cast<double>(rd.y))};
+      b = m + r;
+      c = m - r;
+    }
+  }
+}
+
+// 9-point DFT as 3 x 3 (n = 3 n1 + n2, k = k1 + 3 k2) of y[0..NZ) (the
+// rest zero), natural order out in X[9].
+template <bool INV, int NZ, class T>
+BPM_INLINE void dft9(const cx<T> (&y)[9], cx<T> (&X)[9]) {
+  static_assert(NZ == 5 || NZ == 9, "pruned forms built: 5 or 9 inputs");
+  cx<T> a[3][3];   // a[n2][k1]
+#pragma unroll
+  for (int n2 = 0; n2 < 3; ++n2) {
+    a[n2][0] = y[n2];
+    a[n2][1] = y[n2 + 3];
+    a[n2][2] = y[n2 + 6];
+  }
+  if constexpr (NZ == 9) {
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) dft3<INV, 3>(a[n2][0], a[n2][1], a[n2][2]);
+  } else {
+    // y[5..8] = 0: column n2 = 0, 1 has inputs (y n2, y n2+3, 0), n2 = 2 only y2
+    dft3<INV, 2>(a[0][0], a[0][1], a[0][2]);
+    dft3<INV, 2>(a[1][0], a[1][1], a[1][2]);
+    dft3<INV, 1>(a[2][0], a[2][1], a[2][2]);
+  }
+  a[1][1] = tw9<1, INV>(a[1][1]);
+  a[1][2] = tw9<2, INV>(a[1][2]);
+  a[2][1] = tw9<2, INV>(a[2][1]);
+  a[2][2] = tw9<4, INV>(a[2][2]);
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    dft3<INV, 3>(a[0][k1], a[1][k1], a[2][k1]);
+    X[k1] = a[0][k1];
+    X[k1 + 3] = a[1][k1];
+    X[k1 + 6] = a[2][k1];
+  }
+}
+
+// Rows of length L = 9 M (M = 512, 1024) for Nx <= 4.5 M, where the next
+// power of two would be 2 L * 8 / 9: the four-step layout of RowFour with
+// W = 9 wavefronts (T = 576 threads) and a radix-9 step.  The M columns
+// x[m + M q] (q < 9) are shared out over the threads, t + T c for c <
+// ceil(M / T) (the last set partial, whole wavefronts idle), and read from
+// and written to HBM directly by the radix-9 steps; only q < 5 can be
+// nonzero on input (Nx <= 4.5 M) or is needed on output.  The block
+// exchange and the in-wavefront transforms are those of RowFour: slot i of
+// lane l of wavefront w holds bin w + 9 (l + 64 i) between the transforms.
+// At M = 1024 in the FP32 storage modes a row takes 80 KB of LDS, so two
+// rows share a CU (five wavefronts per SIMD, 96 VGPRs).
+template <class In_, int WAVES_PER_EU>
+struct RowNine {
+  using In = In_;
+  using CT = typename In::CT;
+  using ST = typename In::ST;
+  using SV = typename In::SV;
+  static constexpr int W = 9, M = In::N, R = In::R, N = W * M, T = 64 * W;
+  static constexpr int NC = (M + T - 1) / T;   // column sets per thread
+  static constexpr int QN = 5;                 // q < QN: possibly nonzero samples
+  static constexpr int kWavesPerEu = WAVES_PER_EU;
+  static_assert(In::T == 64, "one wavefront per in-wave transform");
+  static constexpr int kRegion = In::kEnv;
+  static constexpr size_t kLdsSlots = size_t(W) * kRegion;
+  static constexpr bool kFits = kLdsSlots * sizeof(SV) <= 160 * 1024;
+
+  BPM_INLINE static void put(SV* lds, int idx, cx<CT> v) {
+    SV s;
+    s.x = static_cast<ST>(v.x);
+    s.y = static_cast<ST>(v.y);
+    lds[idx] = s;
+  }
+
+  BPM_INLINE static void forward(cx<ST> (&v)[1][R], const SV* line, int Nx,
+                                 const cx<double>* tab, SV* lds, int t) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int m = opaque(t) + T * c;
+      if (T * (c + 1) <= M || m < M) {
+        cx<CT> y[9], X[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          SV s;
+          s.x = 0;
+          s.y = 0;
+          if (q < QN && m + M * q < Nx) s = line[m + M * q];
+          y[q] = {static_cast<CT>(s.x), static_cast<CT>(s.y)};
+        }
+        dft9<false, QN>(y, X);
+#pragma unroll
+        for (int k1 = 0; k1 < W; ++k1)
+          put(lds + k1 * kRegion, m, k1 ? Tw<CT>{tab[m * k1]}.mul(X[k1]) : X[k1]);
+      }
+    }
+    lds_barrier();
+    const int l = t & 63;
+    SV* own = lds + (t >> 6) * kRegion;
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[0][i] = In::template load_as<ST>(own, l + 64 * i);
+    wave_sync();
+    int xbuf = 0;
+    In::template fft_n<false, In::kWave, 1>(v, TwGlobal<In, N>{tab}, own, opaque(l), xbuf);
+  }
+
+  BPM_INLINE static void inverse(cx<ST> (&v)[1][R], SV* line, int Nx,
+                                 const cx<double>* tab, SV* lds, int t) {
+    const int l = t & 63;
+    SV* own = lds + (t >> 6) * kRegion;
+    int xbuf = 0;
+    In::template fft_n<true, In::kWave, 1>(v, TwGlobal<In, N>{tab}, own, opaque(l), xbuf);
+#pragma unroll
+    for (int i = 0; i < R; ++i) put(own, l + 64 * i, conv<CT>(v[0][i]));
+    lds_barrier();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int m = opaque(t) + T * c;
+      if (T * (c + 1) <= M || m < M) {
+        cx<CT> z[9], y[9];
+#pragma unroll
+        for (int k1 = 0; k1 < W; ++k1) {
+          z[k1] = In::template load_as<CT>(lds + k1 * kRegion, m);
+          if (k1 > 0) z[k1] = Tw<CT>{tab[m * k1]}.mulc(z[k1]);
+        }
+        dft9<true, 9>(z, y);
+#pragma unroll
+        for (int q = 0; q < QN; ++q)
+          if (m + M * q < Nx) {
+            SV s;
+            s.x = static_cast<ST>(y[q].x);
+            s.y = static_cast<ST>(y[q].y);
+            line[m + M * q] = s;
+          }
+      }
+    }
+  }
+};
+
+// One row per work group with the radix-9 four-step transform; Q holds
+// each row's table in the kernel's bin order (as for row3_four_kernel).
+template <class F>
+__global__ void __launch_bounds__(F::T) __attribute__((amdgpu_waves_per_eu(F::kWavesPerEu)))
+row3_nine_kernel(Row3Params p) {
+  using ST = typename F::ST;
+  using SV = typename F::SV;
+  constexpr int R = F::R, T = F::T;
+  __shared__ __align__(16) SV lds[F::kLdsSlots];
+  const int t = threadIdx.x;
+  const int row = blockIdx.x;
+  const int ky = row % p.Ny;
+  const int env = (row / p.Ny) & 1;
+  const int w = row / (2 * p.Ny);
+  SV* line = static_cast<SV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
+  const cx<double>* Qrow = p.Q + size_t(table_row(row, p.Ny)) * F::N;
+  cx<ST> v[1][R];
+  F::forward(v, line, p.Nx, p.tw, lds, t);
+  phase_fence();
+  const int tq = opaque(t);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (i % 4 == 0) phase_fence();     // table loads in groups of four
+    v[0][i] = conv<ST>(cmul(to_d(v[0][i]), Qrow[i * T + tq]));
+  }
+  phase_fence();
+  F::inverse(v, line, p.Nx, p.tw, lds, t);
+}
+
 struct Col3Params {
   const void* E0_in;          // x-space input psi~_+ (first launch)
   const void* Eh_in;          // x-space input psi~_- (first launch), or nullptr: zero
@@ -543,17 +753,29 @@ template <int PREC> struct Row3T<PREC, 2048> { using type = March<PREC, 2048, 8,
 template <int PREC> struct Row3T<PREC, 4096> { using type = March<PREC, 4096, 8, 8, 8, 8, 8>; };
 template <int PREC> struct Row3T<PREC, 8192> { using type = RowFour<InWave1024<PREC>, 8>; };
 template <int PREC> struct Row3T<PREC, 16384> { using type = RowFour<InWave1024<PREC>, 16>; };
+// 9 M: waves per SIMD requested where LDS lets several rows share a CU
+// (FP32 storage: two rows of 9216, three of 4608; FP64: one row)
+template <int PREC> struct Row3T<PREC, 4608> {
+  using type = RowNine<InWave512<PREC>, PREC == BPM_PREC_FP64 ? 1 : 7>;
+};
+template <int PREC> struct Row3T<PREC, 9216> {
+  using type = RowNine<InWave1024<PREC>, PREC == BPM_PREC_FP64 ? 1 : 5>;
+};
 
 template <int PREC, int L>
 int launch_row3_l(int rows, const Row3Params& p, hipStream_t s) {
-  using M = typename Row3T<PREC, L>::type;
-  if constexpr ((PREC == BPM_PREC_FP64 ? 2 : 1) * L > 16384) {
-    return BPM_EUNSUPPORTED;   // an FP64 row of this length does not fit in LDS
+  if constexpr (!row3_fits(PREC, L)) {
+    return BPM_EUNSUPPORTED;   // a row of this length and storage does not fit in LDS
   } else {
-    if constexpr (L >= kRow3FourStepMin)
+    using M = typename Row3T<PREC, L>::type;
+    if constexpr (L % 9 == 0) {
+      if (2 * p.Nx > L) return BPM_EINVAL;   // the radix-9 steps read and write q < 5
+      hipLaunchKernelGGL((row3_nine_kernel<M>), dim3(rows), dim3(M::T), 0, s, p);
+    } else if constexpr (L >= kRow3FourStepMin) {
       hipLaunchKernelGGL((row3_four_kernel<M>), dim3(rows), dim3(M::T), 0, s, p);
-    else
+    } else {
       hipLaunchKernelGGL((row3_kernel<M>), dim3(rows), dim3(M::T), 0, s, p);
+    }
     return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
   }
 }
@@ -568,7 +790,9 @@ int launch_row3_p(int L, int rows, const Row3Params& p, hipStream_t s) {
     case 1024: return launch_row3_l<PREC, 1024>(rows, p, s);
     case 2048: return launch_row3_l<PREC, 2048>(rows, p, s);
     case 4096: return launch_row3_l<PREC, 4096>(rows, p, s);
+    case 4608: return launch_row3_l<PREC, 4608>(rows, p, s);
     case 8192: return launch_row3_l<PREC, 8192>(rows, p, s);
+    case 9216: return launch_row3_l<PREC, 9216>(rows, p, s);
     case 16384: return launch_row3_l<PREC, 16384>(rows, p, s);
     default: return BPM_EUNSUPPORTED;
   }

@@ -122,8 +122,8 @@ cplx mul_h(cplx a, cplx b) {
 
 // Forward FFT (kernel exp(-2 pi i jk / n), no scaling) of a power-of-two
 // length n in FP64, in place: iterative radix 2, twiddles from the table
-// tab[m] = exp(-2 pi i m / n).
-void fft_host(cplx* a, size_t n, const cplx* tab) {
+// tab[m stride] = exp(-2 pi i m / n) (a table of length n stride).
+void fft_host(cplx* a, size_t n, const cplx* tab, size_t stride = 1) {
   for (size_t i = 1, j = 0; i < n; ++i) {
     size_t bit = n >> 1;
     for (; j & bit; bit >>= 1) j ^= bit;
@@ -131,10 +131,10 @@ void fft_host(cplx* a, size_t n, const cplx* tab) {
     if (i < j) std::swap(a[i], a[j]);
   }
   for (size_t len = 2; len <= n; len <<= 1) {
-    const size_t stride = n / len;
+    const size_t step = n / len * stride;
     for (size_t i = 0; i < n; i += len) {
       for (size_t k = 0; k < len / 2; ++k) {
-        const cplx u = a[i + k], v = mul_h(a[i + k + len / 2], tab[k * stride]);
+        const cplx u = a[i + k], v = mul_h(a[i + k + len / 2], tab[k * step]);
         a[i + k] = u + v;
         a[i + k + len / 2] = u - v;
       }
@@ -142,23 +142,56 @@ void fft_host(cplx* a, size_t n, const cplx* tab) {
   }
 }
 
+// Forward FFT of length n = 9 M (M a power of two) in FP64, in place, by
+// the four-step decomposition n = m + M q, k = k1 + 9 k2: a direct 9-point
+// DFT over q for every m, the twiddle W_n^{m k1}, then nine M-point FFTs.
+// tab[j] = exp(-2 pi i j / n).
+void fft_nine_host(cplx* a, size_t n, const cplx* tab) {
+  const size_t M = n / 9;
+  std::vector<cplx> b(n);   // b[k1 M + m]
+  for (size_t m = 0; m < M; ++m)
+    for (size_t k1 = 0; k1 < 9; ++k1) {
+      cplx acc(0.0, 0.0);
+      for (size_t q = 0; q < 9; ++q) acc += mul_h(a[m + M * q], tab[(M * q * k1) % n]);
+      b[k1 * M + m] = mul_h(acc, tab[m * k1]);
+    }
+  for (size_t k1 = 0; k1 < 9; ++k1) {
+    fft_host(b.data() + k1 * M, M, tab, 9);
+    for (size_t k2 = 0; k2 < M; ++k2) a[k1 + 9 * k2] = b[k1 * M + k2];
+  }
+}
+
+// Bluestein's convolution length for Nx: the smallest power of two >=
+// max(2 Nx - 1, 64).
+size_t bluestein_length(int Nx) {
+  size_t L = 64;
+  while (L < size_t(2) * Nx - 1) L <<= 1;
+  return L;
+}
+
 // FP64 tables of a 3D plan: the length-L twiddles exp(-2 pi i m / L), the
 // y-DFT twiddles exp(-2 pi i j / Ny) (both on the device), and for lengths
 // Nx that are not transformed directly the chirp w_n = exp(-i pi n^2 / Nx)
-// (n^2 reduced modulo 2 Nx in integers) and G = FFT_L(conj(w) wrapped
-// circularly) / L of Bluestein's algorithm (host only).
+// (n^2 reduced modulo 2 Nx in integers), the twiddles twb of Bluestein's
+// power-of-two length Lb and G = FFT_Lb(conj(w) wrapped circularly) / Lb
+// (host only).
 struct Tables3 {
-  std::vector<cplx> tw, wy, chirp, G;
+  std::vector<cplx> tw, wy, chirp, twb, G;
 };
 
-Tables3 tables3(const bpm_plan* p) {
-  const int N = p->Nx, L = p->L3, Ny = p->Ny;
-  Tables3 t;
-  t.tw.resize(L);
-  for (int m = 0; m < L; ++m) {
+std::vector<cplx> twiddles_host(size_t L) {
+  std::vector<cplx> tw(L);
+  for (size_t m = 0; m < L; ++m) {
     const double ang = -2.0 * M_PI * double(m) / double(L);
-    t.tw[m] = cplx(std::cos(ang), std::sin(ang));
+    tw[m] = cplx(std::cos(ang), std::sin(ang));
   }
+  return tw;
+}
+
+Tables3 tables3(const bpm_plan* p) {
+  const int N = p->Nx, Ny = p->Ny;
+  Tables3 t;
+  t.tw = twiddles_host(size_t(p->L3));
   t.wy.resize(Ny);
   for (int j = 0; j < Ny; ++j) {
     const double ang = -2.0 * M_PI * double(j) / double(Ny);
@@ -171,11 +204,13 @@ Tables3 tables3(const bpm_plan* p) {
       const double ang = -M_PI * double(m) / double(N);
       t.chirp[n] = cplx(std::cos(ang), std::sin(ang));
     }
-    t.G.assign(L, cplx(0.0, 0.0));
+    const size_t Lb = bluestein_length(N);
+    t.twb = size_t(p->L3) == Lb ? t.tw : twiddles_host(Lb);
+    t.G.assign(Lb, cplx(0.0, 0.0));
     for (int m = 0; m < N; ++m) t.G[m] = std::conj(t.chirp[m]);
-    for (int m = 1; m < N; ++m) t.G[L - m] = std::conj(t.chirp[m]);
-    fft_host(t.G.data(), L, t.tw.data());
-    for (auto& v : t.G) v /= double(L);
+    for (int m = 1; m < N; ++m) t.G[Lb - m] = std::conj(t.chirp[m]);
+    fft_host(t.G.data(), Lb, t.twb.data());
+    for (auto& v : t.G) v /= double(Lb);
   }
   return t;
 }
@@ -183,32 +218,36 @@ Tables3 tables3(const bpm_plan* p) {
 // Row tables Q = FFT_L(q) / L of a plan whose Nx is not transformed
 // directly, from its propagator rows P (length Nx, FP64): p = IDFT_Nx(P)
 // (unnormalised) = conj(DFT_Nx(conj(P))) by Bluestein's algorithm
-// (X_k = w_k (a * conj(w))_k, a_n = x_n w_n, the cyclic convolution on L),
-// then q_d = p_d and q_{L-Nx+d} = p_d (d >= 1), zero elsewhere.  Rows are
-// shared out over host threads.
+// (X_k = w_k (a * conj(w))_k, a_n = x_n w_n, the cyclic convolution on the
+// power of two Lb), then q_d = p_d and q_{L-Nx+d} = p_d (d >= 1), zero
+// elsewhere, and its FFT on the row length L (a power of two or 9 M).  Rows
+// are shared out over host threads.
 void rows3_bluestein(const bpm_plan* p, const Tables3& t, const std::vector<cplx>& P,
                      std::vector<cplx>& Q) {
   const int N = p->Nx;
-  const size_t L = size_t(p->L3);
+  const size_t L = size_t(p->L3), Lb = t.G.size();
   const size_t rows = size_t(p->Nomega) * 2 * (p->Ny / 2 + 1);   // table rows
   Q.assign(rows * L, cplx(0.0, 0.0));
   auto work = [&](size_t r0, size_t r1) {
-    std::vector<cplx> buf(L), q(L);
+    std::vector<cplx> buf(Lb), q(L);
     for (size_t r = r0; r < r1; ++r) {
       const cplx* Pr = P.data() + r * N;
       std::fill(buf.begin(), buf.end(), cplx(0.0, 0.0));
       for (int n = 0; n < N; ++n) buf[n] = mul_h(std::conj(Pr[n]), t.chirp[n]);
-      fft_host(buf.data(), L, t.tw.data());
+      fft_host(buf.data(), Lb, t.twb.data());
       // conj of the unnormalised inverse transform: buf = conj(a * conj(w))
-      for (size_t j = 0; j < L; ++j) buf[j] = std::conj(mul_h(buf[j], t.G[j]));
-      fft_host(buf.data(), L, t.tw.data());
+      for (size_t j = 0; j < Lb; ++j) buf[j] = std::conj(mul_h(buf[j], t.G[j]));
+      fft_host(buf.data(), Lb, t.twb.data());
       std::fill(q.begin(), q.end(), cplx(0.0, 0.0));
       for (int d = 0; d < N; ++d) {
         const cplx pd = mul_h(std::conj(t.chirp[d]), buf[d]);   // conj(X_d)
         q[d] = pd;
         if (d > 0) q[L - N + d] = pd;
       }
-      fft_host(q.data(), L, t.tw.data());
+      if (is_pow2(int(L)))
+        fft_host(q.data(), L, t.tw.data());
+      else
+        fft_nine_host(q.data(), L, t.tw.data());
       cplx* Qr = Q.data() + r * L;
       for (size_t j = 0; j < L; ++j) Qr[j] = q[j] / double(L);
     }
@@ -239,11 +278,11 @@ int freeze_host_locked(bpm_plan* p) {
   return BPM_OK;
 }
 
-// Rows of length L >= kRow3FourStepMin are read by the four-step row
-// kernel in its bin order: entry i T + t of a row is bin w + W (l + 64 i)
-// of thread t = 64 w + l (W = L / 1024, T = 64 W, i < 16).
+// Rows that the four-step row kernels read (row3_four_step) are stored in
+// their bin order: entry i T + t of a row is bin w + W (l + 64 i) of thread
+// t = 64 w + l (W = row3_waves(L), T = 64 W, i < L / T).
 void permute_rows3(std::vector<cplx>& Q, size_t rows, int L) {
-  const int W = L / 1024, T = 64 * W, R = L / T;
+  const int W = bpm::row3_waves(L), T = 64 * W, R = L / T;
   std::vector<cplx> tmp(L);
   for (size_t r = 0; r < rows; ++r) {
     cplx* q = Q.data() + r * size_t(L);
@@ -303,7 +342,7 @@ int upload_tables3(bpm_plan* p) {
   }
   // The propagator is evaluated on the device; the rows go through the host
   // when they need the cyclic-convolution table or the four-step bin order.
-  const bool via_host = p->bluestein || p->L3 >= bpm::kRow3FourStepMin;
+  const bool via_host = p->bluestein || bpm::row3_four_step(p->L3);
   for (int set = 0; set < nsets; ++set) {
     cplx* dst = static_cast<cplx*>(p->dev_rows3) + size_t(set) * rows * L;
     void* P = dst;
@@ -331,7 +370,7 @@ int upload_tables3(bpm_plan* p) {
       rows3_bluestein(p, t, hP, Q);
     else
       Q.swap(hP);
-    if (p->L3 >= bpm::kRow3FourStepMin) permute_rows3(Q, rows, p->L3);
+    if (bpm::row3_four_step(p->L3)) permute_rows3(Q, rows, p->L3);
     e = hipMemcpy(dst, Q.data(), Q.size() * sizeof(cplx), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(3D row propagators)");
   }
@@ -397,9 +436,9 @@ int reject_3d(const bpm_plan* p, const char* what) {
 // launches of every sub-step (bpm3d.hip).
 int march3(bpm_plan* p, const void* E0_in, const void* Eh_in, const void* table, int n0,
            int nsteps, void* E0_out, void* Eh_out, hipStream_t s) {
-  if (p->precision == BPM_PREC_FP64 && p->L3 > 8192)
-    return fail(BPM_EUNSUPPORTED, "FP64 3D rows need a transform length <= 8192 "
-                                  "(Nx <= 4096, or a power of two <= 8192)");
+  if (!bpm::row3_fits(p->precision, p->L3))
+    return fail(BPM_EUNSUPPORTED, "FP64 3D rows need a transform length <= 9216 "
+                                  "(Nx <= 4608, or a power of two <= 8192)");
   int rc = freeze(p);
   if (rc) return rc;
   const cplx* t3 = static_cast<const cplx*>(p->dev_tables3);
@@ -441,9 +480,9 @@ int march3(bpm_plan* p, const void* E0_in, const void* Eh_in, const void* table,
 // The whole 3D march: deformation table, then every step.
 int propagate3(bpm_plan* p, const void* E0_in, const double* u_field, void* E0_out,
                void* Eh_out, void* workspace, hipStream_t s) {
-  if (p->precision == BPM_PREC_FP64 && p->L3 > 8192)
-    return fail(BPM_EUNSUPPORTED, "FP64 3D rows need a transform length <= 8192 "
-                                  "(Nx <= 4096, or a power of two <= 8192)");
+  if (!bpm::row3_fits(p->precision, p->L3))
+    return fail(BPM_EUNSUPPORTED, "FP64 3D rows need a transform length <= 9216 "
+                                  "(Nx <= 4608, or a power of two <= 8192)");
   int rc = freeze(p);
   if (rc) return rc;
   void* table = nullptr;
@@ -858,12 +897,7 @@ bpm_plan* bpm_plan_create_3d(int Nx, int Ny, double dx, double dy, double dz, in
   p->dy = dy;
   p->three_d = true;
   p->bluestein = !(is_pow2(Nx) && Nx >= 64);
-  int L = 64;
-  if (p->bluestein)
-    while (L < 2 * Nx - 1) L <<= 1;
-  else
-    L = Nx;
-  p->L3 = L;
+  p->L3 = bpm::row3_length(Nx);
   return p;
 }
 

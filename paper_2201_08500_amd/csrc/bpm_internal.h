@@ -112,10 +112,28 @@ int launch_prop3(void* P, const SliceConst* sc, int Nx, int Ny, int Nomega, doub
                  double dy, double dz, double frac, double h_half, hipStream_t stream);
 int launch_march3(const March3Params& q, hipStream_t stream);
 // Row lengths from which the 3D row kernel uses the four-step layout
-// (W = L / 1024 wavefronts, 1024-point in-wavefront transforms): its row
-// tables are stored with entry i T + t holding bin w + W (l + 64 i) of
-// thread t = 64 w + l, T = 64 W, i < 16.
+// (W = L / 1024 wavefronts, 1024-point in-wavefront transforms), and the
+// lengths 9 M (M = 512, 1024) with W = 9 wavefronts of M-point transforms:
+// their row tables are stored with entry i T + t holding bin w + W (l + 64 i)
+// of thread t = 64 w + l, T = 64 W, i < L / T.
 constexpr int kRow3FourStepMin = 8192;
+constexpr bool row3_four_step(int L) { return L >= kRow3FourStepMin || L % 9 == 0; }
+constexpr int row3_waves(int L) { return L % 9 == 0 ? 9 : L / 1024; }
+// Whether a row of length L fits in LDS in the plan's storage type (FP64
+// rows of 16384 samples do not).
+constexpr bool row3_fits(int prec, int L) { return prec != BPM_PREC_FP64 || L <= 9216; }
+// The row transform length for Nx samples: Nx for powers of two >= 64;
+// otherwise the smallest length >= 2 Nx - 1 among the powers of two >= 64
+// and 4608, 9216 (which save 44% of the padded work where they apply:
+// 2048 < Nx <= 2304 and 4096 < Nx <= 4608).
+inline int row3_length(int Nx) {
+  if (Nx >= 64 && (Nx & (Nx - 1)) == 0) return Nx;
+  int L = 64;
+  while (L < 2 * Nx - 1) L <<= 1;
+  for (int c : {4608, 9216})
+    if (2 * Nx - 1 <= c && c < L) return c;
+  return L;
+}
 
 }  // namespace bpm
 
