@@ -73,6 +73,10 @@ BPM_INLINE cx<double> to_d(cx<T> a) {
   return {static_cast<double>(a.x), static_cast<double>(a.y)};
 }
 BPM_INLINE cx<double> conjd(cx<double> a) { return {a.x, -a.y}; }
+// acc + a w with each component one expression (two FMAs)
+BPM_INLINE cx<double> cmac(cx<double> acc, cx<double> a, cx<double> w) {
+  return {acc.x + a.x * w.x - a.y * w.y, acc.y + a.x * w.y + a.y * w.x};
+}
 
 // exp(i frac dz sqrt(k^2 - (K_x + band h/2)^2 - K_y^2)) / (Nx Ny) for signed bins
 // (mx, my), K = 2 pi m / (N d), evaluated and reduced modulo 2 pi in
@@ -605,7 +609,11 @@ constexpr int kMaxNy = 32;
 // column x of both envelopes: samples in x space, bins K_y in k space.  All
 // lanes of a wavefront share r, so each DFT twiddle is one wavefront-wide
 // value, and every input read from LDS serves both of the thread's outputs.
-template <class ST>
+// EVEN (Ny even): the outputs r and r + Ny/2 are E + O and E - O, E and O
+// the sums over the even and the odd inputs with the twiddles of r (those
+// of r + Ny/2 differ by (-1)^n), so each DFT takes Ny products, not 2 Ny.
+// LDS: 2 Ny kCol FP64 samples (dynamic, 45 KB at Ny = 22).
+template <class ST, bool EVEN>
 __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
   using SV = typename vec2<ST>::type;
   __shared__ cx<double> sa[kMaxNy * kCol];
@@ -631,17 +639,34 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
     static_cast<SV*>(f)[i] = s;
   };
   // coupling sub-step j of this launch inside the crystal (Eq. fov10, Eq.
-  // Authier, the sub-step constants of Eq. split-op) at (x, y_i): the slab,
-  // or the general mask row of the sub-step's step
+  // Authier, the sub-step constants of Eq. split-op) at (x, y_i), i = i0
+  // (r = 0) or i1 (r = 1): the slab, or the general mask row of the
+  // sub-step's step.  The deformation factors and mask bytes are loaded
+  // here, before the transforms, so that their latency overlaps them.
   const double xp = static_cast<double>(x - p.Nx / 2) * p.dx;
   const bool in_slab = xp >= p.x_front && xp < p.x_end;
-  auto couple = [&](cx<double>& a, cx<double>& b, int i, int j) {
-    if (p.mask ? !p.mask[(size_t(p.row[j]) * Ny + i) * p.Nx + x] : !in_slab) return;
+  bool inside[2][2];
+  SV fac[2][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      inside[j][r] = false;
+      fac[j][r].x = 1;
+      fac[j][r].y = 0;
+      if (j < p.nb && valid && (r == 0 || two)) {
+        const size_t idx = (size_t(p.row[j]) * Ny + (r ? i1 : i0)) * p.Nx + x;
+        inside[j][r] = p.mask ? p.mask[idx] != 0 : in_slab;
+        if (p.table) fac[j][r] = static_cast<const SV*>(p.table)[idx];
+      }
+    }
+  auto couple = [&](cx<double>& a, cx<double>& b, int r, int j) {
+    if (!inside[j][r]) return;
     const double* d = p.sc[w].d[p.sub[j]];
     const cx<double> d0 = {d[0], d[1]};
     cx<double> cp = {d[2], d[3]}, cm = {d[4], d[5]};
     if (p.table) {
-      const cx<double> e = ld(p.table, (size_t(p.row[j]) * Ny + i) * p.Nx + x);
+      const cx<double> e = {static_cast<double>(fac[j][r].x), static_cast<double>(fac[j][r].y)};
       cp = cmul(cp, e);
       cm = cmulc(cm, e);
     }
@@ -649,8 +674,10 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
     a = cmuladd(d0, a0, cp, b);
     b = cmuladd(d0, b, cm, a0);
   };
-  auto couple_all = [&](cx<double>& a, cx<double>& b, int i) {
-    for (int j = 0; j < p.nb; ++j) couple(a, b, i, j);
+  auto couple_all = [&](cx<double>& a, cx<double>& b, int r) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (j < p.nb) couple(a, b, r, j);
   };
   cx<double> a0 = {0.0, 0.0}, b0 = {0.0, 0.0}, a1 = {0.0, 0.0}, b1 = {0.0, 0.0};
   if (p.mode == 0) {
@@ -663,8 +690,8 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
       }
     }
     if (valid) {
-      couple_all(a0, b0, i0);
-      if (two) couple_all(a1, b1, i1);
+      couple_all(a0, b0, 0);
+      if (two) couple_all(a1, b1, 1);
     }
   } else {
     if (valid) {
@@ -677,24 +704,44 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
     }
     lds_barrier();
     // inverse DFT along y (unnormalised; 1/Ny is in the propagator)
-    for (int k = 0, m0 = 0, m1 = 0; k < Ny; ++k) {   // m = i k mod Ny
-      const cx<double> A = sa[k * kCol + xl], B = sb[k * kCol + xl];
-      const cx<double> t0 = conjd(p.wy[m0]);
-      a0 = a0 + cmul(A, t0);
-      b0 = b0 + cmul(B, t0);
-      if (two) {
-        const cx<double> t1 = conjd(p.wy[m1]);
-        a1 = a1 + cmul(A, t1);
-        b1 = b1 + cmul(B, t1);
+    if constexpr (EVEN) {
+      cx<double> ao = {0.0, 0.0}, bo = {0.0, 0.0};   // odd inputs; even in a0, b0
+      for (int k = 0, m0 = 0; k < Ny; k += 2) {      // m0 = i0 k mod Ny
+        const cx<double> t0 = conjd(p.wy[m0]);
+        a0 = cmac(a0, sa[k * kCol + xl], t0);
+        b0 = cmac(b0, sb[k * kCol + xl], t0);
+        m0 += i0;
+        if (m0 >= Ny) m0 -= Ny;
+        const cx<double> t1 = conjd(p.wy[m0]);
+        ao = cmac(ao, sa[(k + 1) * kCol + xl], t1);
+        bo = cmac(bo, sb[(k + 1) * kCol + xl], t1);
+        m0 += i0;
+        if (m0 >= Ny) m0 -= Ny;
       }
-      m0 += i0;
-      if (m0 >= Ny) m0 -= Ny;
-      m1 += i1 - Ny;             // i1 < Ny: one correction suffices
-      if (m1 < 0) m1 += Ny;
+      a1 = a0 - ao;
+      b1 = b0 - bo;
+      a0 = a0 + ao;
+      b0 = b0 + bo;
+    } else {
+      for (int k = 0, m0 = 0, m1 = 0; k < Ny; ++k) {   // m = i k mod Ny
+        const cx<double> A = sa[k * kCol + xl], B = sb[k * kCol + xl];
+        const cx<double> t0 = conjd(p.wy[m0]);
+        a0 = cmac(a0, A, t0);
+        b0 = cmac(b0, B, t0);
+        if (two) {
+          const cx<double> t1 = conjd(p.wy[m1]);
+          a1 = cmac(a1, A, t1);
+          b1 = cmac(b1, B, t1);
+        }
+        m0 += i0;
+        if (m0 >= Ny) m0 -= Ny;
+        m1 += i1 - Ny;             // i1 < Ny: one correction suffices
+        if (m1 < 0) m1 += Ny;
+      }
     }
     if (valid) {
-      couple_all(a0, b0, i0);
-      if (two) couple_all(a1, b1, i1);
+      couple_all(a0, b0, 0);
+      if (two) couple_all(a1, b1, 1);
     }
     lds_barrier();        // every column read before it is overwritten
   }
@@ -717,20 +764,40 @@ __global__ void __launch_bounds__(kCol * kMaxNy / 2) col3_kernel(Col3Params p) {
   }
   lds_barrier();
   cx<double> A0 = {0.0, 0.0}, B0 = {0.0, 0.0}, A1 = {0.0, 0.0}, B1 = {0.0, 0.0};
-  for (int j = 0, m0 = 0, m1 = 0; j < Ny; ++j) {
-    const cx<double> A = sa[j * kCol + xl], B = sb[j * kCol + xl];
-    const cx<double> t0 = p.wy[m0];
-    A0 = A0 + cmul(A, t0);
-    B0 = B0 + cmul(B, t0);
-    if (two) {
-      const cx<double> t1 = p.wy[m1];
-      A1 = A1 + cmul(A, t1);
-      B1 = B1 + cmul(B, t1);
+  if constexpr (EVEN) {
+    cx<double> Ao = {0.0, 0.0}, Bo = {0.0, 0.0};
+    for (int j = 0, m0 = 0; j < Ny; j += 2) {
+      const cx<double> t0 = p.wy[m0];
+      A0 = cmac(A0, sa[j * kCol + xl], t0);
+      B0 = cmac(B0, sb[j * kCol + xl], t0);
+      m0 += i0;
+      if (m0 >= Ny) m0 -= Ny;
+      const cx<double> t1 = p.wy[m0];
+      Ao = cmac(Ao, sa[(j + 1) * kCol + xl], t1);
+      Bo = cmac(Bo, sb[(j + 1) * kCol + xl], t1);
+      m0 += i0;
+      if (m0 >= Ny) m0 -= Ny;
     }
-    m0 += i0;
-    if (m0 >= Ny) m0 -= Ny;
-    m1 += i1 - Ny;
-    if (m1 < 0) m1 += Ny;
+    A1 = A0 - Ao;
+    B1 = B0 - Bo;
+    A0 = A0 + Ao;
+    B0 = B0 + Bo;
+  } else {
+    for (int j = 0, m0 = 0, m1 = 0; j < Ny; ++j) {
+      const cx<double> A = sa[j * kCol + xl], B = sb[j * kCol + xl];
+      const cx<double> t0 = p.wy[m0];
+      A0 = cmac(A0, A, t0);
+      B0 = cmac(B0, B, t0);
+      if (two) {
+        const cx<double> t1 = p.wy[m1];
+        A1 = cmac(A1, A, t1);
+        B1 = cmac(B1, B, t1);
+      }
+      m0 += i0;
+      if (m0 >= Ny) m0 -= Ny;
+      m1 += i1 - Ny;
+      if (m1 < 0) m1 += Ny;
+    }
   }
   if (valid) {
     st(p.a, at0, A0);
@@ -836,12 +903,20 @@ int launch_march3(const March3Params& q, hipStream_t s) {
   const dim3 cgrid((q.Nx + kCol - 1) / kCol, q.Nomega);
   const dim3 cblock(kCol, (q.Ny + 1) / 2);
   const int rows = q.Nomega * 2 * q.Ny;
+  const bool even = q.Ny % 2 == 0;
   auto col = [&](int mode) -> int {
     c.mode = mode;
-    if (q.prec == BPM_PREC_FP64)
-      hipLaunchKernelGGL(col3_kernel<double>, cgrid, cblock, 0, s, c);
-    else
-      hipLaunchKernelGGL(col3_kernel<float>, cgrid, cblock, 0, s, c);
+    if (q.prec == BPM_PREC_FP64) {
+      if (even)
+        hipLaunchKernelGGL((col3_kernel<double, true>), cgrid, cblock, 0, s, c);
+      else
+        hipLaunchKernelGGL((col3_kernel<double, false>), cgrid, cblock, 0, s, c);
+    } else {
+      if (even)
+        hipLaunchKernelGGL((col3_kernel<float, true>), cgrid, cblock, 0, s, c);
+      else
+        hipLaunchKernelGGL((col3_kernel<float, false>), cgrid, cblock, 0, s, c);
+    }
     c.nb = 0;
     return hipGetLastError() == hipSuccess ? BPM_OK : BPM_EHIP;
   };
