@@ -68,6 +68,21 @@ struct TwGlobal {
   }
 };
 
+// The same twiddles from an LDS table tab[m] = exp(-2 pi i m / M::N)
+// (FP64, 16 M::N bytes) that the work group fills from the global table.
+template <class M>
+struct TwShared {
+  static constexpr bool kOpaqueIndex = true;
+  const cx<double>* tab;
+  template <int P>
+  BPM_INLINE Tw<typename M::CT> get(int t, int s, int r) const {
+    constexpr int Ns = M::ns(P);
+    constexpr int Rp = M::rad[P];
+    const int j = (Ns <= M::T ? t : t + s * M::T) & (Ns - 1);
+    return Tw<typename M::CT>{tab[(r * j) * (M::N / (Ns * Rp))]};
+  }
+};
+
 template <class T>
 BPM_INLINE cx<double> to_d(cx<T> a) {
   return {static_cast<double>(a.x), static_cast<double>(a.y)};
@@ -468,9 +483,13 @@ BPM_INLINE void dft9(const cx<T> (&y)[9], cx<T> (&X)[9]) {
 // nonzero on input (Nx <= 4.5 M) or is needed on output.  The block
 // exchange and the in-wavefront transforms are those of RowFour: slot i of
 // lane l of wavefront w holds bin w + 9 (l + 64 i) between the transforms.
-// At M = 1024 in the FP32 storage modes a row takes 80 KB of LDS, so two
-// rows share a CU (five wavefronts per SIMD, 96 VGPRs).
-template <class In_, int WAVES_PER_EU>
+// TWL: the in-wavefront twiddles come from a table W_M^m in LDS (16 M
+// bytes, filled from the global table at the start of the row) instead of
+// the global table.  At M = 1024 in the FP32 storage modes the row takes 80
+// KB of LDS: with the table, one row per CU; without it two rows could
+// share a CU, which measured slower (0.074 against 0.068 ms per launch on
+// the paper's grid).  WAVES_PER_EU: the occupancy asked of the compiler.
+template <class In_, int WAVES_PER_EU, bool TWL = false>
 struct RowNine {
   using In = In_;
   using CT = typename In::CT;
@@ -483,7 +502,19 @@ struct RowNine {
   static_assert(In::T == 64, "one wavefront per in-wave transform");
   static constexpr int kRegion = In::kEnv;
   static constexpr size_t kLdsSlots = size_t(W) * kRegion;
-  static constexpr bool kFits = kLdsSlots * sizeof(SV) <= 160 * 1024;
+  // TWL: the in-wavefront twiddles W_M^m in an LDS table after the row
+  static constexpr size_t kTabOff = (kLdsSlots * sizeof(SV) + 15) / 16 * 16;
+  static constexpr size_t kLdsBytes = kTabOff + (TWL ? size_t(M) * sizeof(cx<double>) : 0);
+  static constexpr bool kFits = kLdsBytes <= 160 * 1024;
+  BPM_INLINE static cx<double>* table(SV* lds) {
+    return reinterpret_cast<cx<double>*>(reinterpret_cast<char*>(lds) + kTabOff);
+  }
+  BPM_INLINE static auto in_twiddles(const cx<double>* tab, SV* lds) {
+    if constexpr (TWL)
+      return TwShared<In>{table(lds)};
+    else
+      return TwGlobal<In, N>{tab};
+  }
 
   BPM_INLINE static void put(SV* lds, int idx, cx<CT> v) {
     SV s;
@@ -494,6 +525,12 @@ struct RowNine {
 
   BPM_INLINE static void forward(cx<ST> (&v)[1][R], const SV* line, int Nx,
                                  const cx<double>* tab, SV* lds, int t) {
+    if constexpr (TWL) {
+      // W_M^m = W_N^{9 m}; the barrier of the block exchange below orders
+      // these stores before the first in-wavefront pass
+      cx<double>* tl = table(lds);
+      for (int m = t; m < M; m += T) tl[m] = tab[W * m];
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int m = opaque(t) + T * c;
@@ -520,7 +557,8 @@ struct RowNine {
     for (int i = 0; i < R; ++i) v[0][i] = In::template load_as<ST>(own, l + 64 * i);
     wave_sync();
     int xbuf = 0;
-    In::template fft_n<false, In::kWave, 1>(v, TwGlobal<In, N>{tab}, own, opaque(l), xbuf);
+    In::template fft_n<false, In::kWave, 1>(v, in_twiddles(tab, lds), own, opaque(l),
+                                            xbuf);
   }
 
   BPM_INLINE static void inverse(cx<ST> (&v)[1][R], SV* line, int Nx,
@@ -528,7 +566,8 @@ struct RowNine {
     const int l = t & 63;
     SV* own = lds + (t >> 6) * kRegion;
     int xbuf = 0;
-    In::template fft_n<true, In::kWave, 1>(v, TwGlobal<In, N>{tab}, own, opaque(l), xbuf);
+    In::template fft_n<true, In::kWave, 1>(v, in_twiddles(tab, lds), own, opaque(l),
+                                           xbuf);
 #pragma unroll
     for (int i = 0; i < R; ++i) put(own, l + 64 * i, conv<CT>(v[0][i]));
     lds_barrier();
@@ -564,7 +603,7 @@ row3_nine_kernel(Row3Params p) {
   using ST = typename F::ST;
   using SV = typename F::SV;
   constexpr int R = F::R, T = F::T;
-  __shared__ __align__(16) SV lds[F::kLdsSlots];
+  __shared__ __align__(16) SV lds[F::kLdsBytes / sizeof(SV)];
   const int t = threadIdx.x;
   const int row = blockIdx.x;
   const int ky = row % p.Ny;
@@ -820,13 +859,14 @@ template <int PREC> struct Row3T<PREC, 2048> { using type = March<PREC, 2048, 8,
 template <int PREC> struct Row3T<PREC, 4096> { using type = March<PREC, 4096, 8, 8, 8, 8, 8>; };
 template <int PREC> struct Row3T<PREC, 8192> { using type = RowFour<InWave1024<PREC>, 8>; };
 template <int PREC> struct Row3T<PREC, 16384> { using type = RowFour<InWave1024<PREC>, 16>; };
-// 9 M: waves per SIMD requested where LDS lets several rows share a CU
-// (FP32 storage: two rows of 9216, three of 4608; FP64: one row)
+// 9 M: FP32 storage rows of 9216 take their in-wavefront twiddles from LDS
+// (one row per CU); rows of 4608 ask for the seven wavefronts per SIMD of
+// three rows per CU; FP64 rows fill the LDS (one per CU).
 template <int PREC> struct Row3T<PREC, 4608> {
   using type = RowNine<InWave512<PREC>, PREC == BPM_PREC_FP64 ? 1 : 7>;
 };
 template <int PREC> struct Row3T<PREC, 9216> {
-  using type = RowNine<InWave1024<PREC>, PREC == BPM_PREC_FP64 ? 1 : 5>;
+  using type = RowNine<InWave1024<PREC>, 1, PREC != BPM_PREC_FP64>;
 };
 
 template <int PREC, int L>
