@@ -229,7 +229,7 @@ def test_3d_segments_fp32s_within_rounding():
     assert not within(r, 1e-6), r
 
 
-@pytest.mark.parametrize("prec", ["fp32s", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32s", "fp64", "fp32"])
 def test_3d_paper_grid_sampled_slice(prec):
     """The grid of the paper's finite-element example, 22 x 4267 x 1842
     (rows of L = 9216), two slices; the oracle recomputes one of them."""
