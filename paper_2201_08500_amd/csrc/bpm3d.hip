@@ -523,6 +523,21 @@ struct RowNine {
     lds[idx] = s;
   }
 
+  // The twiddles W_N^{m k1}, k1 = 1..8, of column m: one load of W_N^m and
+  // products of depth at most three (a few ulps from the table values).
+  // Eight loads per column, each waited for in the radix-9 step, took 13%
+  // of the row's time.
+  BPM_INLINE static void col_twiddles(const cx<double>* tab, int m, cx<double> (&w)[W]) {
+    w[1] = tab[m];
+    w[2] = cmul(w[1], w[1]);
+    w[3] = cmul(w[2], w[1]);
+    w[4] = cmul(w[2], w[2]);
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[3], w[3]);
+    w[7] = cmul(w[4], w[3]);
+    w[8] = cmul(w[4], w[4]);
+  }
+
   BPM_INLINE static void forward(cx<ST> (&v)[1][R], const SV* line, int Nx,
                                  const cx<double>* tab, SV* lds, int t) {
     if constexpr (TWL) {
@@ -545,9 +560,11 @@ struct RowNine {
           y[q] = {static_cast<CT>(s.x), static_cast<CT>(s.y)};
         }
         dft9<false, QN>(y, X);
+        cx<double> w[W];
+        col_twiddles(tab, m, w);
 #pragma unroll
         for (int k1 = 0; k1 < W; ++k1)
-          put(lds + k1 * kRegion, m, k1 ? Tw<CT>{tab[m * k1]}.mul(X[k1]) : X[k1]);
+          put(lds + k1 * kRegion, m, k1 ? Tw<CT>{w[k1]}.mul(X[k1]) : X[k1]);
       }
     }
     lds_barrier();
@@ -576,10 +593,12 @@ struct RowNine {
       const int m = opaque(t) + T * c;
       if (T * (c + 1) <= M || m < M) {
         cx<CT> z[9], y[9];
+        cx<double> w[W];
+        col_twiddles(tab, m, w);
 #pragma unroll
         for (int k1 = 0; k1 < W; ++k1) {
           z[k1] = In::template load_as<CT>(lds + k1 * kRegion, m);
-          if (k1 > 0) z[k1] = Tw<CT>{tab[m * k1]}.mulc(z[k1]);
+          if (k1 > 0) z[k1] = Tw<CT>{w[k1]}.mulc(z[k1]);
         }
         dft9<true, 9>(z, y);
 #pragma unroll
