@@ -49,29 +49,31 @@ BPM_INLINE int opaque(int v) {
   return v;
 }
 
-// Twiddle W_{Ns Rp}^{r j} of pass P of transform M as W_L^{r j L/(Ns Rp)}
-// from the table tab[m] = exp(-2 pi i m / NT), loaded where it is used.  The
-// thread index is opaque per pass (kOpaqueIndex), so a pass's loads can be
-// neither hoisted into an earlier pass nor shared with another transform;
-// within a pass, the butterflies s of a thread share j while Ns <= T, and
-// their loads are one.
-template <class M, int NT = M::N>   // NT: table length, a multiple of M::N
-struct TwGlobal {
-  static constexpr bool kOpaqueIndex = true;
-  const cx<double>* tab;
-  template <int P>
-  BPM_INLINE Tw<typename M::CT> get(int t, int s, int r) const {
-    constexpr int Ns = M::ns(P);
-    constexpr int Rp = M::rad[P];
-    const int j = (Ns <= M::T ? t : t + s * M::T) & (Ns - 1);
-    return Tw<typename M::CT>{tab[(r * j) * (NT / (Ns * Rp))]};
+// w[n] = w[1]^n for 1 <= n < K: powers of two by squaring, the others as
+// w[p] w[n - p] with p the largest power of two below n, so that each is a
+// product of depth at most log2(K) (a few ulps from the exact value).
+// Several twiddles of one butterfly group or column are formed this way
+// from one table load: each table load is waited for where it is used, and
+// eight or fifteen of them per group cost more than the products.
+template <int K>
+BPM_INLINE void twiddle_powers(cx<double> (&w)[K]) {
+#pragma unroll
+  for (int n = 2; n < K; ++n) {
+    int p = 1;
+    while (2 * p < n) p *= 2;
+    w[n] = cmul(w[p], w[n - p]);
   }
-};
+}
 
-// The same twiddles from an LDS table tab[m] = exp(-2 pi i m / M::N)
-// (FP64, 16 M::N bytes) that the work group fills from the global table.
-template <class M>
-struct TwShared {
+// Twiddle W_{Ns Rp}^{r j} of pass P of transform M: W_L^{j L/(Ns Rp)} from
+// the table tab[m] = exp(-2 pi i m / NT), and its powers r >= 2 as products
+// (twiddle_powers; the compiler merges the common factors of one group).
+// The thread index is opaque per pass (kOpaqueIndex), so a pass's loads can
+// be neither hoisted into an earlier pass nor shared with another
+// transform; within a pass, the butterflies s of a thread share j while
+// Ns <= T, and their loads are one.
+template <class M, int NT = M::N>   // NT: table length, a multiple of M::N
+struct TwDerived {
   static constexpr bool kOpaqueIndex = true;
   const cx<double>* tab;
   template <int P>
@@ -79,7 +81,10 @@ struct TwShared {
     constexpr int Ns = M::ns(P);
     constexpr int Rp = M::rad[P];
     const int j = (Ns <= M::T ? t : t + s * M::T) & (Ns - 1);
-    return Tw<typename M::CT>{tab[(r * j) * (M::N / (Ns * Rp))]};
+    cx<double> w[Rp];
+    w[1] = tab[j * (NT / (Ns * Rp))];
+    twiddle_powers(w);
+    return Tw<typename M::CT>{w[r]};
   }
 };
 
@@ -177,7 +182,7 @@ __global__ void __launch_bounds__(M::T) row3_kernel(Row3Params p) {
   const int w = row / (2 * p.Ny);
   SV* line = static_cast<SV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
   const cx<double>* Qrow = p.Q + size_t(table_row(row, p.Ny)) * M::N;
-  const TwGlobal<M> tws{p.tw};
+  const TwDerived<M> tws{p.tw};
   int xbuf = 0;
   cx<CT> v[1][R];
 #pragma unroll
@@ -266,6 +271,9 @@ struct RowFour {
     // opaque: the twiddle addresses are formed here, not shared with the
     // inverse and kept live across the whole row step
     const int t = opaque(t_in);
+    cx<double> w[16];   // W_N^{t K}
+    w[1] = tab[t];
+    twiddle_powers(w);
 #pragma unroll
     for (int n2 = 0; n2 < 4; ++n2) {
       cx<CT> a[4];
@@ -284,7 +292,7 @@ struct RowFour {
 #pragma unroll
       for (int k2 = 0; k2 < 4; ++k2) {
         const int K = k1 + 4 * k2;
-        put(lds + K * kRegion, t, K ? Tw<CT>{tab[t * K]}.mul(b[k2]) : b[k2]);
+        put(lds + K * kRegion, t, K ? Tw<CT>{w[K]}.mul(b[k2]) : b[k2]);
       }
     }
   }
@@ -300,9 +308,12 @@ struct RowFour {
 #pragma unroll
       for (int q = 0; q < W; ++q) va[q] = conv<CT>(v[0][j + J * q]);
       dft<W, false>(va);
+      cx<double> w[W];   // W_N^{m k1}
+      w[1] = tab[m];
+      twiddle_powers(w);
 #pragma unroll
       for (int k1 = 0; k1 < W; ++k1) {
-        if (k1 > 0) va[k1] = Tw<CT>{tab[m * k1]}.mul(va[k1]);
+        if (k1 > 0) va[k1] = Tw<CT>{w[k1]}.mul(va[k1]);
         put(lds + k1 * kRegion, m, va[k1]);
       }
     }
@@ -311,14 +322,14 @@ struct RowFour {
     for (int i = 0; i < R; ++i) v[0][i] = In::template load_as<ST>(own, l + 64 * i);
     wave_sync();
     int xbuf = 0;
-    In::template fft_n<false, In::kWave, 1>(v, TwGlobal<In, N>{tab}, own, opaque(l), xbuf);
+    In::template fft_n<false, In::kWave, 1>(v, TwDerived<In, N>{tab}, own, opaque(l), xbuf);
   }
 
   BPM_INLINE static void inverse(cx<ST> (&v)[1][R], const cx<double>* tab, SV* lds, int t) {
     const int l = t & 63;
     SV* own = lds + (t >> 6) * kRegion;
     int xbuf = 0;
-    In::template fft_n<true, In::kWave, 1>(v, TwGlobal<In, N>{tab}, own, opaque(l), xbuf);
+    In::template fft_n<true, In::kWave, 1>(v, TwDerived<In, N>{tab}, own, opaque(l), xbuf);
 #pragma unroll
     for (int i = 0; i < R; ++i) put(own, l + 64 * i, conv<CT>(v[0][i]));
     lds_barrier();
@@ -326,10 +337,13 @@ struct RowFour {
     for (int j = 0; j < J; ++j) {
       const int m = opaque(t) + T * j;
       cx<CT> va[W];
+      cx<double> w[W];
+      w[1] = tab[m];
+      twiddle_powers(w);
 #pragma unroll
       for (int k1 = 0; k1 < W; ++k1) {
         va[k1] = In::template load_as<CT>(lds + k1 * kRegion, m);
-        if (k1 > 0) va[k1] = Tw<CT>{tab[m * k1]}.mulc(va[k1]);
+        if (k1 > 0) va[k1] = Tw<CT>{w[k1]}.mulc(va[k1]);
       }
       dft<W, true>(va);
 #pragma unroll
@@ -483,13 +497,10 @@ BPM_INLINE void dft9(const cx<T> (&y)[9], cx<T> (&X)[9]) {
 // nonzero on input (Nx <= 4.5 M) or is needed on output.  The block
 // exchange and the in-wavefront transforms are those of RowFour: slot i of
 // lane l of wavefront w holds bin w + 9 (l + 64 i) between the transforms.
-// TWL: the in-wavefront twiddles come from a table W_M^m in LDS (16 M
-// bytes, filled from the global table at the start of the row) instead of
-// the global table.  At M = 1024 in the FP32 storage modes the row takes 80
-// KB of LDS: with the table, one row per CU; without it two rows could
-// share a CU, which measured slower (0.074 against 0.068 ms per launch on
-// the paper's grid).  WAVES_PER_EU: the occupancy asked of the compiler.
-template <class In_, int WAVES_PER_EU, bool TWL = false>
+// WAVES_PER_EU: the occupancy asked of the compiler (at M = 1024 in the FP32
+// storage modes a row takes 80 KB of LDS, so two rows share a CU at five
+// wavefronts per SIMD).
+template <class In_, int WAVES_PER_EU>
 struct RowNine {
   using In = In_;
   using CT = typename In::CT;
@@ -502,19 +513,7 @@ struct RowNine {
   static_assert(In::T == 64, "one wavefront per in-wave transform");
   static constexpr int kRegion = In::kEnv;
   static constexpr size_t kLdsSlots = size_t(W) * kRegion;
-  // TWL: the in-wavefront twiddles W_M^m in an LDS table after the row
-  static constexpr size_t kTabOff = (kLdsSlots * sizeof(SV) + 15) / 16 * 16;
-  static constexpr size_t kLdsBytes = kTabOff + (TWL ? size_t(M) * sizeof(cx<double>) : 0);
-  static constexpr bool kFits = kLdsBytes <= 160 * 1024;
-  BPM_INLINE static cx<double>* table(SV* lds) {
-    return reinterpret_cast<cx<double>*>(reinterpret_cast<char*>(lds) + kTabOff);
-  }
-  BPM_INLINE static auto in_twiddles(const cx<double>* tab, SV* lds) {
-    if constexpr (TWL)
-      return TwShared<In>{table(lds)};
-    else
-      return TwGlobal<In, N>{tab};
-  }
+  static constexpr bool kFits = kLdsSlots * sizeof(SV) <= 160 * 1024;
 
   BPM_INLINE static void put(SV* lds, int idx, cx<CT> v) {
     SV s;
@@ -523,29 +522,8 @@ struct RowNine {
     lds[idx] = s;
   }
 
-  // The twiddles W_N^{m k1}, k1 = 1..8, of column m: one load of W_N^m and
-  // products of depth at most three (a few ulps from the table values).
-  // Eight loads per column, each waited for in the radix-9 step, took 13%
-  // of the row's time.
-  BPM_INLINE static void col_twiddles(const cx<double>* tab, int m, cx<double> (&w)[W]) {
-    w[1] = tab[m];
-    w[2] = cmul(w[1], w[1]);
-    w[3] = cmul(w[2], w[1]);
-    w[4] = cmul(w[2], w[2]);
-    w[5] = cmul(w[4], w[1]);
-    w[6] = cmul(w[3], w[3]);
-    w[7] = cmul(w[4], w[3]);
-    w[8] = cmul(w[4], w[4]);
-  }
-
   BPM_INLINE static void forward(cx<ST> (&v)[1][R], const SV* line, int Nx,
                                  const cx<double>* tab, SV* lds, int t) {
-    if constexpr (TWL) {
-      // W_M^m = W_N^{9 m}; the barrier of the block exchange below orders
-      // these stores before the first in-wavefront pass
-      cx<double>* tl = table(lds);
-      for (int m = t; m < M; m += T) tl[m] = tab[W * m];
-    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int m = opaque(t) + T * c;
@@ -560,8 +538,9 @@ struct RowNine {
           y[q] = {static_cast<CT>(s.x), static_cast<CT>(s.y)};
         }
         dft9<false, QN>(y, X);
-        cx<double> w[W];
-        col_twiddles(tab, m, w);
+        cx<double> w[W];   // W_N^{m k1}
+        w[1] = tab[m];
+        twiddle_powers(w);
 #pragma unroll
         for (int k1 = 0; k1 < W; ++k1)
           put(lds + k1 * kRegion, m, k1 ? Tw<CT>{w[k1]}.mul(X[k1]) : X[k1]);
@@ -574,8 +553,7 @@ struct RowNine {
     for (int i = 0; i < R; ++i) v[0][i] = In::template load_as<ST>(own, l + 64 * i);
     wave_sync();
     int xbuf = 0;
-    In::template fft_n<false, In::kWave, 1>(v, in_twiddles(tab, lds), own, opaque(l),
-                                            xbuf);
+    In::template fft_n<false, In::kWave, 1>(v, TwDerived<In, N>{tab}, own, opaque(l), xbuf);
   }
 
   BPM_INLINE static void inverse(cx<ST> (&v)[1][R], SV* line, int Nx,
@@ -583,8 +561,7 @@ struct RowNine {
     const int l = t & 63;
     SV* own = lds + (t >> 6) * kRegion;
     int xbuf = 0;
-    In::template fft_n<true, In::kWave, 1>(v, in_twiddles(tab, lds), own, opaque(l),
-                                           xbuf);
+    In::template fft_n<true, In::kWave, 1>(v, TwDerived<In, N>{tab}, own, opaque(l), xbuf);
 #pragma unroll
     for (int i = 0; i < R; ++i) put(own, l + 64 * i, conv<CT>(v[0][i]));
     lds_barrier();
@@ -594,7 +571,8 @@ struct RowNine {
       if (T * (c + 1) <= M || m < M) {
         cx<CT> z[9], y[9];
         cx<double> w[W];
-        col_twiddles(tab, m, w);
+        w[1] = tab[m];
+        twiddle_powers(w);
 #pragma unroll
         for (int k1 = 0; k1 < W; ++k1) {
           z[k1] = In::template load_as<CT>(lds + k1 * kRegion, m);
@@ -622,7 +600,7 @@ row3_nine_kernel(Row3Params p) {
   using ST = typename F::ST;
   using SV = typename F::SV;
   constexpr int R = F::R, T = F::T;
-  __shared__ __align__(16) SV lds[F::kLdsBytes / sizeof(SV)];
+  __shared__ __align__(16) SV lds[F::kLdsSlots];
   const int t = threadIdx.x;
   const int row = blockIdx.x;
   const int ky = row % p.Ny;
@@ -885,7 +863,7 @@ template <int PREC> struct Row3T<PREC, 4608> {
   using type = RowNine<InWave512<PREC>, PREC == BPM_PREC_FP64 ? 1 : 7>;
 };
 template <int PREC> struct Row3T<PREC, 9216> {
-  using type = RowNine<InWave1024<PREC>, 1, PREC != BPM_PREC_FP64>;
+  using type = RowNine<InWave1024<PREC>, PREC == BPM_PREC_FP64 ? 1 : 5>;
 };
 
 template <int PREC, int L>
