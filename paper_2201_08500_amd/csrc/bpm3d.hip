@@ -26,7 +26,8 @@
 // step.  For L = Nx, Q = P.  The plan builds Q once (FP64), the host
 // evaluating IDFT_Nx by Bluestein's algorithm for other lengths.  Twiddles
 // of the length-L transform come from an FP64 table W_L^m in global memory
-// (shared by every row, resident in L2): registers and LDS hold the row.
+// (shared by every row, resident in L2), one entry per butterfly group and
+// the group's other twiddles as its powers: registers and LDS hold the row.
 // The y transform is a direct DFT (Ny <= 32).
 
 #include "bpm_device.h"
@@ -489,7 +490,7 @@ BPM_INLINE void dft9(const cx<T> (&y)[9], cx<T> (&X)[9]) {
 }
 
 // Rows of length L = 9 M (M = 512, 1024) for Nx <= 4.5 M, where the next
-// power of two would be 2 L * 8 / 9: the four-step layout of RowFour with
+// power of two would be 16 M: the four-step layout of RowFour with
 // W = 9 wavefronts (T = 576 threads) and a radix-9 step.  The M columns
 // x[m + M q] (q < 9) are shared out over the threads, t + T c for c <
 // ceil(M / T) (the last set partial, whole wavefronts idle), and read from
