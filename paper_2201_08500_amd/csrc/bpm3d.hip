@@ -500,13 +500,15 @@ BPM_INLINE void dft9(const cx<T> (&y)[9], cx<T> (&X)[9]) {
 // lane l of wavefront w holds bin w + 9 (l + 64 i) between the transforms.
 // WAVES_PER_EU: the occupancy asked of the compiler (at M = 1024 in the FP32
 // storage modes a row takes 80 KB of LDS, so two rows share a CU at five
-// wavefronts per SIMD).
-template <class In_, int WAVES_PER_EU>
+// wavefronts per SIMD).  HT: the scalar type of the row in HBM (the plan's
+// storage type), which may differ from the transform's storage type ST.
+template <class In_, int WAVES_PER_EU, class HT = typename In_::ST>
 struct RowNine {
   using In = In_;
   using CT = typename In::CT;
   using ST = typename In::ST;
   using SV = typename In::SV;
+  using HV = typename vec2<HT>::type;
   static constexpr int W = 9, M = In::N, R = In::R, N = W * M, T = 64 * W;
   static constexpr int NC = (M + T - 1) / T;   // column sets per thread
   static constexpr int QN = 5;                 // q < QN: possibly nonzero samples
@@ -523,7 +525,7 @@ struct RowNine {
     lds[idx] = s;
   }
 
-  BPM_INLINE static void forward(cx<ST> (&v)[1][R], const SV* line, int Nx,
+  BPM_INLINE static void forward(cx<ST> (&v)[1][R], const HV* line, int Nx,
                                  const cx<double>* tab, SV* lds, int t) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -532,7 +534,7 @@ struct RowNine {
         cx<CT> y[9], X[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          SV s;
+          HV s;
           s.x = 0;
           s.y = 0;
           if (q < QN && m + M * q < Nx) s = line[m + M * q];
@@ -557,7 +559,7 @@ struct RowNine {
     In::template fft_n<false, In::kWave, 1>(v, TwDerived<In, N>{tab}, own, opaque(l), xbuf);
   }
 
-  BPM_INLINE static void inverse(cx<ST> (&v)[1][R], SV* line, int Nx,
+  BPM_INLINE static void inverse(cx<ST> (&v)[1][R], HV* line, int Nx,
                                  const cx<double>* tab, SV* lds, int t) {
     const int l = t & 63;
     SV* own = lds + (t >> 6) * kRegion;
@@ -583,9 +585,9 @@ struct RowNine {
 #pragma unroll
         for (int q = 0; q < QN; ++q)
           if (m + M * q < Nx) {
-            SV s;
-            s.x = static_cast<ST>(y[q].x);
-            s.y = static_cast<ST>(y[q].y);
+            HV s;
+            s.x = static_cast<HT>(y[q].x);
+            s.y = static_cast<HT>(y[q].y);
             line[m + M * q] = s;
           }
       }
@@ -607,7 +609,7 @@ row3_nine_kernel(Row3Params p) {
   const int ky = row % p.Ny;
   const int env = (row / p.Ny) & 1;
   const int w = row / (2 * p.Ny);
-  SV* line = static_cast<SV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
+  typename F::HV* line = static_cast<typename F::HV*>(env ? p.b : p.a) + (size_t(w) * p.Ny + ky) * p.Nx;
   const cx<double>* Qrow = p.Q + size_t(table_row(row, p.Ny)) * F::N;
   cx<ST> v[1][R];
   F::forward(v, line, p.Nx, p.tw, lds, t);
@@ -857,14 +859,17 @@ template <int PREC> struct Row3T<PREC, 2048> { using type = March<PREC, 2048, 8,
 template <int PREC> struct Row3T<PREC, 4096> { using type = March<PREC, 4096, 8, 8, 8, 8, 8>; };
 template <int PREC> struct Row3T<PREC, 8192> { using type = RowFour<InWave1024<PREC>, 8>; };
 template <int PREC> struct Row3T<PREC, 16384> { using type = RowFour<InWave1024<PREC>, 16>; };
-// 9 M: FP32 storage rows of 9216 take their in-wavefront twiddles from LDS
-// (one row per CU); rows of 4608 ask for the seven wavefronts per SIMD of
-// three rows per CU; FP64 rows fill the LDS (one per CU).
+// 9 M: fp32 rows of 9216 ask for the five wavefronts per SIMD of two rows
+// per CU; fp32s rows of 9216 run the FP64 transform (FP64 LDS exchanges, one
+// row per CU) on their FP32 rows in HBM, measured 2% faster than two rows
+// per CU with FP32 exchanges and their conversions; rows of 4608 ask for the
+// seven wavefronts per SIMD of three rows per CU; FP64 rows fill the LDS.
 template <int PREC> struct Row3T<PREC, 4608> {
   using type = RowNine<InWave512<PREC>, PREC == BPM_PREC_FP64 ? 1 : 7>;
 };
 template <int PREC> struct Row3T<PREC, 9216> {
-  using type = RowNine<InWave1024<PREC>, PREC == BPM_PREC_FP64 ? 1 : 5>;
+  using type = RowNine<InWave1024<PREC == BPM_PREC_FP32S ? BPM_PREC_FP64 : PREC>,
+                       PREC == BPM_PREC_FP32 ? 5 : 1, typename Prec<PREC>::ST>;
 };
 
 template <int PREC, int L>
