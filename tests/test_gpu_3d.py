@@ -132,6 +132,21 @@ def test_3d_radix9_rows(Nx, prec):
     check3(W.small3d(Nx=Nx, Ny=3, Nz=5, Nomega=2, seed=Nx), prec)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+@pytest.mark.parametrize("Nx,L", [(2048, 2048), (2305, 8192), (4096, 4096), (4609, 16384)])
+def test_3d_row_length_boundaries(Nx, L, prec):
+    """Either side of the lengths 9 M: 2305 and 4609 are the smallest Nx
+    past 4608 and 9216 (next power of two), 2048 and 4096 are transformed
+    directly.  FP64 rows of 16384 do not fit in LDS and are refused."""
+    from paper_2201_08500_amd import BpmError
+    w = W.small3d(Nx=Nx, Ny=2, Nz=5, Nomega=1, seed=Nx + 7)
+    if prec == "fp64" and L > 9216:
+        with pytest.raises(BpmError, match="FP64"):
+            gpu3(w, prec)
+        return
+    check3(w, prec)
+
+
 @pytest.mark.parametrize("order", [1, 2, 4])
 def test_3d_one_row_matches_the_2d_march(order):
     """Ny = 1 on a power-of-two x grid: the 3D kernels and the 2D march
