@@ -167,12 +167,13 @@ def test_3d_one_row_matches_the_2d_march(order):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32s"])
-def test_3d_general_mask(prec):
+@pytest.mark.parametrize("Nx", [90, 4267])
+def test_3d_general_mask(Nx, prec):
     """A crystal mask Pi(x, y, z) that changes with y and z (a wedge whose
     front moves with y, a hole in a few steps), with Strang splitting,
     against the oracle with the same mask."""
     from paper_2201_08500_amd import Plan3D
-    w = W.small3d(Nx=90, Ny=6, Nz=14, Nomega=2, seed=31)
+    w = W.small3d(Nx=Nx, Ny=6, Nz=14, Nomega=2, seed=31)
     x = (np.arange(w.Nx) - w.Nx // 2) * w.dx
     mask = np.zeros((w.Nz, w.Ny, w.Nx), dtype=bool)
     for n in range(w.Nz):
@@ -191,14 +192,14 @@ def test_3d_general_mask(prec):
     assert not within(r, tol(prec, w.Nz), phase_tol=None if prec == "fp64" else 1e-4), r
 
 
-@pytest.mark.parametrize("order", [1, 2, 4])
-def test_3d_segments_chain_bitwise_fp64(order):
+@pytest.mark.parametrize("order,Nx", [(1, 100), (2, 100), (4, 100), (2, 4267)])
+def test_3d_segments_chain_bitwise_fp64(order, Nx):
     """bpm_deformation_table, bpm_march and bpm_march_segment on a 3D plan:
     three segments chained through their outputs (the last in place) equal
     the whole march bitwise in FP64, and a segment resumed from a checkpoint
     of both envelopes matches the oracle started from that checkpoint."""
     from paper_2201_08500_amd import Plan3D
-    w = W.small3d(Nx=100, Ny=5, Nz=12, Nomega=2, seed=40 + order)
+    w = W.small3d(Nx=Nx, Ny=5, Nz=12, Nomega=2, seed=40 + order)
     p = Plan3D.from_workload(w, precision="fp64", split_order=order)
     E0 = torch.from_numpy(w.E0_in).cuda()
     u = torch.from_numpy(np.ascontiguousarray(w.u)).cuda()
