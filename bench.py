@@ -602,9 +602,9 @@ def main():
                     help="arrival rates of the same traces served all in fp64")
     ap.add_argument("--serve-duration", type=float, default=60.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
-    ap.add_argument("--serve-streams", type=int, default=2,
-                    help="launch streams = launches in flight (torch caches freed "
-                         "blocks per stream, so more streams split the cache)")
+    ap.add_argument("--serve-streams", type=int, default=4,
+                    help="launch streams = launches in flight (four measured best "
+                         "below capacity, equal throughput above it)")
     ap.add_argument("--serve-fp32", default="fp32s", choices=["fp32s", "fp32"],
                     help="precision used for the stream's FP32 requests")
     ap.add_argument("--batch-problems", type=int, default=512)
