@@ -479,15 +479,16 @@ class GpuBackend:
     host, `meta['u_factors'] = (row, gz, gx, amp)` describing
     u[n, j] = row[j] + (amp gz[n]) gx[j], or `u` as an array, or no u)."""
 
-    def __init__(self, streams: int = 4, device: int = 0, keep_outputs=True,
+    def __init__(self, streams: int = 3, device: int = 0, keep_outputs=True,
                  headroom_bytes: float = 0.0, staging_bytes: int = 2 << 30):
         """streams: launch streams, one launch in flight on each.  Below the
         GPU's capacity more launches in flight shorten the wait for a slot
         (at 150 req/s of the uneven mix, p50 0.72 / 0.45 / 0.25 s with two /
-        three / four streams) at the same throughput.  Torch caches freed
-        blocks per stream, so each stream splits the allocator's cache; with
-        the inputs staged through the pinned ring that no longer stalls the
-        scheduler.
+        three / four streams) at the same throughput; above capacity (200
+        req/s) four streams raised p99 by 10-15% and three kept it.  Torch
+        caches freed blocks per stream, so each stream splits the
+        allocator's cache; with the inputs staged through the pinned ring
+        that no longer stalls the scheduler.
 
         headroom_bytes > 0 caps torch's caching allocator at the device's
         memory minus that much, so the HIP runtime (queues, kernel scratch)
